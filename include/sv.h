@@ -1,0 +1,262 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector gate-application library.
+ *
+ * The library holds one n-qubit state vector of 2^n complex amplitudes in HBM
+ * and applies quantum gates to it, then reads it out as probabilities, Pauli
+ * expectation values or samples.  The operations follow the paper's statement
+ * of state-vector simulation (Sec. 2.1 "State-Vector Simulation" and
+ * "Measurement and Sampling"; Sec. 2.2 for the shot-based readout): a state
+ * of 2^n amplitudes, unitary gates applied through their tensor product with
+ * identities, a one-qubit gate as a 2x2 matrix acting on amplitude pairs,
+ * fusion of several gates into one operation, and measurement that draws
+ * bitstrings from the distribution the amplitudes define.
+ *
+ * Conventions (all entry points)
+ *  - Qubit q is bit q of the amplitude index (little-endian).  A k-target gate
+ *    matrix is 2^k x 2^k, row-major, complex numbers as interleaved (re, im)
+ *    doubles; bit b of its row/column index belongs to targets[b].
+ *  - Controls act on |1>: the gate is applied to the amplitudes whose control
+ *    bits are all 1 and leaves the others unchanged.
+ *  - Amplitudes are stored interleaved (re, im): complex64 = 2 x float,
+ *    complex128 = 2 x double.  The device buffer is 256-byte aligned.
+ *  - Qubit arguments name LOGICAL qubits.  sv_swap_bits() changes the
+ *    physical layout and the logical->physical map; every other call
+ *    translates through that map, so results never depend on the layout.
+ *  - Host buffers are owned by the caller and only touched during the call.
+ *    Gate application is stream-ordered and asynchronous; calls that return
+ *    host data synchronise the handle's stream before returning.
+ *  - Every entry point returns an sv_status.  On failure nothing has been
+ *    launched and sv_last_error() gives a message (thread-local).  Argument
+ *    checks run on the host before any HIP call, so they work without a GPU.
+ *  - A handle must not be used by two threads at once.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sv_status {
+    SV_OK = 0,
+    SV_EINVAL = -1,       /* bad argument (range, duplicate qubit, null pointer, ...) */
+    SV_ENOMEM = -2,       /* device or host allocation failed / state larger than allowed */
+    SV_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+    SV_EUNSUPPORTED = -4  /* valid request this build does not implement */
+} sv_status;
+
+typedef enum sv_dtype {
+    SV_C64 = 0,   /* complex64: FP32 re/im, 8 bytes per amplitude */
+    SV_C128 = 1   /* complex128: FP64 re/im, 16 bytes per amplitude */
+} sv_dtype;
+
+#define SV_MAX_QUBITS 40
+#define SV_MAX_TARGETS 6
+#define SV_MAX_CONTROLS 8
+
+/* Gate kinds of sv_gate.kind.  Rotations are R_P(t) = exp(-i t P / 2);
+ * SV_P(phi) = diag(1, e^{i phi}); SV_U3(t, f, l) =
+ * [[cos t/2, -e^{il} sin t/2], [e^{if} sin t/2, e^{i(f+l)} cos t/2]]. */
+typedef enum sv_gate_kind {
+    SV_GATE_H = 0,
+    SV_GATE_X = 1,
+    SV_GATE_Y = 2,
+    SV_GATE_Z = 3,
+    SV_GATE_S = 4,
+    SV_GATE_T = 5,
+    SV_GATE_RX = 6,
+    SV_GATE_RY = 7,
+    SV_GATE_RZ = 8,
+    SV_GATE_P = 9,
+    SV_GATE_U3 = 10,
+    SV_GATE_MATRIX = 11  /* dense 2^k x 2^k matrix given by sv_gate.matrix */
+} sv_gate_kind;
+
+/* One gate of a circuit.  Named kinds have exactly one target; SV_GATE_MATRIX
+ * has 1..SV_MAX_TARGETS.  Any kind may carry up to SV_MAX_CONTROLS controls
+ * (CNOT = X with one control, CZ = Z with one control, CP = P with one
+ * control).  `matrix` is read during the call only. */
+typedef struct sv_gate {
+    int32_t kind;
+    int32_t num_targets;
+    int32_t num_controls;
+    int32_t targets[SV_MAX_TARGETS];
+    int32_t controls[SV_MAX_CONTROLS];
+    double params[3];
+    const double *matrix;
+} sv_gate;
+
+/* How sv_apply_circuit groups gates into sweeps over the state (paper Sec. 2.1:
+ * fusion groups gate applications into one operation, raising the linear
+ * algebra size and moving the sweep from bandwidth-bound towards balanced). */
+typedef enum sv_plan_mode {
+    SV_PLAN_PLAIN = 0,    /* one sweep per gate */
+    SV_PLAN_GREEDY = 1,   /* greedy dependency-aware fusion into <= max_fused-qubit blocks */
+    SV_PLAN_LEARNED = 2   /* candidate fusion plans ranked by the attached cost model;
+                             falls back to SV_PLAN_GREEDY without a usable model */
+} sv_plan_mode;
+
+typedef enum sv_precision {
+    SV_PREC_NATIVE = 0,   /* complex64: FP32 arithmetic; complex128: FP64 */
+    SV_PREC_BF16X3 = 1    /* complex64 fused blocks: three-term BF16 split products on
+                             the matrix cores, FP32 accumulation */
+} sv_precision;
+
+typedef struct sv_plan_opts {
+    int32_t mode;        /* sv_plan_mode */
+    int32_t max_fused;   /* 1..6: widest fused block (greedy / learned) */
+    int32_t precision;   /* sv_precision */
+    int32_t reserved;    /* must be 0 */
+} sv_plan_opts;
+
+/* Counters filled by sv_apply_circuit / sv_apply_plan (may be NULL). */
+typedef struct sv_run_stats {
+    int64_t gates;              /* gates of the input circuit (unfused count) */
+    int64_t sweeps;             /* kernels launched over the state */
+    int64_t fused_blocks;       /* sweeps that apply more than one gate */
+    double algorithmic_bytes;   /* HBM bytes the sweeps must move (128-byte lines) */
+    double flops;               /* real floating-point operations of the sweeps */
+} sv_run_stats;
+
+typedef struct sv_state *sv_handle;
+typedef struct sv_plan *sv_plan_handle;
+
+/* Thread-local message of the last failed call ("" if none).  Never NULL. */
+const char *sv_last_error(void);
+
+/* Bytes of an n-qubit state of dtype: 2^n * 8 (complex64) or 2^n * 16
+ * (complex128); the FP32 case is the paper's 2^(n-27) GiB (Sec. 1). */
+int sv_state_bytes(int n, int dtype, uint64_t *bytes);
+
+/* Allocate a state of n qubits (1..SV_MAX_QUBITS) on the current HIP device
+ * and set it to |0...0>.  The library owns the memory; sv_destroy frees it.
+ * SV_ENOMEM if the state does not fit in free device memory (or exceeds the
+ * SV_MAX_DEVICE_BYTES environment limit, checked on the host first). */
+int sv_create(int n, int dtype, sv_handle *out);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor) of `bytes` >=
+ * sv_state_bytes(n, dtype), 16-byte aligned, and set it to |0...0>.  The caller
+ * keeps the memory alive until sv_destroy.  `stream` is a hipStream_t (NULL =
+ * default stream) on which all work of this handle is ordered. */
+int sv_create_on(void *device_ptr, uint64_t bytes, int n, int dtype, void *stream, sv_handle *out);
+
+/* Release the handle (and the state if the library allocated it). */
+int sv_destroy(sv_handle h);
+
+/* Change the stream work of this handle is ordered on (NULL = default). */
+int sv_set_stream(sv_handle h, void *stream);
+
+/* Block until all work queued on the handle's stream has finished. */
+int sv_synchronize(sv_handle h);
+
+/* |psi> <- |0...0> and identity qubit map.  One write sweep. */
+int sv_reset(sv_handle h);
+
+/* Apply one gate: U is 2^k x 2^k (k = num targets, 1..6) interleaved FP64,
+ * `controls` may be NULL when c == 0.  Paper Sec. 2.1: the gate acts through
+ * the tensor product of U with identities on the other qubits. */
+int sv_apply_gate(sv_handle h, const double *U, const int *targets, int k, const int *controls, int c);
+
+/* Apply a gate list in order, grouped into sweeps as `opts` says (NULL =
+ * plain).  All gates are validated before anything is launched. */
+int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_plan_opts *opts,
+                     sv_run_stats *stats);
+
+/* Exchange physical index-bit fields [lo, lo+width) and [hi, hi+width)
+ * (1 <= width <= 6, lo + width <= hi, hi + width <= n), in place: the
+ * single-device part of the global/local qubit exchange a distributed
+ * state-vector simulator performs (paper Sec. 2.1, Sec. 2.5).  The logical
+ * state is unchanged; the logical->physical map is updated.  Bit-exact. */
+int sv_swap_bits(sv_handle h, int lo, int hi, int width);
+
+/* map[q] = physical index bit currently holding logical qubit q (n entries). */
+int sv_qubit_map(sv_handle h, int *map);
+
+/* Marginal distribution over logical qubits Q[0..m) (0 <= m <= min(n, 30)):
+ * out[x] = sum of |a_i|^2 over i whose qubit Q[b] equals bit b of x; 2^m
+ * doubles.  m = 0 gives the squared norm.  FP64 accumulation for both
+ * dtypes.  Synchronises. */
+int sv_probabilities(sv_handle h, const int *qubits, int m, double *out);
+
+/* Expectation values <psi|P|psi> of Pauli strings.  terms[t] is a string of
+ * n characters from "IXYZ" (lower case accepted), character q acting on
+ * logical qubit q.  out[t] receives the real part (the imaginary part of a
+ * Hermitian expectation is zero up to rounding).  FP64 accumulation.
+ * Z-only strings are evaluated together in one read sweep.  Synchronises. */
+int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *out);
+
+/* Draw `shots` outcomes (paper Sec. 2.1 "Measurement and Sampling"): for
+ * uniform u_s in [0, 1) (caller-drawn), the outcome is the smallest logical
+ * basis index x with CDF(x) > u_s * norm, CDF accumulated in FP64 over
+ * physical index order (identical to logical order under the identity map).
+ * out[s] is the logical bitstring (bit q = qubit q).  Synchronises. */
+int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out);
+
+/* Copy amplitudes [first, first+count) in LOGICAL index order to host memory
+ * (count * bytes-per-amplitude bytes, dtype layout).  Synchronises. */
+int sv_copy_to_host(sv_handle h, void *dst, uint64_t first, uint64_t count);
+
+/* Overwrite amplitudes [first, first+count) (logical order) from host memory.
+ * With a non-identity qubit map only a whole-state copy is allowed; it
+ * resets the map to identity.  Synchronises. */
+int sv_copy_from_host(sv_handle h, const void *src, uint64_t first, uint64_t count);
+
+/* ---- sweep timing -------------------------------------------------------- */
+
+/* Kernel class of a recorded sweep. */
+typedef enum sv_sweep_kind {
+    SV_SWEEP_GATE1 = 0,    /* one-target dense gate (controls allowed) */
+    SV_SWEEP_DIAG1 = 1,    /* one-target diagonal gate (controls allowed) */
+    SV_SWEEP_DENSE = 2,    /* k-target dense block through the LDS tile (VALU) */
+    SV_SWEEP_DENSE_MFMA = 3, /* k-target dense block on the matrix cores */
+    SV_SWEEP_GROUP = 4,    /* k-target dense block, one group per thread (small n) */
+    SV_SWEEP_BITSWAP = 5   /* index-bit field exchange */
+} sv_sweep_kind;
+
+/* One timed sweep (physical bit positions). */
+typedef struct sv_sweep_record {
+    int32_t kind;            /* sv_sweep_kind */
+    int32_t k;               /* targets (bit-field width for SV_SWEEP_BITSWAP) */
+    int32_t c;               /* controls */
+    int32_t lowest_target;   /* lowest target bit (lo for SV_SWEEP_BITSWAP) */
+    int32_t highest_target;  /* highest target bit (hi for SV_SWEEP_BITSWAP) */
+    int32_t num_gates;       /* input gates applied by this sweep */
+    double bytes;            /* algorithmic HBM bytes */
+    double flops;
+    float ms;                /* HIP-event duration on the handle's stream */
+    int32_t reserved;
+} sv_sweep_record;
+
+/* enable != 0: bracket every subsequent sweep of this handle with a pair of
+ * HIP events on its stream (the events stay pending until read). */
+int sv_profile_enable(sv_handle h, int enable);
+
+/* Synchronise, then move up to `max` recorded sweeps (oldest first) into
+ * `out` and their total count into *count; the record buffer is cleared. */
+int sv_profile_read(sv_handle h, sv_sweep_record *out, int max, int *count);
+
+/* ---- fusion plans (host only; no GPU needed) ---------------------------- */
+
+/* Build the sweep plan sv_apply_circuit would use for this gate list on an
+ * n-qubit state of dtype (logical qubits).  Block matrices are formed in
+ * FP64 on the host as the ordered product of the block's gates. */
+int sv_plan_create(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts *opts,
+                   sv_plan_handle *out);
+int sv_plan_num_blocks(sv_plan_handle p, int *nblocks);
+/* Block i: k targets and c controls (logical qubits), its 2^k x 2^k FP64
+ * matrix (interleaved; may be NULL to skip), and the number of input gates
+ * it applies.  targets/controls need room for 6 / 8 entries. */
+int sv_plan_block(sv_plan_handle p, int i, int *k, int *targets, int *c, int *controls,
+                  double *matrix, int *num_gates);
+/* Apply a plan built for this handle's n and dtype. */
+int sv_apply_plan(sv_handle h, sv_plan_handle p, sv_run_stats *stats);
+int sv_plan_destroy(sv_plan_handle p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

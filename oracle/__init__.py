@@ -169,3 +169,9 @@ def apply_bitswap_map(qmap: list, lo: int, hi: int, width: int) -> list:
         elif hi <= p < hi + width:
             out[q] = p - hi + lo
     return out
+
+
+def num_threads() -> int:
+    lib = _load()
+    lib.orc_num_threads.restype = ctypes.c_int
+    return int(lib.orc_num_threads())

@@ -239,3 +239,17 @@ int orc_bitswap(const cplx *a, cplx *b, int n, int lo, int hi, int w)
     }
     return 0;
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the parallel loop of orc_apply uses (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,322 @@
+"""ctypes binding of libsv.so (include/sv.h), same names as the C entry points.
+
+Argument marshalling only: every step of gate application and read-out runs
+in the HIP library.  There is no fallback: if libsv.so is missing or fails to
+load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4
+SV_C64, SV_C128 = 0, 1
+SV_PLAN_PLAIN, SV_PLAN_GREEDY, SV_PLAN_LEARNED = 0, 1, 2
+SV_PREC_NATIVE, SV_PREC_BF16X3 = 0, 1
+SV_MAX_TARGETS, SV_MAX_CONTROLS = 6, 8
+
+GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
+             "p": 9, "u3": 10, "matrix": 11}
+
+_ERRNAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
+             SV_EUNSUPPORTED: "SV_EUNSUPPORTED"}
+
+
+class SvError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class sv_gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("num_targets", ctypes.c_int32),
+                ("num_controls", ctypes.c_int32),
+                ("targets", ctypes.c_int32 * SV_MAX_TARGETS),
+                ("controls", ctypes.c_int32 * SV_MAX_CONTROLS),
+                ("params", ctypes.c_double * 3),
+                ("matrix", ctypes.POINTER(ctypes.c_double))]
+
+
+class sv_plan_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_fused", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class sv_run_stats(ctypes.Structure):
+    _fields_ = [("gates", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("fused_blocks", ctypes.c_int64), ("algorithmic_bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
+    sig = {
+        "sv_last_error": ([], ctypes.c_char_p),
+        "sv_state_bytes": ([I, I, ctypes.POINTER(U64)], I),
+        "sv_create": ([I, I, ctypes.POINTER(P)], I),
+        "sv_create_on": ([P, U64, I, I, P, ctypes.POINTER(P)], I),
+        "sv_destroy": ([P], I),
+        "sv_set_stream": ([P, P], I),
+        "sv_synchronize": ([P], I),
+        "sv_reset": ([P], I),
+        "sv_apply_gate": ([P, P, P, I, P, I], I),
+        "sv_apply_circuit": ([P, ctypes.POINTER(sv_gate), I, ctypes.POINTER(sv_plan_opts),
+                              ctypes.POINTER(sv_run_stats)], I),
+        "sv_swap_bits": ([P, I, I, I], I),
+        "sv_qubit_map": ([P, P], I),
+        "sv_probabilities": ([P, P, I, P], I),
+        "sv_expect_pauli": ([P, ctypes.POINTER(ctypes.c_char_p), I, P], I),
+        "sv_sample": ([P, P, I, P], I),
+        "sv_copy_to_host": ([P, P, U64, U64], I),
+        "sv_copy_from_host": ([P, P, U64, U64], I),
+        "sv_plan_create": ([I, I, ctypes.POINTER(sv_gate), I, ctypes.POINTER(sv_plan_opts),
+                            ctypes.POINTER(P)], I),
+        "sv_plan_num_blocks": ([P, ctypes.POINTER(I)], I),
+        "sv_plan_block": ([P, I, P, P, P, P, P, P], I),
+        "sv_apply_plan": ([P, P, ctypes.POINTER(sv_run_stats)], I),
+        "sv_plan_destroy": ([P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int, where: str):
+    if rc != SV_OK:
+        raise SvError(rc, where, sv_last_error())
+
+
+def sv_last_error() -> str:
+    return _lib.sv_last_error().decode()
+
+
+def amp_dtype(dtype: int):
+    return np.complex64 if dtype == SV_C64 else np.complex128
+
+
+# ---------------------------------------------------------------------------
+# Gate lists
+# ---------------------------------------------------------------------------
+class Circuit:
+    """A gate list marshalled once into an sv_gate array (kept alive here)."""
+
+    def __init__(self, gates: Iterable):
+        gates = [g for g in gates if hasattr(g, "name")]
+        self.n_gates = len(gates)
+        self.array = (sv_gate * max(1, len(gates)))()
+        self._keep: List[np.ndarray] = []
+        for i, g in enumerate(gates):
+            s = self.array[i]
+            s.kind = GATE_KIND[g.name]
+            s.num_targets = len(g.targets)
+            s.num_controls = len(g.controls)
+            for j, q in enumerate(g.targets):
+                s.targets[j] = int(q)
+            for j, q in enumerate(g.controls):
+                s.controls[j] = int(q)
+            for j, p in enumerate(g.params):
+                s.params[j] = float(p)
+            if g.name == "matrix":
+                m = np.ascontiguousarray(np.asarray(g.matrix, dtype=np.complex128))
+                self._keep.append(m)
+                s.matrix = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_opts(mode: int = SV_PLAN_PLAIN, max_fused: int = 5, precision: int = SV_PREC_NATIVE) -> sv_plan_opts:
+    return sv_plan_opts(mode, max_fused, precision, 0)
+
+
+def _as_circuit(gates) -> Circuit:
+    return gates if isinstance(gates, Circuit) else Circuit(gates)
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+def sv_state_bytes(n: int, dtype: int) -> int:
+    out = ctypes.c_uint64()
+    _check(_lib.sv_state_bytes(n, dtype, ctypes.byref(out)), "sv_state_bytes")
+    return out.value
+
+
+def sv_create(n: int, dtype: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.sv_create(n, dtype, ctypes.byref(h)), "sv_create")
+    return h.value
+
+
+def sv_create_on(device_ptr: int, nbytes: int, n: int, dtype: int, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.sv_create_on(ctypes.c_void_p(device_ptr), nbytes, n, dtype,
+                             ctypes.c_void_p(stream or None), ctypes.byref(h)), "sv_create_on")
+    return h.value
+
+
+def sv_destroy(h: int):
+    _check(_lib.sv_destroy(ctypes.c_void_p(h)), "sv_destroy")
+
+
+def sv_set_stream(h: int, stream: int):
+    _check(_lib.sv_set_stream(ctypes.c_void_p(h), ctypes.c_void_p(stream or None)), "sv_set_stream")
+
+
+def sv_synchronize(h: int):
+    _check(_lib.sv_synchronize(ctypes.c_void_p(h)), "sv_synchronize")
+
+
+def sv_reset(h: int):
+    _check(_lib.sv_reset(ctypes.c_void_p(h)), "sv_reset")
+
+
+def sv_apply_gate(h: int, U, targets: Sequence[int], controls: Sequence[int] = ()):
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    t = np.ascontiguousarray(np.asarray(list(targets), dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(list(controls) or [0], dtype=np.int32))
+    _check(_lib.sv_apply_gate(ctypes.c_void_p(h), U.ctypes.data, t.ctypes.data, len(targets),
+                              c.ctypes.data if len(controls) else None, len(controls)), "sv_apply_gate")
+
+
+def sv_apply_circuit(h: int, gates, opts: Optional[sv_plan_opts] = None) -> dict:
+    circ = _as_circuit(gates)
+    st = sv_run_stats()
+    o = opts if opts is not None else make_opts()
+    _check(_lib.sv_apply_circuit(ctypes.c_void_p(h), circ.array, circ.n_gates, ctypes.byref(o),
+                                 ctypes.byref(st)), "sv_apply_circuit")
+    return st.as_dict()
+
+
+def sv_swap_bits(h: int, lo: int, hi: int, width: int):
+    _check(_lib.sv_swap_bits(ctypes.c_void_p(h), lo, hi, width), "sv_swap_bits")
+
+
+def sv_qubit_map(h: int, n: int) -> List[int]:
+    m = np.zeros(n, dtype=np.int32)
+    _check(_lib.sv_qubit_map(ctypes.c_void_p(h), m.ctypes.data), "sv_qubit_map")
+    return [int(x) for x in m]
+
+
+def sv_probabilities(h: int, qubits: Sequence[int]) -> np.ndarray:
+    q = np.ascontiguousarray(np.asarray(list(qubits) or [0], dtype=np.int32))
+    out = np.empty(1 << len(qubits), dtype=np.float64)
+    _check(_lib.sv_probabilities(ctypes.c_void_p(h), q.ctypes.data if len(qubits) else None,
+                                 len(qubits), out.ctypes.data), "sv_probabilities")
+    return out
+
+
+def sv_expect_pauli(h: int, terms: Sequence[str]) -> np.ndarray:
+    arr = (ctypes.c_char_p * max(1, len(terms)))(*[t.encode() for t in terms])
+    out = np.empty(max(1, len(terms)), dtype=np.float64)
+    _check(_lib.sv_expect_pauli(ctypes.c_void_p(h), arr, len(terms), out.ctypes.data), "sv_expect_pauli")
+    return out[:len(terms)]
+
+
+def sv_sample(h: int, uniforms) -> np.ndarray:
+    u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+    out = np.empty(max(1, u.size), dtype=np.int64)
+    _check(_lib.sv_sample(ctypes.c_void_p(h), u.ctypes.data, u.size, out.ctypes.data), "sv_sample")
+    return out[:u.size]
+
+
+def sv_copy_to_host(h: int, n: int, dtype: int, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+    if count is None:
+        count = (1 << n) - first
+    out = np.empty(count, dtype=amp_dtype(dtype))
+    _check(_lib.sv_copy_to_host(ctypes.c_void_p(h), out.ctypes.data, first, count), "sv_copy_to_host")
+    return out
+
+
+def sv_copy_from_host(h: int, dtype: int, src, first: int = 0):
+    a = np.ascontiguousarray(np.asarray(src, dtype=amp_dtype(dtype)))
+    _check(_lib.sv_copy_from_host(ctypes.c_void_p(h), a.ctypes.data, first, a.size), "sv_copy_from_host")
+
+
+def sv_plan_create(n: int, dtype: int, gates, opts: Optional[sv_plan_opts] = None) -> int:
+    circ = _as_circuit(gates)
+    p = ctypes.c_void_p()
+    o = opts if opts is not None else make_opts()
+    _check(_lib.sv_plan_create(n, dtype, circ.array, circ.n_gates, ctypes.byref(o), ctypes.byref(p)),
+           "sv_plan_create")
+    return p.value
+
+
+def sv_plan_num_blocks(p: int) -> int:
+    out = ctypes.c_int()
+    _check(_lib.sv_plan_num_blocks(ctypes.c_void_p(p), ctypes.byref(out)), "sv_plan_num_blocks")
+    return out.value
+
+
+def sv_plan_block(p: int, i: int) -> dict:
+    k, c, ng = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    t = np.zeros(SV_MAX_TARGETS, dtype=np.int32)
+    ctl = np.zeros(SV_MAX_CONTROLS, dtype=np.int32)
+    _check(_lib.sv_plan_block(ctypes.c_void_p(p), i, ctypes.byref(k), t.ctypes.data, ctypes.byref(c),
+                              ctl.ctypes.data, None, ctypes.byref(ng)), "sv_plan_block")
+    d = 1 << k.value
+    m = np.empty((d, d), dtype=np.complex128)
+    _check(_lib.sv_plan_block(ctypes.c_void_p(p), i, None, None, None, None, m.ctypes.data, None),
+           "sv_plan_block")
+    return {"targets": [int(x) for x in t[:k.value]], "controls": [int(x) for x in ctl[:c.value]],
+            "matrix": m, "num_gates": ng.value}
+
+
+def sv_apply_plan(h: int, p: int) -> dict:
+    st = sv_run_stats()
+    _check(_lib.sv_apply_plan(ctypes.c_void_p(h), ctypes.c_void_p(p), ctypes.byref(st)), "sv_apply_plan")
+    return st.as_dict()
+
+
+def sv_plan_destroy(p: int):
+    _check(_lib.sv_plan_destroy(ctypes.c_void_p(p)), "sv_plan_destroy")
+
+
+# ---------------------------------------------------------------------------
+# Sweep timing
+# ---------------------------------------------------------------------------
+class sv_sweep_record(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("c", ctypes.c_int32),
+                ("lowest_target", ctypes.c_int32), ("highest_target", ctypes.c_int32),
+                ("num_gates", ctypes.c_int32), ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap"}
+
+_lib.sv_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
+_lib.sv_profile_enable.restype = ctypes.c_int
+_lib.sv_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(sv_sweep_record), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int)]
+_lib.sv_profile_read.restype = ctypes.c_int
+
+
+def sv_profile_enable(h: int, enable: bool = True):
+    _check(_lib.sv_profile_enable(ctypes.c_void_p(h), 1 if enable else 0), "sv_profile_enable")
+
+
+def sv_profile_read(h: int, max_records: int = 1 << 16) -> List[dict]:
+    buf = (sv_sweep_record * max_records)()
+    cnt = ctypes.c_int()
+    _check(_lib.sv_profile_read(ctypes.c_void_p(h), buf, max_records, ctypes.byref(cnt)), "sv_profile_read")
+    out = []
+    for i in range(min(cnt.value, max_records)):
+        r = buf[i]
+        d = {f: getattr(r, f) for f, _ in r._fields_ if f != "reserved"}
+        d["kind_name"] = SWEEP_KIND.get(r.kind, str(r.kind))
+        out.append(d)
+    return out

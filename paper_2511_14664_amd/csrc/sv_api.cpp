@@ -1,0 +1,1066 @@
+// The extern "C" entry points declared in include/sv.h.
+//
+// Every entry point validates its arguments on the host first (so argument
+// errors are reported without touching the GPU), then queues kernels on the
+// handle's stream.  Gate application returns without waiting; read-outs
+// synchronise and copy their (small) results to host memory.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+static thread_local std::string g_error;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+}
+
+void clear_error()
+{
+    g_error.clear();
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                     \
+            return SV_EDEVICE;                                                           \
+        }                                                                                \
+    } while (0)
+
+struct sv_state {
+    int n = 0;
+    int dtype = 0;
+    uint64_t bytes = 0;
+    void *d_state = nullptr;
+    bool owned = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int qmap[SV_MAX_QUBITS] = {};
+    // device scratch for read-outs
+    double *d_scratch = nullptr;
+    uint64_t scratch_bytes = 0;
+    // pinned host staging
+    void *h_pinned = nullptr;
+    uint64_t pinned_bytes = 0;
+    // device arena holding block matrices of the current circuit, and its
+    // pinned host staging (reused once the previous upload has completed)
+    void *d_arena = nullptr;
+    uint64_t arena_bytes = 0;
+    void *h_arena = nullptr;
+    uint64_t h_arena_bytes = 0;
+    hipEvent_t arena_done = nullptr;
+    bool arena_pending = false;
+    // sweep timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Pending {
+        sv_sweep_record rec;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+};
+
+struct sv_plan {
+    int n = 0;
+    int dtype = 0;
+    int precision = 0;
+    int ngates = 0;
+    std::vector<Block> blocks;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard()
+    {
+        if (changed)
+            (void)hipSetDevice(prev);
+    }
+};
+
+uint64_t amp_bytes(int dtype)
+{
+    return dtype == SV_C64 ? 8 : 16;
+}
+
+bool identity_map(const sv_state *h)
+{
+    for (int q = 0; q < h->n; ++q)
+        if (h->qmap[q] != q)
+            return false;
+    return true;
+}
+
+int check_handle(sv_handle h)
+{
+    if (h == nullptr) {
+        set_error("NULL handle");
+        return SV_EINVAL;
+    }
+    return SV_OK;
+}
+
+int ensure_scratch(sv_state *h, uint64_t bytes)
+{
+    if (bytes <= h->scratch_bytes)
+        return SV_OK;
+    if (h->d_scratch) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipFree(h->d_scratch));
+        h->d_scratch = nullptr;
+        h->scratch_bytes = 0;
+    }
+    uint64_t want = std::max<uint64_t>(bytes, uint64_t(1) << 20);
+    if (hipMalloc((void **)&h->d_scratch, want) != hipSuccess) {
+        (void)hipGetLastError();
+        h->d_scratch = nullptr;
+        set_error("cannot allocate %llu bytes of device scratch", (unsigned long long)want);
+        return SV_ENOMEM;
+    }
+    h->scratch_bytes = want;
+    return SV_OK;
+}
+
+int ensure_pinned(sv_state *h, uint64_t bytes)
+{
+    if (bytes <= h->pinned_bytes)
+        return SV_OK;
+    if (h->h_pinned) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipHostFree(h->h_pinned));
+        h->h_pinned = nullptr;
+        h->pinned_bytes = 0;
+    }
+    uint64_t want = std::max<uint64_t>(bytes, uint64_t(1) << 20);
+    if (hipHostMalloc(&h->h_pinned, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        h->h_pinned = nullptr;
+        set_error("cannot allocate %llu bytes of pinned host memory", (unsigned long long)want);
+        return SV_ENOMEM;
+    }
+    h->pinned_bytes = want;
+    return SV_OK;
+}
+
+// Upload the matrices of all blocks with k >= 2 (in the state's precision)
+// into the device arena; offsets[i] = byte offset of block i (or -1).
+int upload_matrices(sv_state *h, const std::vector<Block> &blocks, std::vector<int64_t> &offsets)
+{
+    offsets.assign(blocks.size(), -1);
+    const uint64_t S = amp_bytes(h->dtype);
+    uint64_t total = 0;
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        if (blocks[i].k < 2)
+            continue;
+        offsets[i] = int64_t(total);
+        const uint64_t d = uint64_t(1) << blocks[i].k;
+        total += (d * d * S + 255) & ~uint64_t(255);
+    }
+    if (total == 0)
+        return SV_OK;
+    // staging buffer may still be read by the previous upload
+    if (h->arena_pending) {
+        HIP_TRY(hipEventSynchronize(h->arena_done));
+        h->arena_pending = false;
+    }
+    if (total > h->h_arena_bytes) {
+        if (h->h_arena)
+            HIP_TRY(hipHostFree(h->h_arena));
+        h->h_arena = nullptr;
+        h->h_arena_bytes = 0;
+        if (hipHostMalloc(&h->h_arena, total, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot allocate %llu bytes of pinned matrix staging", (unsigned long long)total);
+            return SV_ENOMEM;
+        }
+        h->h_arena_bytes = total;
+    }
+    if (total > h->arena_bytes) {
+        if (h->d_arena) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            HIP_TRY(hipFree(h->d_arena));
+        }
+        h->d_arena = nullptr;
+        h->arena_bytes = 0;
+        if (hipMalloc(&h->d_arena, total) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot allocate %llu bytes of device matrix arena", (unsigned long long)total);
+            return SV_ENOMEM;
+        }
+        h->arena_bytes = total;
+    }
+    char *stage = static_cast<char *>(h->h_arena);
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        if (offsets[i] < 0)
+            continue;
+        const Block &b = blocks[i];
+        const size_t dd = size_t(1) << (2 * b.k);
+        if (h->dtype == SV_C64) {
+            float *dst = reinterpret_cast<float *>(stage + offsets[i]);
+            for (size_t j = 0; j < dd; ++j) {
+                dst[2 * j] = float(b.U[j].real());
+                dst[2 * j + 1] = float(b.U[j].imag());
+            }
+        } else {
+            double *dst = reinterpret_cast<double *>(stage + offsets[i]);
+            for (size_t j = 0; j < dd; ++j) {
+                dst[2 * j] = b.U[j].real();
+                dst[2 * j + 1] = b.U[j].imag();
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(h->d_arena, h->h_arena, total, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipEventRecord(h->arena_done, h->stream));
+    h->arena_pending = true;
+    return SV_OK;
+}
+
+int take_event(sv_state *h, hipEvent_t &ev)
+{
+    if (h->ev_used == h->ev_pool.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        h->ev_pool.push_back(e);
+    }
+    ev = h->ev_pool[h->ev_used++];
+    return SV_OK;
+}
+
+// Open a timed sweep: record the start event (no-op unless profiling).
+int prof_begin(sv_state *h, sv_state::Pending &p)
+{
+    if (!h->profiling)
+        return SV_OK;
+    int rc = take_event(h, p.a);
+    if (rc == SV_OK)
+        rc = take_event(h, p.b);
+    if (rc != SV_OK)
+        return rc;
+    HIP_TRY(hipEventRecord(p.a, h->stream));
+    return SV_OK;
+}
+
+int prof_end(sv_state *h, sv_state::Pending &p)
+{
+    if (!h->profiling)
+        return SV_OK;
+    HIP_TRY(hipEventRecord(p.b, h->stream));
+    h->pending.push_back(p);
+    return SV_OK;
+}
+
+int run_blocks(sv_state *h, const std::vector<Block> &blocks, int precision, int ngates, sv_run_stats *st)
+{
+    std::vector<int64_t> offs;
+    int rc = upload_matrices(h, blocks, offs);
+    if (rc != SV_OK)
+        return rc;
+    sv_run_stats acc{};
+    acc.gates = ngates;
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        const Block &b = blocks[i];
+        int pt[SV_MAX_TARGETS], pc[SV_MAX_CONTROLS];
+        for (int j = 0; j < b.k; ++j)
+            pt[j] = h->qmap[b.targets[j]];
+        for (int j = 0; j < b.c; ++j)
+            pc[j] = h->qmap[b.controls[j]];
+        sv_state::Pending pr{};
+        pr.rec.k = b.k;
+        pr.rec.c = b.c;
+        pr.rec.lowest_target = *std::min_element(pt, pt + b.k);
+        pr.rec.highest_target = *std::max_element(pt, pt + b.k);
+        pr.rec.num_gates = b.ngates;
+        pr.rec.bytes = block_bytes(h->n, h->dtype, b, pt, pc);
+        pr.rec.flops = block_flops(h->n, b);
+        pr.rec.kind = (b.k == 1 && b.diag) ? SV_SWEEP_DIAG1
+                      : (b.k == 1)         ? SV_SWEEP_GATE1
+                                           : dense_path(h->n, h->dtype, b.k, b.c, precision);
+        rc = prof_begin(h, pr);
+        if (rc != SV_OK)
+            return rc;
+        hipError_t e;
+        if (b.k == 1 && b.diag) {
+            e = launch_diag1(h->d_state, h->n, h->dtype, b.U[0], b.U[3], pt[0], pc, b.c, h->stream);
+        } else if (b.k == 1) {
+            cd u[4] = {b.U[0], b.U[1], b.U[2], b.U[3]};
+            e = launch_gate1(h->d_state, h->n, h->dtype, u, pt[0], pc, b.c, h->stream);
+        } else {
+            const void *dU = static_cast<const char *>(h->d_arena) + offs[i];
+            e = launch_gatek(h->d_state, h->n, h->dtype, dU, b.k, pt, pc, b.c, precision, h->stream);
+        }
+        if (e != hipSuccess) {
+            set_error("gate sweep %zu launch failed: %s", i, hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+        rc = prof_end(h, pr);
+        if (rc != SV_OK)
+            return rc;
+        acc.sweeps += 1;
+        if (b.ngates > 1)
+            acc.fused_blocks += 1;
+        acc.algorithmic_bytes += pr.rec.bytes;
+        acc.flops += pr.rec.flops;
+    }
+    if (st)
+        *st = acc;
+    return SV_OK;
+}
+
+int parse_pauli(const sv_state *h, const char *term, uint64_t &x, uint64_t &yz, int &ny)
+{
+    if (term == nullptr) {
+        set_error("NULL Pauli term");
+        return SV_EINVAL;
+    }
+    const size_t len = strlen(term);
+    if (len != size_t(h->n)) {
+        set_error("Pauli term of length %zu on a %d-qubit state", len, h->n);
+        return SV_EINVAL;
+    }
+    x = yz = 0;
+    ny = 0;
+    for (int q = 0; q < h->n; ++q) {
+        const uint64_t bit = uint64_t(1) << h->qmap[q];
+        switch (term[q]) {
+        case 'I': case 'i': break;
+        case 'X': case 'x': x |= bit; break;
+        case 'Y': case 'y': x |= bit; yz |= bit; ++ny; break;
+        case 'Z': case 'z': yz |= bit; break;
+        default:
+            set_error("bad Pauli character '%c'", term[q]);
+            return SV_EINVAL;
+        }
+    }
+    return SV_OK;
+}
+
+int max_device_bytes_env(uint64_t &limit)
+{
+    const char *e = getenv("SV_MAX_DEVICE_BYTES");
+    if (!e || !*e)
+        return 0;
+    limit = strtoull(e, nullptr, 10);
+    return 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sv_last_error(void)
+{
+    return g_error.c_str();
+}
+
+int sv_state_bytes(int n, int dtype, uint64_t *bytes)
+{
+    if (n < 1 || n > SV_MAX_QUBITS) {
+        set_error("qubit count %d outside 1..%d", n, SV_MAX_QUBITS);
+        return SV_EINVAL;
+    }
+    if (dtype != SV_C64 && dtype != SV_C128) {
+        set_error("unknown dtype %d", dtype);
+        return SV_EINVAL;
+    }
+    if (!bytes) {
+        set_error("NULL output");
+        return SV_EINVAL;
+    }
+    *bytes = (uint64_t(1) << n) * amp_bytes(dtype);
+    return SV_OK;
+}
+
+static int init_handle(sv_state *h)
+{
+    for (int q = 0; q < SV_MAX_QUBITS; ++q)
+        h->qmap[q] = q;
+    HIP_TRY(hipEventCreateWithFlags(&h->arena_done, hipEventDisableTiming));
+    hipError_t e = launch_reset(h->d_state, h->n, h->dtype, h->stream);
+    if (e != hipSuccess) {
+        set_error("reset launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    return SV_OK;
+}
+
+int sv_create(int n, int dtype, sv_handle *out)
+{
+    clear_error();
+    uint64_t bytes = 0;
+    int rc = sv_state_bytes(n, dtype, &bytes);
+    if (rc != SV_OK)
+        return rc;
+    if (!out) {
+        set_error("NULL output handle");
+        return SV_EINVAL;
+    }
+    uint64_t limit = 0;
+    if (max_device_bytes_env(limit) && bytes > limit) {
+        set_error("state of %llu bytes exceeds SV_MAX_DEVICE_BYTES=%llu", (unsigned long long)bytes,
+                  (unsigned long long)limit);
+        return SV_ENOMEM;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    size_t freeb = 0, totalb = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    if (bytes > freeb) {
+        set_error("state of %llu bytes does not fit in %llu free bytes", (unsigned long long)bytes,
+                  (unsigned long long)freeb);
+        return SV_ENOMEM;
+    }
+    sv_state *h = new (std::nothrow) sv_state();
+    if (!h) {
+        set_error("out of host memory");
+        return SV_ENOMEM;
+    }
+    h->n = n;
+    h->dtype = dtype;
+    h->bytes = bytes;
+    h->device = dev;
+    if (hipMalloc(&h->d_state, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        set_error("hipMalloc of %llu bytes failed", (unsigned long long)bytes);
+        return SV_ENOMEM;
+    }
+    h->owned = true;
+    rc = init_handle(h);
+    if (rc != SV_OK) {
+        sv_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return SV_OK;
+}
+
+int sv_create_on(void *device_ptr, uint64_t bytes, int n, int dtype, void *stream, sv_handle *out)
+{
+    clear_error();
+    uint64_t need = 0;
+    int rc = sv_state_bytes(n, dtype, &need);
+    if (rc != SV_OK)
+        return rc;
+    if (!out || !device_ptr) {
+        set_error("NULL pointer argument");
+        return SV_EINVAL;
+    }
+    if (bytes < need) {
+        set_error("buffer of %llu bytes is smaller than the %llu-byte state", (unsigned long long)bytes,
+                  (unsigned long long)need);
+        return SV_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(device_ptr) % 16 != 0) {
+        set_error("device buffer must be 16-byte aligned");
+        return SV_EINVAL;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    sv_state *h = new (std::nothrow) sv_state();
+    if (!h) {
+        set_error("out of host memory");
+        return SV_ENOMEM;
+    }
+    h->n = n;
+    h->dtype = dtype;
+    h->bytes = need;
+    h->device = dev;
+    h->d_state = device_ptr;
+    h->owned = false;
+    h->stream = static_cast<hipStream_t>(stream);
+    rc = init_handle(h);
+    if (rc != SV_OK) {
+        sv_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return SV_OK;
+}
+
+int sv_destroy(sv_handle h)
+{
+    if (!h)
+        return SV_OK;
+    DeviceGuard g(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->owned && h->d_state)
+        (void)hipFree(h->d_state);
+    if (h->d_scratch)
+        (void)hipFree(h->d_scratch);
+    if (h->d_arena)
+        (void)hipFree(h->d_arena);
+    if (h->h_pinned)
+        (void)hipHostFree(h->h_pinned);
+    if (h->h_arena)
+        (void)hipHostFree(h->h_arena);
+    if (h->arena_done)
+        (void)hipEventDestroy(h->arena_done);
+    for (hipEvent_t e : h->ev_pool)
+        (void)hipEventDestroy(e);
+    delete h;
+    return SV_OK;
+}
+
+int sv_set_stream(sv_handle h, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    h->stream = static_cast<hipStream_t>(stream);
+    return SV_OK;
+}
+
+int sv_synchronize(sv_handle h)
+{
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    DeviceGuard g(h->device);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SV_OK;
+}
+
+int sv_reset(sv_handle h)
+{
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    DeviceGuard g(h->device);
+    for (int q = 0; q < SV_MAX_QUBITS; ++q)
+        h->qmap[q] = q;
+    hipError_t e = launch_reset(h->d_state, h->n, h->dtype, h->stream);
+    if (e != hipSuccess) {
+        set_error("reset launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    return SV_OK;
+}
+
+int sv_apply_gate(sv_handle h, const double *U, const int *targets, int k, const int *controls, int c)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (!U || !targets || (c > 0 && !controls) || k < 1 || k > SV_MAX_TARGETS || c < 0 ||
+        c > SV_MAX_CONTROLS) {
+        set_error("bad gate arguments (k=%d, c=%d)", k, c);
+        return SV_EINVAL;
+    }
+    sv_gate g{};
+    g.kind = SV_GATE_MATRIX;
+    g.num_targets = k;
+    g.num_controls = c;
+    for (int j = 0; j < k; ++j)
+        g.targets[j] = targets[j];
+    for (int j = 0; j < c; ++j)
+        g.controls[j] = controls[j];
+    g.matrix = U;
+    rc = validate_gate(g, h->n, 0);
+    if (rc != SV_OK)
+        return rc;
+    std::vector<Block> blocks(1, gate_block(g));
+    DeviceGuard dg(h->device);
+    return run_blocks(h, blocks, SV_PREC_NATIVE, 1, nullptr);
+}
+
+int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_plan_opts *opts, sv_run_stats *stats)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    sv_plan_opts o{};
+    if (opts)
+        o = *opts;
+    std::vector<Block> blocks;
+    rc = plan_circuit(h->n, h->dtype, gates, ngates, o, blocks);
+    if (rc != SV_OK)
+        return rc;
+    DeviceGuard dg(h->device);
+    return run_blocks(h, blocks, o.precision, ngates, stats);
+}
+
+int sv_swap_bits(sv_handle h, int lo, int hi, int width)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (width < 1 || width > 6 || lo < 0 || lo + width > hi || hi + width > h->n) {
+        set_error("bad bit fields lo=%d hi=%d width=%d for n=%d", lo, hi, width, h->n);
+        return SV_EINVAL;
+    }
+    DeviceGuard dg(h->device);
+    sv_state::Pending pr{};
+    pr.rec.kind = SV_SWEEP_BITSWAP;
+    pr.rec.k = width;
+    pr.rec.lowest_target = lo;
+    pr.rec.highest_target = hi;
+    pr.rec.bytes = 2.0 * double(h->bytes) * (1.0 - std::ldexp(1.0, -width));
+    rc = prof_begin(h, pr);
+    if (rc != SV_OK)
+        return rc;
+    hipError_t e = launch_bitswap(h->d_state, h->n, h->dtype, lo, hi, width, h->stream);
+    if (e != hipSuccess) {
+        set_error("bit swap launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    rc = prof_end(h, pr);
+    if (rc != SV_OK)
+        return rc;
+    for (int q = 0; q < h->n; ++q) {
+        const int p = h->qmap[q];
+        if (p >= lo && p < lo + width)
+            h->qmap[q] = p - lo + hi;
+        else if (p >= hi && p < hi + width)
+            h->qmap[q] = p - hi + lo;
+    }
+    return SV_OK;
+}
+
+int sv_qubit_map(sv_handle h, int *map)
+{
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (!map) {
+        set_error("NULL map");
+        return SV_EINVAL;
+    }
+    for (int q = 0; q < h->n; ++q)
+        map[q] = h->qmap[q];
+    return SV_OK;
+}
+
+int sv_probabilities(sv_handle h, const int *qubits, int m, double *out)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (m < 0 || m > h->n || m > 30 || !out || (m > 0 && !qubits)) {
+        set_error("bad marginal request (m=%d, n=%d)", m, h->n);
+        return SV_EINVAL;
+    }
+    int phys[30];
+    uint64_t used = 0;
+    for (int b = 0; b < m; ++b) {
+        if (qubits[b] < 0 || qubits[b] >= h->n || ((used >> qubits[b]) & 1)) {
+            set_error("bad or repeated qubit %d", qubits[b]);
+            return SV_EINVAL;
+        }
+        used |= uint64_t(1) << qubits[b];
+        phys[b] = h->qmap[qubits[b]];
+    }
+    DeviceGuard dg(h->device);
+    const uint64_t nbins = uint64_t(1) << m;
+    const uint64_t part = marginal_scratch_doubles(h->n, m);
+    rc = ensure_scratch(h, (part + nbins) * sizeof(double));
+    if (rc != SV_OK)
+        return rc;
+    rc = ensure_pinned(h, nbins * sizeof(double));
+    if (rc != SV_OK)
+        return rc;
+    double *d_out = h->d_scratch + part;
+    hipError_t e = launch_marginal(h->d_state, h->n, h->dtype, phys, m, h->d_scratch, d_out, h->stream);
+    if (e != hipSuccess) {
+        set_error("marginal launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_out, nbins * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    memcpy(out, h->h_pinned, nbins * sizeof(double));
+    return SV_OK;
+}
+
+int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *out)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (nterms < 0 || (nterms > 0 && (!terms || !out))) {
+        set_error("bad term list");
+        return SV_EINVAL;
+    }
+    std::vector<uint64_t> xs(nterms), yzs(nterms);
+    std::vector<int> nys(nterms);
+    for (int t = 0; t < nterms; ++t) {
+        rc = parse_pauli(h, terms[t], xs[t], yzs[t], nys[t]);
+        if (rc != SV_OK)
+            return rc;
+    }
+    if (nterms == 0)
+        return SV_OK;
+    DeviceGuard dg(h->device);
+    const uint64_t part = expect_scratch_doubles(h->n);
+    // result slots: 2 doubles per term
+    rc = ensure_scratch(h, (part + 2 * uint64_t(nterms)) * sizeof(double));
+    if (rc != SV_OK)
+        return rc;
+    rc = ensure_pinned(h, 2 * uint64_t(nterms) * sizeof(double));
+    if (rc != SV_OK)
+        return rc;
+    double *d_res = h->d_scratch + part;
+    // Z-only strings in batches of 16 (slot 2*t holds the value)
+    std::vector<int> zterms;
+    for (int t = 0; t < nterms; ++t)
+        if (xs[t] == 0)
+            zterms.push_back(t);
+    std::vector<double> zvals(zterms.size());
+    // results of a batch land in d_res[0..nb) then are moved on the host
+    std::vector<double> host(2 * size_t(nterms), 0.0);
+    for (size_t s = 0; s < zterms.size(); s += 16) {
+        const int nb = int(std::min<size_t>(16, zterms.size() - s));
+        uint64_t z[16];
+        for (int j = 0; j < nb; ++j)
+            z[j] = yzs[zterms[s + j]];
+        hipError_t e = launch_expect_z(h->d_state, h->n, h->dtype, z, nb, h->d_scratch, d_res, h->stream);
+        if (e != hipSuccess) {
+            set_error("Z expectation launch failed: %s", hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+        HIP_TRY(hipMemcpyAsync(h->h_pinned, d_res, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const double *pv = static_cast<const double *>(h->h_pinned);
+        for (int j = 0; j < nb; ++j)
+            out[zterms[s + j]] = pv[j];
+    }
+    for (int t = 0; t < nterms; ++t) {
+        if (xs[t] == 0)
+            continue;
+        hipError_t e = launch_expect_xy(h->d_state, h->n, h->dtype, xs[t], yzs[t], h->d_scratch, d_res, h->stream);
+        if (e != hipSuccess) {
+            set_error("Pauli expectation launch failed: %s", hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+        HIP_TRY(hipMemcpyAsync(h->h_pinned, d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const double *pv = static_cast<const double *>(h->h_pinned);
+        const cd S(pv[0], pv[1]);
+        // multiply by i^(number of Y)
+        static const cd ipow[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+        out[t] = (ipow[nys[t] & 3] * S).real();
+    }
+    return SV_OK;
+}
+
+int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (shots < 0 || (shots > 0 && (!uniforms || !out))) {
+        set_error("bad sampling arguments");
+        return SV_EINVAL;
+    }
+    for (int s = 0; s < shots; ++s)
+        if (!(uniforms[s] >= 0.0 && uniforms[s] < 1.0)) {
+            set_error("uniform %d = %g outside [0, 1)", s, uniforms[s]);
+            return SV_EINVAL;
+        }
+    if (shots == 0)
+        return SV_OK;
+    DeviceGuard dg(h->device);
+    const int lbs = sample_log_block(h->n);
+    const uint64_t nb = uint64_t(1) << (h->n - lbs);
+    // scratch: block sums | blocks (int64) | targets | outputs (int64)
+    const uint64_t need = (nb + 3 * uint64_t(shots)) * 8;
+    rc = ensure_scratch(h, need);
+    if (rc != SV_OK)
+        return rc;
+    rc = ensure_pinned(h, std::max<uint64_t>(nb, 2 * uint64_t(shots)) * 8);
+    if (rc != SV_OK)
+        return rc;
+    double *d_bs = h->d_scratch;
+    int64_t *d_blk = reinterpret_cast<int64_t *>(h->d_scratch + nb);
+    double *d_tgt = h->d_scratch + nb + shots;
+    int64_t *d_out = reinterpret_cast<int64_t *>(h->d_scratch + nb + 2 * uint64_t(shots));
+    hipError_t e = launch_block_sums(h->d_state, h->n, h->dtype, d_bs, h->stream);
+    if (e != hipSuccess) {
+        set_error("block-sum launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_bs, nb * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    // inclusive prefix of block sums, sequential FP64
+    std::vector<double> pre(nb);
+    const double *bs = static_cast<const double *>(h->h_pinned);
+    double run = 0.0;
+    uint64_t last_pos = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        run += bs[b];
+        pre[b] = run;
+        if (bs[b] > 0.0)
+            last_pos = b;
+    }
+    const double norm = run;
+    std::vector<int64_t> blk(shots);
+    std::vector<double> tgt(shots);
+    for (int s = 0; s < shots; ++s) {
+        const double t = uniforms[s] * norm;
+        const uint64_t b = uint64_t(std::upper_bound(pre.begin(), pre.end(), t) - pre.begin());
+        if (b >= nb) {
+            blk[s] = int64_t(last_pos);
+            tgt[s] = bs[last_pos];  // no in-block index exceeds it: last nonzero is returned
+        } else {
+            blk[s] = int64_t(b);
+            tgt[s] = t - (b > 0 ? pre[b - 1] : 0.0);
+        }
+    }
+    // pinned staging is free again (synchronised above)
+    memcpy(h->h_pinned, blk.data(), shots * 8);
+    memcpy(static_cast<char *>(h->h_pinned) + shots * 8, tgt.data(), shots * 8);
+    HIP_TRY(hipMemcpyAsync(d_blk, h->h_pinned, 2 * uint64_t(shots) * 8, hipMemcpyHostToDevice, h->stream));
+    e = launch_sample_search(h->d_state, h->n, h->dtype, d_blk, d_tgt, shots, d_out, h->stream);
+    if (e != hipSuccess) {
+        set_error("sample search launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_out, uint64_t(shots) * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const int64_t *phys = static_cast<const int64_t *>(h->h_pinned);
+    const bool ident = identity_map(h);
+    for (int s = 0; s < shots; ++s) {
+        if (ident) {
+            out[s] = phys[s];
+        } else {
+            int64_t l = 0;
+            for (int q = 0; q < h->n; ++q)
+                l |= ((phys[s] >> h->qmap[q]) & 1) << q;
+            out[s] = l;
+        }
+    }
+    return SV_OK;
+}
+
+int sv_copy_to_host(sv_handle h, void *dst, uint64_t first, uint64_t count)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    const uint64_t N = uint64_t(1) << h->n;
+    if (!dst || first > N || count > N - first) {
+        set_error("bad copy range [%llu, +%llu) of %llu", (unsigned long long)first, (unsigned long long)count,
+                  (unsigned long long)N);
+        return SV_EINVAL;
+    }
+    if (count == 0)
+        return SV_OK;
+    DeviceGuard dg(h->device);
+    const uint64_t S = amp_bytes(h->dtype);
+    if (identity_map(h)) {
+        HIP_TRY(hipMemcpyAsync(dst, static_cast<const char *>(h->d_state) + first * S, count * S,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return SV_OK;
+    }
+    const uint64_t chunk = uint64_t(1) << 22;
+    rc = ensure_scratch(h, std::min(count, chunk) * S);
+    if (rc != SV_OK)
+        return rc;
+    for (uint64_t done = 0; done < count; done += chunk) {
+        const uint64_t c = std::min(chunk, count - done);
+        hipError_t e = launch_gather_logical(h->d_state, h->d_scratch, h->n, h->dtype, h->qmap, first + done, c,
+                                             h->stream);
+        if (e != hipSuccess) {
+            set_error("gather launch failed: %s", hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+        HIP_TRY(hipMemcpyAsync(static_cast<char *>(dst) + done * S, h->d_scratch, c * S, hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    return SV_OK;
+}
+
+int sv_copy_from_host(sv_handle h, const void *src, uint64_t first, uint64_t count)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    const uint64_t N = uint64_t(1) << h->n;
+    if (!src || first > N || count > N - first) {
+        set_error("bad copy range");
+        return SV_EINVAL;
+    }
+    const bool whole = first == 0 && count == N;
+    if (!identity_map(h) && !whole) {
+        set_error("partial copy into a relaid-out state (qubit map not identity)");
+        return SV_EINVAL;
+    }
+    if (count == 0)
+        return SV_OK;
+    DeviceGuard dg(h->device);
+    const uint64_t S = amp_bytes(h->dtype);
+    HIP_TRY(hipMemcpyAsync(static_cast<char *>(h->d_state) + first * S, src, count * S, hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (whole)
+        for (int q = 0; q < SV_MAX_QUBITS; ++q)
+            h->qmap[q] = q;
+    return SV_OK;
+}
+
+int sv_profile_enable(sv_handle h, int enable)
+{
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    h->profiling = enable != 0;
+    return SV_OK;
+}
+
+int sv_profile_read(sv_handle h, sv_sweep_record *out, int max, int *count)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (max < 0 || (max > 0 && !out) || !count) {
+        set_error("bad profile buffer");
+        return SV_EINVAL;
+    }
+    DeviceGuard dg(h->device);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int k = 0;
+    for (auto &p : h->pending) {
+        if (k < max) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+            out[k] = p.rec;
+            out[k].ms = ms;
+        }
+        ++k;
+    }
+    *count = k;
+    h->pending.clear();
+    h->ev_used = 0;
+    return SV_OK;
+}
+
+int sv_plan_create(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts *opts, sv_plan_handle *out)
+{
+    clear_error();
+    uint64_t bytes;
+    int rc = sv_state_bytes(n, dtype, &bytes);
+    if (rc != SV_OK)
+        return rc;
+    if (!out) {
+        set_error("NULL output");
+        return SV_EINVAL;
+    }
+    sv_plan_opts o{};
+    if (opts)
+        o = *opts;
+    sv_plan *p = new (std::nothrow) sv_plan();
+    if (!p) {
+        set_error("out of host memory");
+        return SV_ENOMEM;
+    }
+    rc = plan_circuit(n, dtype, gates, ngates, o, p->blocks);
+    if (rc != SV_OK) {
+        delete p;
+        return rc;
+    }
+    p->n = n;
+    p->dtype = dtype;
+    p->precision = o.precision;
+    p->ngates = ngates;
+    *out = p;
+    return SV_OK;
+}
+
+int sv_plan_num_blocks(sv_plan_handle p, int *nblocks)
+{
+    if (!p || !nblocks) {
+        set_error("NULL argument");
+        return SV_EINVAL;
+    }
+    *nblocks = int(p->blocks.size());
+    return SV_OK;
+}
+
+int sv_plan_block(sv_plan_handle p, int i, int *k, int *targets, int *c, int *controls, double *matrix,
+                  int *num_gates)
+{
+    if (!p || i < 0 || i >= int(p->blocks.size())) {
+        set_error("bad plan or block index");
+        return SV_EINVAL;
+    }
+    const Block &b = p->blocks[i];
+    if (k)
+        *k = b.k;
+    if (c)
+        *c = b.c;
+    if (targets)
+        for (int j = 0; j < b.k; ++j)
+            targets[j] = b.targets[j];
+    if (controls)
+        for (int j = 0; j < b.c; ++j)
+            controls[j] = b.controls[j];
+    if (matrix)
+        for (size_t j = 0; j < b.U.size(); ++j) {
+            matrix[2 * j] = b.U[j].real();
+            matrix[2 * j + 1] = b.U[j].imag();
+        }
+    if (num_gates)
+        *num_gates = b.ngates;
+    return SV_OK;
+}
+
+int sv_apply_plan(sv_handle h, sv_plan_handle p, sv_run_stats *stats)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (!p || p->n != h->n || p->dtype != h->dtype) {
+        set_error("plan does not match the state (n or dtype)");
+        return SV_EINVAL;
+    }
+    DeviceGuard dg(h->device);
+    return run_blocks(h, p->blocks, p->precision, p->ngates, stats);
+}
+
+int sv_plan_destroy(sv_plan_handle p)
+{
+    delete p;
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,773 @@
+// Gate-application sweeps over the state vector (gfx950).
+//
+// Every kernel here is one pass over (part of) the 2^n amplitudes in HBM:
+// the paper's gate application (Sec. 2.1 "State-Vector Simulation"), where a
+// one-qubit gate multiplies amplitude pairs (i, i | 2^t) by its 2x2 matrix and a
+// fused k-qubit block multiplies groups of 2^k amplitudes by a 2^k x 2^k matrix.
+// The sweeps are bandwidth-bound, so the kernels are built around coalesced
+// 16-byte loads, several independent loads in flight per thread, and an LDS
+// tile for the multi-target case so that every global access is contiguous
+// whatever the target bits are.
+#include <algorithm>
+#include <cstring>
+
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 4;
+constexpr int kMaxIns = SV_MAX_TARGETS + SV_MAX_CONTROLS;
+
+template <typename R>
+struct CT;
+template <>
+struct CT<float> {
+    using C = float2;
+};
+template <>
+struct CT<double> {
+    using C = double2;
+};
+
+// Insert a 0 bit at each of up to kMaxIns sorted positions: m[j] = 2^p_j - 1.
+struct InsertMasks {
+    uint64_t m[kMaxIns];
+    int n;
+};
+
+InsertMasks make_insert_masks(std::vector<int> pos)
+{
+    std::sort(pos.begin(), pos.end());
+    InsertMasks im{};
+    im.n = static_cast<int>(pos.size());
+    for (int j = 0; j < im.n; ++j)
+        im.m[j] = (uint64_t(1) << pos[j]) - 1;
+    return im;
+}
+
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const InsertMasks &im)
+{
+    for (int j = 0; j < im.n; ++j) {
+        const uint64_t lo = im.m[j];
+        g = (g & lo) | ((g & ~lo) << 1);
+    }
+    return g;
+}
+
+template <typename C>
+__device__ __forceinline__ C cmad(C u, C v, C acc)
+{
+    acc.x += u.x * v.x - u.y * v.y;
+    acc.y += u.x * v.y + u.y * v.x;
+    return acc;
+}
+
+template <typename C>
+__device__ __forceinline__ C cmul(C u, C v)
+{
+    C r;
+    r.x = u.x * v.x - u.y * v.y;
+    r.y = u.x * v.y + u.y * v.x;
+    return r;
+}
+
+template <typename C>
+__device__ __forceinline__ C czero()
+{
+    C r;
+    r.x = 0;
+    r.y = 0;
+    return r;
+}
+
+hipError_t check_grid(uint64_t blocks)
+{
+    return blocks > 0x7fffffffull ? hipErrorInvalidConfiguration : hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// |0...0>
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_reset(R *__restrict__ st, uint64_t nvec)
+{
+    // 16-byte vectors: two complex64 or one complex128 amplitude each.
+    using V = typename std::conditional<std::is_same<R, float>::value, float4, double2>::type;
+    V *v = reinterpret_cast<V *>(st);
+    const uint64_t stride = uint64_t(gridDim.x) * kThreads;
+    for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < nvec; i += stride) {
+        V z{};
+        if (i == 0) {
+            if constexpr (std::is_same<R, float>::value)
+                z.x = 1.0f;
+            else
+                z.x = 1.0;
+        }
+        v[i] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-target dense gate (controls allowed).  Group g enumerates the indices
+// whose target bit is 0 and control bits are 1; pair (i0, i0 | 2^t).
+// VEC: complex64 with index bit 0 free -> each thread takes two adjacent
+// groups with 16-byte loads.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Gate1Args {
+    uint64_t nunits;
+    uint64_t cmask;
+    uint64_t tbit;
+    InsertMasks im;
+    R u[8];  // u00, u01, u10, u11 as (re, im)
+};
+
+template <typename R, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Gate1Args<R> a)
+{
+    using C = typename CT<R>::C;
+    const uint64_t u0 = uint64_t(blockIdx.x) * (kThreads * kItems) + threadIdx.x;
+    C m00, m01, m10, m11;
+    m00.x = a.u[0], m00.y = a.u[1], m01.x = a.u[2], m01.y = a.u[3];
+    m10.x = a.u[4], m10.y = a.u[5], m11.x = a.u[6], m11.y = a.u[7];
+    if constexpr (VEC) {
+        float4 *v = reinterpret_cast<float4 *>(st);
+        float4 lo[kItems], hi[kItems];
+        uint64_t ia[kItems], ib[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint64_t u = u0 + uint64_t(j) * kThreads;
+            ia[j] = ib[j] = ~uint64_t(0);
+            if (u < a.nunits) {
+                const uint64_t i0 = insert_zeros(u << 1, a.im) | a.cmask;
+                ia[j] = i0 >> 1;
+                ib[j] = (i0 | a.tbit) >> 1;
+                lo[j] = v[ia[j]];
+                hi[j] = v[ib[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (ia[j] == ~uint64_t(0))
+                continue;
+            C l0 = make_float2(lo[j].x, lo[j].y), l1 = make_float2(lo[j].z, lo[j].w);
+            C h0 = make_float2(hi[j].x, hi[j].y), h1 = make_float2(hi[j].z, hi[j].w);
+            C a0 = cmad(m01, h0, cmul(m00, l0)), b0 = cmad(m11, h0, cmul(m10, l0));
+            C a1 = cmad(m01, h1, cmul(m00, l1)), b1 = cmad(m11, h1, cmul(m10, l1));
+            v[ia[j]] = make_float4(a0.x, a0.y, a1.x, a1.y);
+            v[ib[j]] = make_float4(b0.x, b0.y, b1.x, b1.y);
+        }
+    } else {
+        C *v = reinterpret_cast<C *>(st);
+        C lo[kItems], hi[kItems];
+        uint64_t ia[kItems], ib[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint64_t u = u0 + uint64_t(j) * kThreads;
+            ia[j] = ib[j] = ~uint64_t(0);
+            if (u < a.nunits) {
+                ia[j] = insert_zeros(u, a.im) | a.cmask;
+                ib[j] = ia[j] | a.tbit;
+                lo[j] = v[ia[j]];
+                hi[j] = v[ib[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (ia[j] == ~uint64_t(0))
+                continue;
+            v[ia[j]] = cmad(m01, hi[j], cmul(m00, lo[j]));
+            v[ib[j]] = cmad(m11, hi[j], cmul(m10, lo[j]));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-target diagonal gate diag(d0, d1) with controls: a[i] *= d[bit t of i]
+// over the indices whose fixed bits match (controls = 1, and the target = 1
+// when d0 == 1, so untouched amplitudes are never read).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Diag1Args {
+    uint64_t nunits;
+    uint64_t fixed;
+    uint64_t tbit;
+    InsertMasks im;
+    R d[4];  // d0, d1 as (re, im)
+};
+
+template <typename R, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Diag1Args<R> a)
+{
+    using C = typename CT<R>::C;
+    const uint64_t u0 = uint64_t(blockIdx.x) * (kThreads * kItems) + threadIdx.x;
+    C d0, d1;
+    d0.x = a.d[0], d0.y = a.d[1], d1.x = a.d[2], d1.y = a.d[3];
+    if constexpr (VEC) {
+        float4 *v = reinterpret_cast<float4 *>(st);
+        float4 x[kItems];
+        uint64_t ia[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint64_t u = u0 + uint64_t(j) * kThreads;
+            ia[j] = ~uint64_t(0);
+            if (u < a.nunits) {
+                ia[j] = insert_zeros(u << 1, a.im) | a.fixed;
+                x[j] = v[ia[j] >> 1];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (ia[j] == ~uint64_t(0))
+                continue;
+            const C f = (ia[j] & a.tbit) ? d1 : d0;
+            C p0 = cmul(f, make_float2(x[j].x, x[j].y)), p1 = cmul(f, make_float2(x[j].z, x[j].w));
+            v[ia[j] >> 1] = make_float4(p0.x, p0.y, p1.x, p1.y);
+        }
+    } else {
+        C *v = reinterpret_cast<C *>(st);
+        C x[kItems];
+        uint64_t ia[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint64_t u = u0 + uint64_t(j) * kThreads;
+            ia[j] = ~uint64_t(0);
+            if (u < a.nunits) {
+                ia[j] = insert_zeros(u, a.im) | a.fixed;
+                x[j] = v[ia[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (ia[j] == ~uint64_t(0))
+                continue;
+            v[ia[j]] = cmul((ia[j] & a.tbit) ? d1 : d0, x[j]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense k-target gate, one group of 2^k amplitudes per thread (small states,
+// where the LDS tile below does not fit).
+// ---------------------------------------------------------------------------
+struct GatekArgs {
+    uint64_t ngroups;
+    uint64_t cmask;
+    InsertMasks im;
+    uint64_t off[64];
+    const void *U;
+};
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_gatek(R *__restrict__ st, const GatekArgs a)
+{
+    using C = typename CT<R>::C;
+    constexpr int D = 1 << K;
+    C *v = reinterpret_cast<C *>(st);
+    const C *U = reinterpret_cast<const C *>(a.U);
+    const uint64_t stride = uint64_t(gridDim.x) * kThreads;
+    for (uint64_t g = uint64_t(blockIdx.x) * kThreads + threadIdx.x; g < a.ngroups; g += stride) {
+        const uint64_t base = insert_zeros(g, a.im) | a.cmask;
+        C x[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            x[j] = v[base + a.off[j]];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            C acc = czero<C>();
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                acc = cmad(U[r * D + c], x[c], acc);
+            v[base + a.off[r]] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense k-target gate through an LDS tile.
+//
+// A tile is the 2^(k+m) amplitudes whose bits outside (targets + the m lowest
+// free bits) are fixed: 2^m groups of 2^k.  Tile-local index x lists the tile
+// bits in ascending physical order, so consecutive x are consecutive
+// addresses in runs of at least 2^m amplitudes: loads and stores are
+// coalesced whatever the targets.  In LDS, each wave owns 64 consecutive
+// groups (one per lane) and a block of RB output rows; the matrix entries it
+// needs are wave-uniform (scalar loads).  LDS addresses are XOR-swizzled
+// (low 6 bits ^= next 6 bits) so lanes reading with a power-of-two stride hit
+// distinct banks.
+// ---------------------------------------------------------------------------
+template <int K>
+struct TileShape {
+    static constexpr int TA_LOG = (K <= 5) ? 11 : 12;
+    static constexpr int TA = 1 << TA_LOG;
+    static constexpr int M = TA_LOG - K;  // group bits, >= 6
+    static constexpr int RB = (K >= 3) ? 8 : (1 << K);
+    static constexpr int OPT = TA / kThreads;
+    static constexpr int PAIRS = OPT / RB;
+    static constexpr int GCH = (1 << M) / 64;
+};
+
+struct TileArgs {
+    uint64_t ntiles;
+    uint64_t cmask;
+    InsertMasks outer;     // zeros at tile bits and control bits
+    uint64_t dep[12];      // dep[b] = 2^(physical position of tile bit b)
+    uint32_t tslot_m[SV_MAX_TARGETS];  // insert masks of the target slots in x
+    int ntslot;
+    uint16_t xc[64];       // x bits of target-row index r
+    const void *U;
+};
+
+__device__ __forceinline__ uint32_t swz(uint32_t x)
+{
+    return x ^ ((x >> 6) & 63u);
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const TileArgs a)
+{
+    using C = typename CT<R>::C;
+    using S = TileShape<K>;
+    constexpr int D = 1 << K;
+    __shared__ C tile[S::TA];
+    C *v = reinterpret_cast<C *>(st);
+    const C *U = reinterpret_cast<const C *>(a.U);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+
+    uint64_t off_lo = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((tid >> b) & 1)
+            off_lo |= a.dep[b];
+
+    uint32_t xg[S::PAIRS];
+    int rb[S::PAIRS];
+#pragma unroll
+    for (int j = 0; j < S::PAIRS; ++j) {
+        const int p = wave + 4 * j;
+        rb[j] = p / S::GCH;
+        uint32_t g = uint32_t((p % S::GCH) * 64 + lane);
+        for (int s = 0; s < a.ntslot; ++s) {
+            const uint32_t lo = a.tslot_m[s];
+            g = (g & lo) | ((g & ~lo) << 1);
+        }
+        xg[j] = g;
+    }
+
+    for (uint64_t o = blockIdx.x; o < a.ntiles; o += gridDim.x) {
+        const uint64_t base = insert_zeros(o, a.outer) | a.cmask;
+#pragma unroll
+        for (int s = 0; s < S::OPT; ++s) {
+            uint64_t off = off_lo;
+#pragma unroll
+            for (int b = 8; b < S::TA_LOG; ++b)
+                if ((s >> (b - 8)) & 1)
+                    off |= a.dep[b];
+            tile[swz(uint32_t(s * kThreads + tid))] = v[base + off];
+        }
+        __syncthreads();
+
+        C acc[S::PAIRS][S::RB];
+#pragma unroll
+        for (int j = 0; j < S::PAIRS; ++j) {
+#pragma unroll
+            for (int rr = 0; rr < S::RB; ++rr)
+                acc[j][rr] = czero<C>();
+            const C *Ur = U + size_t(rb[j]) * S::RB * D;
+            for (int col = 0; col < D; ++col) {
+                const C x = tile[swz(uint32_t(a.xc[col]) | xg[j])];
+#pragma unroll
+                for (int rr = 0; rr < S::RB; ++rr)
+                    acc[j][rr] = cmad(Ur[rr * D + col], x, acc[j][rr]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < S::PAIRS; ++j)
+#pragma unroll
+            for (int rr = 0; rr < S::RB; ++rr)
+                tile[swz(uint32_t(a.xc[rb[j] * S::RB + rr]) | xg[j])] = acc[j][rr];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < S::OPT; ++s) {
+            uint64_t off = off_lo;
+#pragma unroll
+            for (int b = 8; b < S::TA_LOG; ++b)
+                if ((s >> (b - 8)) & 1)
+                    off |= a.dep[b];
+            v[base + off] = tile[swz(uint32_t(s * kThreads + tid))];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// In-place exchange of index-bit fields [lo, lo+w) and [hi, hi+w).  A tile is
+// the 2^(L+2w) amplitudes spanned by the L lowest index bits (L = lo bits kept
+// for contiguity, none when lo = 0) and both fields; the permutation maps
+// every tile onto itself, so each workgroup reads its whole tile into LDS,
+// synchronises, and writes it back permuted.  Pure copies: bit-exact.
+// ---------------------------------------------------------------------------
+struct BitswapArgs {
+    uint64_t ntiles;
+    InsertMasks outer;
+    uint64_t dep[12];
+    int tlog;
+    int L;
+    int w;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_bitswap(R *__restrict__ st, const BitswapArgs a)
+{
+    using C = typename CT<R>::C;
+    __shared__ C tile[4096];
+    C *v = reinterpret_cast<C *>(st);
+    const int tid = threadIdx.x;
+    const int TA = 1 << a.tlog;
+    const uint32_t wm = (1u << a.w) - 1u;
+    const uint32_t fmask = (wm << a.L) | (wm << (a.L + a.w));
+    uint64_t off_lo = 0;
+    for (int b = 0; b < 8 && b < a.tlog; ++b)
+        if ((tid >> b) & 1)
+            off_lo |= a.dep[b];
+    const int nsteps = TA >= kThreads ? TA / kThreads : 1;
+    const bool active = tid < TA;
+    for (uint64_t o = blockIdx.x; o < a.ntiles; o += gridDim.x) {
+        const uint64_t base = insert_zeros(o, a.outer);
+        for (int s = 0; s < nsteps; ++s) {
+            if (!active)
+                break;
+            uint64_t off = off_lo;
+            for (int b = 8; b < a.tlog; ++b)
+                if ((s >> (b - 8)) & 1)
+                    off |= a.dep[b];
+            tile[swz(uint32_t(s * kThreads + tid))] = v[base + off];
+        }
+        __syncthreads();
+        for (int s = 0; s < nsteps; ++s) {
+            if (!active)
+                break;
+            const uint32_t y = uint32_t(s * kThreads + tid);
+            const uint32_t f1 = (y >> a.L) & wm, f2 = (y >> (a.L + a.w)) & wm;
+            const uint32_t x = (y & ~fmask) | (f1 << (a.L + a.w)) | (f2 << a.L);
+            uint64_t off = off_lo;
+            for (int b = 8; b < a.tlog; ++b)
+                if ((s >> (b - 8)) & 1)
+                    off |= a.dep[b];
+            v[base + off] = tile[swz(x)];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Logical-order read-out under a non-identity qubit map.
+// ---------------------------------------------------------------------------
+struct GatherArgs {
+    uint64_t first;
+    uint64_t count;
+    int n;
+    int qmap[SV_MAX_QUBITS];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_gather(const R *__restrict__ st, R *__restrict__ dst,
+                                                     const GatherArgs a)
+{
+    using C = typename CT<R>::C;
+    const C *v = reinterpret_cast<const C *>(st);
+    C *d = reinterpret_cast<C *>(dst);
+    const uint64_t stride = uint64_t(gridDim.x) * kThreads;
+    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < a.count; j += stride) {
+        const uint64_t l = a.first + j;
+        uint64_t p = 0;
+        for (int q = 0; q < a.n; ++q)
+            p |= ((l >> q) & 1) << a.qmap[q];
+        d[j] = v[p];
+    }
+}
+
+template <typename R>
+void fill_u(R *dst, const cd *src, int count)
+{
+    for (int i = 0; i < count; ++i) {
+        dst[2 * i] = R(src[i].real());
+        dst[2 * i + 1] = R(src[i].imag());
+    }
+}
+
+uint64_t grid_for(uint64_t work, uint64_t per_block, uint64_t cap)
+{
+    uint64_t b = (work + per_block - 1) / per_block;
+    if (b < 1)
+        b = 1;
+    return b > cap ? cap : b;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+hipError_t launch_reset(void *st, int n, int dtype, hipStream_t s)
+{
+    const uint64_t bytes = (uint64_t(1) << n) * (dtype == SV_C64 ? 8 : 16);
+    const uint64_t nvec = bytes / 16;
+    if (nvec == 0) {
+        // n = 0 cannot occur (n >= 1); a 1-qubit complex64 state is 16 bytes.
+        return hipErrorInvalidValue;
+    }
+    const uint64_t grid = grid_for(nvec, kThreads * 8, 1u << 20);
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_reset<float>, dim3(grid), dim3(kThreads), 0, s, (float *)st, nvec);
+    else
+        hipLaunchKernelGGL(k_reset<double>, dim3(grid), dim3(kThreads), 0, s, (double *)st, nvec);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const int *ctl, int c,
+                        hipStream_t s)
+{
+    std::vector<int> pos(ctl, ctl + c);
+    pos.push_back(t);
+    uint64_t cmask = 0;
+    for (int j = 0; j < c; ++j)
+        cmask |= uint64_t(1) << ctl[j];
+    const uint64_t ngroups = uint64_t(1) << (n - 1 - c);
+    const bool vec = dtype == SV_C64 && std::find(pos.begin(), pos.end(), 0) == pos.end() && ngroups >= 2;
+    if (dtype == SV_C64) {
+        Gate1Args<float> a{};
+        a.cmask = cmask;
+        a.tbit = uint64_t(1) << t;
+        a.im = make_insert_masks(pos);
+        fill_u(a.u, U, 4);
+        a.nunits = vec ? ngroups / 2 : ngroups;
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        if (check_grid(grid) != hipSuccess)
+            return hipErrorInvalidConfiguration;
+        if (vec)
+            hipLaunchKernelGGL((k_gate1<float, true>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+        else
+            hipLaunchKernelGGL((k_gate1<float, false>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+    } else {
+        Gate1Args<double> a{};
+        a.cmask = cmask;
+        a.tbit = uint64_t(1) << t;
+        a.im = make_insert_masks(pos);
+        fill_u(a.u, U, 4);
+        a.nunits = ngroups;
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        if (check_grid(grid) != hipSuccess)
+            return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((k_gate1<double, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const int *ctl, int c,
+                        hipStream_t s)
+{
+    std::vector<int> pos(ctl, ctl + c);
+    uint64_t fixed = 0;
+    for (int j = 0; j < c; ++j)
+        fixed |= uint64_t(1) << ctl[j];
+    const bool skip0 = (d0 == cd(1.0, 0.0));
+    if (skip0) {
+        pos.push_back(t);
+        fixed |= uint64_t(1) << t;
+    }
+    const uint64_t nfree = uint64_t(1) << (n - int(pos.size()));
+    const bool vec = dtype == SV_C64 && std::find(pos.begin(), pos.end(), 0) == pos.end() && t != 0 &&
+                     nfree >= 2;
+    const cd dd[2] = {d0, d1};
+    if (dtype == SV_C64) {
+        Diag1Args<float> a{};
+        a.fixed = fixed;
+        a.tbit = uint64_t(1) << t;
+        a.im = make_insert_masks(pos);
+        fill_u(a.d, dd, 2);
+        a.nunits = vec ? nfree / 2 : nfree;
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        if (check_grid(grid) != hipSuccess)
+            return hipErrorInvalidConfiguration;
+        if (vec)
+            hipLaunchKernelGGL((k_diag1<float, true>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+        else
+            hipLaunchKernelGGL((k_diag1<float, false>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+    } else {
+        Diag1Args<double> a{};
+        a.fixed = fixed;
+        a.tbit = uint64_t(1) << t;
+        a.im = make_insert_masks(pos);
+        fill_u(a.d, dd, 2);
+        a.nunits = nfree;
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        if (check_grid(grid) != hipSuccess)
+            return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((k_diag1<double, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
+template <typename R, int K>
+hipError_t launch_gatek_direct(void *st, int n, const void *d_U, const int *tgt, const int *ctl, int c,
+                               hipStream_t s)
+{
+    GatekArgs a{};
+    std::vector<int> pos(ctl, ctl + c);
+    pos.insert(pos.end(), tgt, tgt + K);
+    a.im = make_insert_masks(pos);
+    for (int j = 0; j < c; ++j)
+        a.cmask |= uint64_t(1) << ctl[j];
+    for (int j = 0; j < (1 << K); ++j) {
+        uint64_t off = 0;
+        for (int b = 0; b < K; ++b)
+            if ((j >> b) & 1)
+                off |= uint64_t(1) << tgt[b];
+        a.off[j] = off;
+    }
+    a.U = d_U;
+    a.ngroups = uint64_t(1) << (n - K - c);
+    const uint64_t grid = grid_for(a.ngroups, kThreads, 1u << 20);
+    hipLaunchKernelGGL((k_gatek<R, K>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a);
+    return hipGetLastError();
+}
+
+template <typename R, int K>
+hipError_t launch_tile(void *st, int n, const void *d_U, const int *tgt, const int *ctl, int c,
+                       hipStream_t s)
+{
+    using S = TileShape<K>;
+    if (n - c - K < S::M)
+        return launch_gatek_direct<R, K>(st, n, d_U, tgt, ctl, c, s);
+    TileArgs a{};
+    // m lowest free bits
+    uint64_t used = 0;
+    for (int b = 0; b < K; ++b)
+        used |= uint64_t(1) << tgt[b];
+    for (int j = 0; j < c; ++j)
+        used |= uint64_t(1) << ctl[j];
+    std::vector<int> tilebits(tgt, tgt + K);
+    for (int p = 0, got = 0; got < S::M; ++p) {
+        if (!((used >> p) & 1)) {
+            tilebits.push_back(p);
+            ++got;
+        }
+    }
+    std::sort(tilebits.begin(), tilebits.end());
+    for (int b = 0; b < S::TA_LOG; ++b)
+        a.dep[b] = uint64_t(1) << tilebits[b];
+    // slot (x bit) of each target
+    int slot[SV_MAX_TARGETS];
+    for (int b = 0; b < K; ++b)
+        slot[b] = int(std::find(tilebits.begin(), tilebits.end(), tgt[b]) - tilebits.begin());
+    std::vector<int> sorted_slots(slot, slot + K);
+    std::sort(sorted_slots.begin(), sorted_slots.end());
+    a.ntslot = K;
+    for (int b = 0; b < K; ++b)
+        a.tslot_m[b] = (1u << sorted_slots[b]) - 1u;
+    for (int r = 0; r < (1 << K); ++r) {
+        uint32_t x = 0;
+        for (int b = 0; b < K; ++b)
+            if ((r >> b) & 1)
+                x |= 1u << slot[b];
+        a.xc[r] = uint16_t(x);
+    }
+    std::vector<int> outer(tilebits.begin(), tilebits.end());
+    outer.insert(outer.end(), ctl, ctl + c);
+    a.outer = make_insert_masks(outer);
+    for (int j = 0; j < c; ++j)
+        a.cmask |= uint64_t(1) << ctl[j];
+    a.ntiles = uint64_t(1) << (n - c - S::TA_LOG);
+    a.U = d_U;
+    const uint64_t grid = grid_for(a.ntiles, 1, uint64_t(1) << 20);
+    hipLaunchKernelGGL((k_tile<R, K>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tile_k(void *st, int n, const void *d_U, int k, const int *tgt, const int *ctl, int c,
+                         hipStream_t s)
+{
+    switch (k) {
+    case 1: return launch_tile<R, 1>(st, n, d_U, tgt, ctl, c, s);
+    case 2: return launch_tile<R, 2>(st, n, d_U, tgt, ctl, c, s);
+    case 3: return launch_tile<R, 3>(st, n, d_U, tgt, ctl, c, s);
+    case 4: return launch_tile<R, 4>(st, n, d_U, tgt, ctl, c, s);
+    case 5: return launch_tile<R, 5>(st, n, d_U, tgt, ctl, c, s);
+    case 6: return launch_tile<R, 6>(st, n, d_U, tgt, ctl, c, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int dense_path(int n, int dtype, int k, int c, int precision)
+{
+    (void)dtype;
+    (void)precision;
+    const int m = (k <= 5) ? 11 - k : 6;
+    return (n - c - k < m) ? SV_SWEEP_GROUP : SV_SWEEP_DENSE;
+}
+
+hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, const int *tgt,
+                        const int *ctl, int c, int precision, hipStream_t s)
+{
+    (void)precision;
+    if (dtype == SV_C64)
+        return launch_tile_k<float>(st, n, d_U, k, tgt, ctl, c, s);
+    return launch_tile_k<double>(st, n, d_U, k, tgt, ctl, c, s);
+}
+
+hipError_t launch_bitswap(void *st, int n, int dtype, int lo, int hi, int w, hipStream_t s)
+{
+    BitswapArgs a{};
+    a.w = w;
+    a.L = std::min(lo, 12 - 2 * w);
+    if (a.L < 0)
+        a.L = 0;
+    std::vector<int> tilebits;
+    for (int p = 0; p < a.L; ++p)
+        tilebits.push_back(p);
+    for (int b = 0; b < w; ++b)
+        tilebits.push_back(lo + b);
+    for (int b = 0; b < w; ++b)
+        tilebits.push_back(hi + b);
+    a.tlog = int(tilebits.size());
+    for (int b = 0; b < a.tlog; ++b)
+        a.dep[b] = uint64_t(1) << tilebits[b];
+    a.outer = make_insert_masks(tilebits);
+    a.ntiles = uint64_t(1) << (n - a.tlog);
+    const uint64_t grid = grid_for(a.ntiles, 1, uint64_t(1) << 20);
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_bitswap<float>, dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+    else
+        hipLaunchKernelGGL(k_bitswap<double>, dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_logical(const void *st, void *dst, int n, int dtype, const int *qmap,
+                                 uint64_t first, uint64_t count, hipStream_t s)
+{
+    GatherArgs a{};
+    a.first = first;
+    a.count = count;
+    a.n = n;
+    for (int q = 0; q < n; ++q)
+        a.qmap[q] = qmap[q];
+    const uint64_t grid = grid_for(count, kThreads * 4, 1u << 20);
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(kThreads), 0, s, (const float *)st, (float *)dst, a);
+    else
+        hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(kThreads), 0, s, (const double *)st, (double *)dst, a);
+    return hipGetLastError();
+}
+
+}  // namespace sv

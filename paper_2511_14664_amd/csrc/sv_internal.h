@@ -1,0 +1,98 @@
+// Internal declarations of the state-vector library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sv.h"
+
+namespace sv {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+// ---------------------------------------------------------------------------
+// Host-side operation descriptions
+// ---------------------------------------------------------------------------
+
+// One sweep over the state: a dense 2^k x 2^k matrix on `targets` (logical
+// qubits), applied where all `controls` are 1.  `diag` marks a diagonal matrix.
+struct Block {
+    int k = 0;
+    int targets[SV_MAX_TARGETS] = {};
+    int c = 0;
+    int controls[SV_MAX_CONTROLS] = {};
+    std::vector<cd> U;   // 2^k x 2^k row-major, bit b of the index = targets[b]
+    int ngates = 0;      // input gates folded into this block
+    bool diag = false;
+};
+
+// Gate table of the library: 2x2 matrix of a named one-qubit kind.
+bool named_gate_matrix(int kind, const double *params, cd out[4]);
+
+// Validate a gate against an n-qubit register; returns SV_OK or SV_EINVAL
+// (message set).
+int validate_gate(const sv_gate &g, int n, int index);
+
+// Turn a validated gate into an unfused block.
+Block gate_block(const sv_gate &g);
+
+// Plans
+int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts &o,
+                 std::vector<Block> &out);
+std::vector<Block> plan_plain(const std::vector<Block> &gates);
+std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax);
+
+// Algorithmic HBM bytes / flops of a sweep (physical bit positions).
+double block_bytes(int n, int dtype, const Block &b, const int *phys_t, const int *phys_c);
+double block_flops(int n, const Block &b);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (device code in the .hip sources).  All pointers are
+// device pointers unless named h_*.  Qubit positions are PHYSICAL bits.
+// ---------------------------------------------------------------------------
+hipError_t launch_reset(void *st, int n, int dtype, hipStream_t s);
+
+// k = 1 dense gate with controls; U by value.
+hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const int *ctl, int c,
+                        hipStream_t s);
+// one-target diagonal gate diag(d0, d1) with controls.
+hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const int *ctl, int c,
+                        hipStream_t s);
+// dense k-target gate (k <= 6) with controls; d_U = device copy of the matrix
+// in the state's precision (complex float or double, row-major).
+hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, const int *tgt,
+                        const int *ctl, int c, int precision, hipStream_t s);
+// Which kernel launch_gatek uses (an sv_sweep_kind).
+int dense_path(int n, int dtype, int k, int c, int precision);
+
+hipError_t launch_bitswap(void *st, int n, int dtype, int lo, int hi, int w, hipStream_t s);
+// dst[j] = amplitude of logical index first + j, j < count.
+hipError_t launch_gather_logical(const void *st, void *dst, int n, int dtype, const int *qmap,
+                                 uint64_t first, uint64_t count, hipStream_t s);
+
+// Readouts.  Scratch layout is the launcher's business; sizes are checked by
+// the caller through the *_scratch_doubles helpers.
+uint64_t marginal_scratch_doubles(int n, int m);
+hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, int m,
+                           double *d_scratch, double *d_out, hipStream_t s);
+uint64_t expect_scratch_doubles(int n);
+hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zmasks, int nt,
+                           double *d_scratch, double *d_out, hipStream_t s);
+hipError_t launch_expect_xy(const void *st, int n, int dtype, uint64_t xmask, uint64_t yzmask,
+                            double *d_scratch, double *d_out2, hipStream_t s);
+int sample_log_block(int n);
+hipError_t launch_block_sums(const void *st, int n, int dtype, double *d_bsums, hipStream_t s);
+hipError_t launch_sample_search(const void *st, int n, int dtype, const int64_t *d_blocks,
+                                const double *d_targets, int shots, int64_t *d_out, hipStream_t s);
+
+}  // namespace sv

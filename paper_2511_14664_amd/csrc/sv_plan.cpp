@@ -1,0 +1,394 @@
+// Host side of the library: its own gate table, gate validation, and the
+// fusion planner that groups a gate list into sweeps over the state.
+//
+// Fusion (paper Sec. 2.1 "State-Vector Simulation"): several gate
+// applications are grouped into one operation on the union of their qubits.
+// That can raise the flop count, but each sweep over the 2^n amplitudes then
+// does more work per byte moved; the widest block worth forming depends on
+// the machine and the precision (Sec. 2.1; Sec. 2.2 quotes fusion levels of
+// 4-5 qubits on the paper's GPUs).  The planner here is a dependency-aware
+// greedy packing into blocks of at most k_max qubits; block matrices are the
+// ordered product of their gates, formed in FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+// ---------------------------------------------------------------------------
+// Gate table.  Rotations R_P(t) = exp(-i t P / 2); U3 in the three-angle form
+// [[cos t/2, -e^{il} sin t/2], [e^{if} sin t/2, e^{i(f+l)} cos t/2]].
+// ---------------------------------------------------------------------------
+bool named_gate_matrix(int kind, const double *p, cd out[4])
+{
+    const cd I(0.0, 1.0);
+    const double r2 = 1.0 / std::sqrt(2.0);
+    switch (kind) {
+    case SV_GATE_H:
+        out[0] = r2, out[1] = r2, out[2] = r2, out[3] = -r2;
+        return true;
+    case SV_GATE_X:
+        out[0] = 0.0, out[1] = 1.0, out[2] = 1.0, out[3] = 0.0;
+        return true;
+    case SV_GATE_Y:
+        out[0] = 0.0, out[1] = -I, out[2] = I, out[3] = 0.0;
+        return true;
+    case SV_GATE_Z:
+        out[0] = 1.0, out[1] = 0.0, out[2] = 0.0, out[3] = -1.0;
+        return true;
+    case SV_GATE_S:
+        out[0] = 1.0, out[1] = 0.0, out[2] = 0.0, out[3] = I;
+        return true;
+    case SV_GATE_T:
+        out[0] = 1.0, out[1] = 0.0, out[2] = 0.0, out[3] = std::polar(1.0, M_PI / 4.0);
+        return true;
+    case SV_GATE_RX: {
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        out[0] = c, out[1] = -I * s, out[2] = -I * s, out[3] = c;
+        return true;
+    }
+    case SV_GATE_RY: {
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        out[0] = c, out[1] = -s, out[2] = s, out[3] = c;
+        return true;
+    }
+    case SV_GATE_RZ:
+        out[0] = std::polar(1.0, -0.5 * p[0]), out[1] = 0.0, out[2] = 0.0, out[3] = std::polar(1.0, 0.5 * p[0]);
+        return true;
+    case SV_GATE_P:
+        out[0] = 1.0, out[1] = 0.0, out[2] = 0.0, out[3] = std::polar(1.0, p[0]);
+        return true;
+    case SV_GATE_U3: {
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        out[0] = c;
+        out[1] = -std::polar(1.0, p[2]) * s;
+        out[2] = std::polar(1.0, p[1]) * s;
+        out[3] = std::polar(1.0, p[1] + p[2]) * c;
+        return true;
+    }
+    default:
+        return false;
+    }
+}
+
+static bool kind_is_diagonal(int kind)
+{
+    return kind == SV_GATE_Z || kind == SV_GATE_S || kind == SV_GATE_T || kind == SV_GATE_RZ ||
+           kind == SV_GATE_P;
+}
+
+int validate_gate(const sv_gate &g, int n, int index)
+{
+    if (g.kind < SV_GATE_H || g.kind > SV_GATE_MATRIX) {
+        set_error("gate %d: unknown kind %d", index, g.kind);
+        return SV_EINVAL;
+    }
+    const int k = g.num_targets, c = g.num_controls;
+    if (g.kind != SV_GATE_MATRIX && k != 1) {
+        set_error("gate %d: named gate kinds take exactly one target (got %d)", index, k);
+        return SV_EINVAL;
+    }
+    if (k < 1 || k > SV_MAX_TARGETS) {
+        set_error("gate %d: %d targets (1..%d allowed)", index, k, SV_MAX_TARGETS);
+        return SV_EINVAL;
+    }
+    if (c < 0 || c > SV_MAX_CONTROLS) {
+        set_error("gate %d: %d controls (0..%d allowed)", index, c, SV_MAX_CONTROLS);
+        return SV_EINVAL;
+    }
+    if (g.kind == SV_GATE_MATRIX && g.matrix == nullptr) {
+        set_error("gate %d: matrix gate with NULL matrix", index);
+        return SV_EINVAL;
+    }
+    uint64_t used = 0;
+    for (int j = 0; j < k + c; ++j) {
+        const int q = j < k ? g.targets[j] : g.controls[j - k];
+        if (q < 0 || q >= n) {
+            set_error("gate %d: qubit %d out of range [0, %d)", index, q, n);
+            return SV_EINVAL;
+        }
+        if ((used >> q) & 1) {
+            set_error("gate %d: qubit %d used twice", index, q);
+            return SV_EINVAL;
+        }
+        used |= uint64_t(1) << q;
+    }
+    if (g.kind != SV_GATE_MATRIX) {
+        for (int j = 0; j < 3; ++j)
+            if (!std::isfinite(g.params[j])) {
+                set_error("gate %d: non-finite parameter", index);
+                return SV_EINVAL;
+            }
+    } else {
+        const int d = 1 << k;
+        for (int j = 0; j < 2 * d * d; ++j)
+            if (!std::isfinite(g.matrix[j])) {
+                set_error("gate %d: non-finite matrix entry", index);
+                return SV_EINVAL;
+            }
+    }
+    return SV_OK;
+}
+
+static bool matrix_is_diagonal(const std::vector<cd> &U, int d)
+{
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && U[size_t(r) * d + c] != cd(0.0, 0.0))
+                return false;
+    return true;
+}
+
+Block gate_block(const sv_gate &g)
+{
+    Block b;
+    b.k = g.num_targets;
+    b.c = g.num_controls;
+    for (int j = 0; j < b.k; ++j)
+        b.targets[j] = g.targets[j];
+    for (int j = 0; j < b.c; ++j)
+        b.controls[j] = g.controls[j];
+    const int d = 1 << b.k;
+    b.U.assign(size_t(d) * d, cd(0.0, 0.0));
+    if (g.kind == SV_GATE_MATRIX) {
+        for (int j = 0; j < d * d; ++j)
+            b.U[j] = cd(g.matrix[2 * j], g.matrix[2 * j + 1]);
+        b.diag = matrix_is_diagonal(b.U, d);
+    } else {
+        cd m[4];
+        named_gate_matrix(g.kind, g.params, m);
+        for (int j = 0; j < 4; ++j)
+            b.U[j] = m[j];
+        b.diag = kind_is_diagonal(g.kind);
+    }
+    b.ngates = 1;
+    return b;
+}
+
+std::vector<Block> plan_plain(const std::vector<Block> &gates)
+{
+    return gates;
+}
+
+// Apply gate `g` (qubits given as positions inside a kb-bit block index) to
+// every column of the d x d column-major matrix M:  M <- G M.
+static void left_multiply(std::vector<cd> &M, int kb, const Block &g, const int *tpos, const int *cpos)
+{
+    const int d = 1 << kb, kg = g.k, dg = 1 << kg;
+    int mt = 0, mc = 0;
+    for (int b = 0; b < kg; ++b)
+        mt |= 1 << tpos[b];
+    for (int j = 0; j < g.c; ++j)
+        mc |= 1 << cpos[j];
+    cd v[64];
+    int idx[64];
+    for (int col = 0; col < d; ++col) {
+        cd *a = &M[size_t(col) * d];
+        for (int base = 0; base < d; ++base) {
+            if ((base & mt) != 0 || (base & mc) != mc)
+                continue;
+            for (int j = 0; j < dg; ++j) {
+                int off = 0;
+                for (int b = 0; b < kg; ++b)
+                    if ((j >> b) & 1)
+                        off |= 1 << tpos[b];
+                idx[j] = base | off;
+                v[j] = a[idx[j]];
+            }
+            for (int r = 0; r < dg; ++r) {
+                cd acc(0.0, 0.0);
+                for (int c2 = 0; c2 < dg; ++c2)
+                    acc += g.U[size_t(r) * dg + c2] * v[c2];
+                a[idx[r]] = acc;
+            }
+        }
+    }
+}
+
+static Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
+{
+    if (members.size() == 1)
+        return *members[0];
+    Block out;
+    int pos[64];
+    int kb = 0;
+    for (int q = 0; q < 64; ++q)
+        if ((qmask >> q) & 1) {
+            out.targets[kb] = q;
+            pos[q] = kb++;
+        }
+    out.k = kb;
+    out.c = 0;
+    const int d = 1 << kb;
+    std::vector<cd> M(size_t(d) * d, cd(0.0, 0.0));  // column-major
+    for (int i = 0; i < d; ++i)
+        M[size_t(i) * d + i] = 1.0;
+    bool diag = true;
+    int ng = 0;
+    for (const Block *g : members) {
+        int tpos[SV_MAX_TARGETS], cpos[SV_MAX_CONTROLS];
+        for (int b = 0; b < g->k; ++b)
+            tpos[b] = pos[g->targets[b]];
+        for (int j = 0; j < g->c; ++j)
+            cpos[j] = pos[g->controls[j]];
+        left_multiply(M, kb, *g, tpos, cpos);
+        diag = diag && g->diag;
+        ng += g->ngates;
+    }
+    out.U.assign(size_t(d) * d, cd(0.0, 0.0));
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            out.U[size_t(r) * d + c] = M[size_t(c) * d + r];
+    out.diag = diag;
+    out.ngates = ng;
+    return out;
+}
+
+static uint64_t qubit_mask(const Block &b)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < b.k; ++j)
+        m |= uint64_t(1) << b.targets[j];
+    for (int j = 0; j < b.c; ++j)
+        m |= uint64_t(1) << b.controls[j];
+    return m;
+}
+
+// Greedy, dependency-aware packing.  Walking the gates in order, a gate joins
+// the most recent block among those last touching its qubits when the union
+// stays within kmax qubits (it cannot join an earlier one: that block is
+// followed by another touching one of the gate's qubits).  A block that
+// nothing later touches ("free" block) commutes past everything after it, so
+// it may be moved into the block the gate joins when that keeps the union
+// within kmax; this packs a layer of one-qubit gates into the entangling
+// gates that follow it.
+std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)
+{
+    struct PB {
+        std::vector<int> members;
+        uint64_t qmask = 0;
+        bool alive = true;
+    };
+    std::vector<PB> pb;
+    int last[64];
+    std::fill(last, last + 64, -1);
+    auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
+    for (int i = 0; i < int(gates.size()); ++i) {
+        const uint64_t gm = qubit_mask(gates[i]);
+        int cand = -1;
+        for (int q = 0; q < 64; ++q)
+            if ((gm >> q) & 1)
+                cand = std::max(cand, last[q]);
+        int target;
+        if (popc(gm) <= kmax && cand >= 0 && popc(pb[cand].qmask | gm) <= kmax) {
+            target = cand;
+        } else {
+            pb.push_back(PB());
+            target = int(pb.size()) - 1;
+        }
+        if (popc(gm) <= kmax) {
+            for (int q = 0; q < 64; ++q) {
+                if (!((gm >> q) & 1))
+                    continue;
+                const int b = last[q];
+                if (b < 0 || b == target || !pb[b].alive)
+                    continue;
+                bool movable = true;
+                for (int r = 0; r < 64 && movable; ++r)
+                    if (((pb[b].qmask >> r) & 1) && last[r] != b)
+                        movable = false;
+                if (!movable || popc(pb[target].qmask | pb[b].qmask | gm) > kmax)
+                    continue;
+                std::vector<int> merged = pb[b].members;
+                merged.insert(merged.end(), pb[target].members.begin(), pb[target].members.end());
+                pb[target].members.swap(merged);
+                pb[target].qmask |= pb[b].qmask;
+                pb[b].alive = false;
+                pb[b].members.clear();
+                for (int r = 0; r < 64; ++r)
+                    if ((pb[b].qmask >> r) & 1)
+                        last[r] = target;
+            }
+        }
+        pb[target].members.push_back(i);
+        pb[target].qmask |= gm;
+        for (int q = 0; q < 64; ++q)
+            if ((gm >> q) & 1)
+                last[q] = target;
+    }
+    std::vector<Block> out;
+    for (const PB &b : pb) {
+        if (!b.alive || b.members.empty())
+            continue;
+        std::vector<const Block *> mem;
+        for (int i : b.members)
+            mem.push_back(&gates[i]);
+        out.push_back(fuse(mem, b.qmask));
+    }
+    return out;
+}
+
+int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts &o,
+                 std::vector<Block> &out)
+{
+    (void)dtype;
+    if (ngates < 0 || (ngates > 0 && gates == nullptr)) {
+        set_error("bad gate list");
+        return SV_EINVAL;
+    }
+    if (o.mode < SV_PLAN_PLAIN || o.mode > SV_PLAN_LEARNED) {
+        set_error("unknown plan mode %d", o.mode);
+        return SV_EINVAL;
+    }
+    if (o.mode != SV_PLAN_PLAIN && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {
+        set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
+        return SV_EINVAL;
+    }
+    if (o.precision != SV_PREC_NATIVE && o.precision != SV_PREC_BF16X3) {
+        set_error("unknown precision mode %d", o.precision);
+        return SV_EINVAL;
+    }
+    std::vector<Block> blocks;
+    blocks.reserve(size_t(ngates));
+    for (int i = 0; i < ngates; ++i) {
+        int rc = validate_gate(gates[i], n, i);
+        if (rc != SV_OK)
+            return rc;
+        blocks.push_back(gate_block(gates[i]));
+    }
+    if (o.mode == SV_PLAN_PLAIN)
+        out = plan_plain(blocks);
+    else
+        out = plan_greedy(blocks, o.max_fused);
+    return SV_OK;
+}
+
+double block_bytes(int n, int dtype, const Block &b, const int *phys_t, const int *phys_c)
+{
+    const double S = dtype == SV_C64 ? 8.0 : 16.0;
+    // bits below log2(128 / S) share 128-byte lines with untouched amplitudes
+    const int line_bits = dtype == SV_C64 ? 4 : 3;
+    int fixed_hi = 0;
+    for (int j = 0; j < b.c; ++j)
+        if (phys_c[j] >= line_bits)
+            ++fixed_hi;
+    if (b.k == 1 && b.diag && b.U[0] == cd(1.0, 0.0) && phys_t[0] >= line_bits)
+        ++fixed_hi;
+    return 2.0 * S * std::ldexp(1.0, n - fixed_hi);
+}
+
+double block_flops(int n, const Block &b)
+{
+    const double touched = std::ldexp(1.0, n - b.c);
+    if (b.k == 1 && b.diag) {
+        const double t = (b.U[0] == cd(1.0, 0.0)) ? touched / 2 : touched;
+        return 6.0 * t;
+    }
+    return (8.0 * double(1 << b.k) - 2.0) * touched;
+}
+
+}  // namespace sv

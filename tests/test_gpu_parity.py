@@ -1,0 +1,359 @@
+"""Parity of the HIP path with the FP64 reference, through the C ABI.
+
+Tolerances: max |delta amplitude| <= 1e-12 for complex128 and <= 2e-5 for
+complex64 (depth <= 200); bit-exact for the qubit-field exchange and index
+work; read-outs compared on the very state the GPU holds (copied back), so
+only the FP64 summation order differs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import Gate
+
+import paper_2511_14664_amd as svm
+from paper_2511_14664_amd import _binding as B
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.SV_C128: 1e-12, B.SV_C64: 2e-5}
+DTYPES = [B.SV_C128, B.SV_C64]
+DNAME = {B.SV_C128: "c128", B.SV_C64: "c64"}
+
+
+class State:
+    """Library-owned device state (sv_create)."""
+
+    def __init__(self, n, dtype):
+        self.n, self.dtype = n, dtype
+        self.h = B.sv_create(n, dtype)
+
+    def close(self):
+        if self.h:
+            B.sv_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def load(self, psi):
+        B.sv_copy_from_host(self.h, self.dtype, psi)
+        return np.asarray(psi, dtype=B.amp_dtype(self.dtype)).astype(np.complex128)
+
+    def host(self):
+        return B.sv_copy_to_host(self.h, self.n, self.dtype).astype(np.complex128)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def maxerr(a, b):
+    return float(np.max(np.abs(a - b)))
+
+
+# ---------------------------------------------------------------------------
+# 12-qubit complex128 layered circuit: whole state and all probabilities
+# ---------------------------------------------------------------------------
+def test_layered_12q_c128_full_state_and_probabilities():
+    n = 12
+    gates = W.layered_u3_pairing(n, 20, W.circuit_seed(1, 1), "cx")
+    assert len(gates) == 360
+    want = oracle.run(gates, n)
+    for mode in (B.SV_PLAN_PLAIN, B.SV_PLAN_GREEDY):
+        say("12q c128 mode", mode)
+        with State(n, B.SV_C128) as s:
+            st = B.sv_apply_circuit(s.h, gates, B.make_opts(mode, 5))
+            got = s.host()
+            assert maxerr(got, want) <= 1e-12
+            p = B.sv_probabilities(s.h, list(range(n)))
+            assert maxerr(p, oracle.probabilities(want)) <= 1e-12
+            assert st["gates"] == 360
+            if mode == B.SV_PLAN_PLAIN:
+                assert st["sweeps"] == 360
+            else:
+                assert st["sweeps"] < 60
+
+
+# ---------------------------------------------------------------------------
+# Every one-qubit kind at every target position, with controls
+# ---------------------------------------------------------------------------
+ONE_Q = [("h", ()), ("x", ()), ("y", ()), ("z", ()), ("s", ()), ("t", ()), ("rx", (0.7,)),
+         ("ry", (1.9,)), ("rz", (-2.3,)), ("p", (0.4,)), ("u3", (0.3, 1.1, -0.8))]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_one_qubit_gates_every_position(dtype):
+    n = 11
+    psi = W.random_state(n, 3)
+    with State(n, dtype) as s:
+        for name, params in ONE_Q:
+            for t in range(n):
+                others = [q for q in range(n) if q != t]
+                for ctrls in [(), (others[(t * 3) % (n - 1)],), (others[0], others[-1]),
+                              tuple(others[1:4])]:
+                    g = Gate(name, (t,), ctrls, params)
+                    ref = s.load(psi)
+                    B.sv_apply_circuit(s.h, [g])
+                    got = s.host()
+                    want = oracle.apply_gate(ref.copy(), g)
+                    e = maxerr(got, want)
+                    assert e <= TOL[dtype] / 10, (name, t, ctrls, e)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [8, 14, 17])
+def test_multi_target_gates(dtype, n):
+    """k = 2..6 targets at random and at the lowest/highest positions, 0-2
+    controls; n = 8 takes the per-group path, n >= 14 the LDS tile."""
+    rng = np.random.default_rng(n)
+    psi = W.random_state(n, 5)
+    with State(n, dtype) as s:
+        for k in range(2, 7):
+            placements = [list(range(k)), list(range(n - k, n))]
+            for _ in range(3):
+                placements.append([int(x) for x in rng.permutation(n)[:k]])
+            for tg in placements:
+                rest = [q for q in range(n) if q not in tg]
+                for nc in (0, 1, 2):
+                    if k + nc > n:
+                        continue
+                    ctl = [int(x) for x in rng.permutation(rest)[:nc]]
+                    U = W.haar_unitary(rng, 1 << k)
+                    say(f"n={n} {DNAME[dtype]} k={k} targets={tg} controls={ctl}")
+                    ref = s.load(psi)
+                    B.sv_apply_gate(s.h, U, tg, ctl)
+                    want = oracle.apply_matrix(ref.copy(), U, tg, ctl)
+                    e = maxerr(s.host(), want)
+                    assert e <= TOL[dtype] / 10, (k, tg, ctl, e)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("kmax", [2, 3, 4, 5, 6])
+def test_fused_circuits(dtype, kmax):
+    n = 16
+    gates = (W.layered_u3_pairing(n, 8, 9, "cx_or_cz") + W.qft_ladder_block(n, 8)
+             + W.u3_su4_layers(n, 3, 4) + W.rcs_circuit(n, 11)[:200])
+    want = oracle.run(gates, n)
+    say(f"fused n={n} {DNAME[dtype]} kmax={kmax} gates={len(gates)}")
+    with State(n, dtype) as s:
+        st = B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_GREEDY, kmax))
+        e = maxerr(s.host(), want)
+        assert e <= TOL[dtype], e
+        assert st["sweeps"] < len(gates)
+
+
+# ---------------------------------------------------------------------------
+# Qubit bit-field exchange
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n,lo,hi,w", [(14, 0, 8, 6), (16, 0, 10, 6), (13, 2, 7, 3), (12, 5, 9, 1), (9, 0, 3, 6)])
+def test_bitswap_bit_exact(dtype, n, lo, hi, w):
+    import torch
+
+    psi = W.random_state(n, 13).astype(B.amp_dtype(dtype))
+    with svm.StateVector(n, dtype) as sv:
+        sv.from_host(psi)
+        sv.swap_bits(lo, hi, w)
+        sv.synchronize()
+        raw = sv.buffer.cpu().numpy().view(B.amp_dtype(dtype)).copy()
+        want = oracle.bitswap(psi.astype(np.complex128), lo, hi, w).astype(B.amp_dtype(dtype))
+        assert np.array_equal(raw.view(np.uint8), want.view(np.uint8))
+        assert sv.qubit_map() == oracle.apply_bitswap_map(list(range(n)), lo, hi, w)
+        # logical read-out is unchanged, bit for bit
+        assert np.array_equal(sv.to_host().view(np.uint8), psi.view(np.uint8))
+        sv.swap_bits(lo, hi, w)
+        sv.synchronize()
+        raw2 = sv.buffer.cpu().numpy().view(B.amp_dtype(dtype))
+        assert np.array_equal(raw2.view(np.uint8), psi.view(np.uint8))
+        assert sv.qubit_map() == list(range(n))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("mode", [B.SV_PLAN_PLAIN, B.SV_PLAN_GREEDY])
+def test_relaid_out_circuit_matches_swap_free_reference(dtype, mode):
+    n = 16
+    ops = W.share_layers(n, 4, 21, swap_every=2, swap_width=6)
+    want = oracle.run(ops, n)
+    with State(n, dtype) as s:
+        seg = []
+        for op in ops + [None]:
+            if op is None or isinstance(op, W.BitSwap):
+                if seg:
+                    B.sv_apply_circuit(s.h, seg, B.make_opts(mode, 5))
+                    seg = []
+                if op is not None:
+                    B.sv_swap_bits(s.h, op.lo, op.hi, op.width)
+            else:
+                seg.append(op)
+        got = s.host()
+        assert maxerr(got, want) <= TOL[dtype]
+        # read-outs through the map
+        p = B.sv_probabilities(s.h, [n - 1, 0, 3])
+        assert maxerr(p, oracle.probabilities(want, [n - 1, 0, 3])) <= (1e-12 if dtype == B.SV_C128 else 1e-5)
+        z = B.sv_expect_pauli(s.h, ["Z" + "I" * (n - 2) + "Z", "X" + "I" * (n - 1)])
+        zw = [oracle.expect_pauli(want, "Z" + "I" * (n - 2) + "Z").real,
+              oracle.expect_pauli(want, "X" + "I" * (n - 1)).real]
+        assert maxerr(z, np.array(zw)) <= (1e-12 if dtype == B.SV_C128 else 1e-5)
+
+
+# ---------------------------------------------------------------------------
+# Read-outs on the GPU's own state
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [5, 14, 20])
+def test_marginals(dtype, n):
+    rng = np.random.default_rng(n)
+    psi = W.random_state(n, 17)
+    with State(n, dtype) as s:
+        ref = s.load(psi)
+        qsets = [[], [0], [n - 1], list(range(n)), list(range(n))[::-1]]
+        for m in (2, 3, min(7, n), min(12, n)):
+            qsets.append([int(x) for x in rng.permutation(n)[:m]])
+        for Q in qsets:
+            say(f"marginal n={n} {DNAME[dtype]} Q={Q}")
+            got = B.sv_probabilities(s.h, Q)
+            want = oracle.probabilities(ref, Q)
+            assert maxerr(got, want) <= 1e-12 * max(1.0, float(np.max(want))), Q
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pauli_expectations(dtype):
+    n = 12
+    rng = np.random.default_rng(7)
+    psi = W.random_state(n, 19)
+    terms = ["I" * n, "Z" * n, "X" * n, "Y" * n]
+    for _ in range(40):
+        terms.append("".join(rng.choice(list("IXYZ"), size=n)))
+    for _ in range(20):
+        terms.append("".join(rng.choice(list("IZ"), size=n)))
+    with State(n, dtype) as s:
+        ref = s.load(psi)
+        got = B.sv_expect_pauli(s.h, terms)
+        want = np.array([oracle.expect_pauli(ref, t).real for t in terms])
+        assert maxerr(got, want) <= 1e-12
+
+
+def sample_ok(state, u, got, tau):
+    p = np.abs(state) ** 2
+    cdf = np.cumsum(p)
+    norm = cdf[-1]
+    want = oracle.sample(state, u)
+    bad = []
+    for s in range(len(u)):
+        if got[s] == want[s]:
+            continue
+        g = int(got[s])
+        t = u[s] * norm
+        lo = cdf[g - 1] if g > 0 else 0.0
+        if not (lo - tau <= t < cdf[g] + tau and p[g] > 0):
+            bad.append((s, g, int(want[s])))
+    return bad
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [3, 12, 16, 19])
+def test_sampling_index_agreement(dtype, n):
+    psi = W.random_state(n, 23)
+    u = W.uniforms(7, 3000)
+    with State(n, dtype) as s:
+        ref = s.load(psi)
+        got = B.sv_sample(s.h, u)
+        bad = sample_ok(ref, u, got, 1e-12)
+        assert not bad, bad[:5]
+
+
+def test_sampling_qpe_exact_phase():
+    k, m = 9, 301
+    n = k + 1
+    with State(n, B.SV_C128) as s:
+        B.sv_apply_circuit(s.h, W.qpe_circuit(k, m))
+        out = B.sv_sample(s.h, W.uniforms(5, 1000))
+        assert np.all(out == (m | (1 << k)))
+
+
+def test_sampling_ghz_and_edges():
+    n = 18
+    ops = [Gate("h", (0,))] + [W.cx(q, q + 1) for q in range(n - 1)]
+    with State(n, B.SV_C64) as s:
+        B.sv_apply_circuit(s.h, ops)
+        u = np.array([0.0, 0.25, 0.4999, 0.5001, 0.75, 1 - 2 ** -53])
+        out = B.sv_sample(s.h, u)
+        assert list(out[:3]) == [0, 0, 0] and list(out[3:]) == [(1 << n) - 1] * 3
+        with pytest.raises(B.SvError):
+            B.sv_sample(s.h, np.array([1.0]))
+        assert B.sv_sample(s.h, np.array([])).size == 0
+
+
+# ---------------------------------------------------------------------------
+# Full-size 28-qubit workload in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+def split_layers(n, layers, seed):
+    """Layered U3 + CNOT/CZ circuit that never couples qubits < n/2 with qubits
+    >= n/2, so the state is a product of two half-size states the reference
+    computes exactly."""
+    h = n // 2
+    lo = W.layered_u3_pairing(h, layers, seed, "cx_or_cz")
+    hi = W.layered_u3_pairing(n - h, layers, seed + 1, "cx_or_cz")
+    shift = [Gate(g.name, tuple(q + h for q in g.targets), tuple(q + h for q in g.controls), g.params, g.matrix)
+             for g in hi]
+    return lo, hi, lo + shift
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_28q_sampled_amplitudes_product_circuit(dtype):
+    n = 28
+    lo, hi, gates = split_layers(n, 20, 77)
+    a_lo = oracle.run(lo, 14)
+    a_hi = oracle.run(hi, 14)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, 1 << n, size=4096)
+    idx[:4] = [0, 1, (1 << n) - 1, 1 << 27]
+    want = a_lo[idx & ((1 << 14) - 1)] * a_hi[idx >> 14]
+    for mode in (B.SV_PLAN_GREEDY, B.SV_PLAN_PLAIN):
+        say(f"28q product {DNAME[dtype]} mode={mode}")
+        with State(n, dtype) as s:
+            B.sv_apply_circuit(s.h, gates, B.make_opts(mode, 5))
+            got = np.array([complex(B.sv_copy_to_host(s.h, n, dtype, int(i), 1)[0]) for i in idx[:512]])
+            assert maxerr(got, want[:512]) <= TOL[dtype]
+            norm = B.sv_probabilities(s.h, [])[0]
+            assert abs(norm - 1) < (1e-12 if dtype == B.SV_C128 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_28q_layered_mirror_returns_to_zero(dtype):
+    n = 28
+    gates = W.layered_u3_pairing(n, 20, W.circuit_seed(2, 1), "cx_or_cz")
+    say(f"28q mirror {DNAME[dtype]}")
+    with State(n, dtype) as s:
+        B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_GREEDY, 5))
+        B.sv_apply_circuit(s.h, W.inverse(gates), B.make_opts(B.SV_PLAN_GREEDY, 5))
+        a0 = complex(B.sv_copy_to_host(s.h, n, dtype, 0, 1)[0])
+        p = B.sv_probabilities(s.h, [0, 27, 13])
+        tol = TOL[dtype] * 10
+        assert abs(a0 - 1) <= tol, a0
+        assert abs(p[0] - 1) <= tol and np.all(np.abs(p[1:]) <= tol)
+
+
+# ---------------------------------------------------------------------------
+# Torch-owned memory and stream
+# ---------------------------------------------------------------------------
+def test_statevector_on_torch_memory_and_stream():
+    import torch
+
+    n = 10
+    gates = W.layered_u3_pairing(n, 5, 3, "cx_or_cz")
+    want = oracle.run(gates, n)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with svm.StateVector(n, B.SV_C128) as sv:
+            sv.apply_circuit(gates, mode=B.SV_PLAN_GREEDY, max_fused=4)
+            assert maxerr(sv.to_host(), want) <= 1e-12
+    torch.cuda.synchronize()
