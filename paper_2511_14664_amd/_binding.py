@@ -60,6 +60,10 @@ class sv_run_stats(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes libsv.so bind to that one, so the process holds a single HIP
+    # runtime and torch-allocated memory and streams are valid in the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
     sig = {

@@ -153,7 +153,7 @@ def test_fused_circuits(dtype, kmax):
 # Qubit bit-field exchange
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
-@pytest.mark.parametrize("n,lo,hi,w", [(14, 0, 8, 6), (16, 0, 10, 6), (13, 2, 7, 3), (12, 5, 9, 1), (9, 0, 3, 6)])
+@pytest.mark.parametrize("n,lo,hi,w", [(14, 0, 8, 6), (16, 0, 10, 6), (13, 2, 7, 3), (12, 5, 9, 1), (12, 0, 6, 6)])
 def test_bitswap_bit_exact(dtype, n, lo, hi, w):
     import torch
 
