@@ -14,6 +14,7 @@ ARCH = os.environ.get("SV_OFFLOAD_ARCH", "gfx950")
 SOURCES = [
     "sv_gates.hip",
     "sv_readout.hip",
+    "sv_fused_mfma.hip",
     "sv_plan.cpp",
     "sv_api.cpp",
 ]

@@ -9,78 +9,18 @@
 // tile for the multi-target case so that every global access is contiguous
 // whatever the target bits are.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
+#include "sv_device.h"
 #include "sv_internal.h"
 
 namespace sv {
 namespace {
 
-constexpr int kThreads = 256;
+using namespace dev;
+
 constexpr int kItems = 4;
-constexpr int kMaxIns = SV_MAX_TARGETS + SV_MAX_CONTROLS;
-
-template <typename R>
-struct CT;
-template <>
-struct CT<float> {
-    using C = float2;
-};
-template <>
-struct CT<double> {
-    using C = double2;
-};
-
-// Insert a 0 bit at each of up to kMaxIns sorted positions: m[j] = 2^p_j - 1.
-struct InsertMasks {
-    uint64_t m[kMaxIns];
-    int n;
-};
-
-InsertMasks make_insert_masks(std::vector<int> pos)
-{
-    std::sort(pos.begin(), pos.end());
-    InsertMasks im{};
-    im.n = static_cast<int>(pos.size());
-    for (int j = 0; j < im.n; ++j)
-        im.m[j] = (uint64_t(1) << pos[j]) - 1;
-    return im;
-}
-
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const InsertMasks &im)
-{
-    for (int j = 0; j < im.n; ++j) {
-        const uint64_t lo = im.m[j];
-        g = (g & lo) | ((g & ~lo) << 1);
-    }
-    return g;
-}
-
-template <typename C>
-__device__ __forceinline__ C cmad(C u, C v, C acc)
-{
-    acc.x += u.x * v.x - u.y * v.y;
-    acc.y += u.x * v.y + u.y * v.x;
-    return acc;
-}
-
-template <typename C>
-__device__ __forceinline__ C cmul(C u, C v)
-{
-    C r;
-    r.x = u.x * v.x - u.y * v.y;
-    r.y = u.x * v.y + u.y * v.x;
-    return r;
-}
-
-template <typename C>
-__device__ __forceinline__ C czero()
-{
-    C r;
-    r.x = 0;
-    r.y = 0;
-    return r;
-}
 
 hipError_t check_grid(uint64_t blocks)
 {
@@ -309,22 +249,6 @@ struct TileShape {
     static constexpr int GCH = (1 << M) / 64;
 };
 
-struct TileArgs {
-    uint64_t ntiles;
-    uint64_t cmask;
-    InsertMasks outer;     // zeros at tile bits and control bits
-    uint64_t dep[12];      // dep[b] = 2^(physical position of tile bit b)
-    uint32_t tslot_m[SV_MAX_TARGETS];  // insert masks of the target slots in x
-    int ntslot;
-    uint16_t xc[64];       // x bits of target-row index r
-    const void *U;
-};
-
-__device__ __forceinline__ uint32_t swz(uint32_t x)
-{
-    return x ^ ((x >> 6) & 63u);
-}
-
 template <typename R, int K>
 __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const TileArgs a)
 {
@@ -332,17 +256,10 @@ __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const Til
     using S = TileShape<K>;
     constexpr int D = 1 << K;
     __shared__ C tile[S::TA];
-    C *v = reinterpret_cast<C *>(st);
     const C *U = reinterpret_cast<const C *>(a.U);
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-
-    uint64_t off_lo = 0;
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-        if ((tid >> b) & 1)
-            off_lo |= a.dep[b];
 
     uint32_t xg[S::PAIRS];
     int rb[S::PAIRS];
@@ -350,27 +267,10 @@ __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const Til
     for (int j = 0; j < S::PAIRS; ++j) {
         const int p = wave + 4 * j;
         rb[j] = p / S::GCH;
-        uint32_t g = uint32_t((p % S::GCH) * 64 + lane);
-        for (int s = 0; s < a.ntslot; ++s) {
-            const uint32_t lo = a.tslot_m[s];
-            g = (g & lo) | ((g & ~lo) << 1);
-        }
-        xg[j] = g;
+        xg[j] = group_slot(uint32_t((p % S::GCH) * 64 + lane), a);
     }
 
-    for (uint64_t o = blockIdx.x; o < a.ntiles; o += gridDim.x) {
-        const uint64_t base = insert_zeros(o, a.outer) | a.cmask;
-#pragma unroll
-        for (int s = 0; s < S::OPT; ++s) {
-            uint64_t off = off_lo;
-#pragma unroll
-            for (int b = 8; b < S::TA_LOG; ++b)
-                if ((s >> (b - 8)) & 1)
-                    off |= a.dep[b];
-            tile[swz(uint32_t(s * kThreads + tid))] = v[base + off];
-        }
-        __syncthreads();
-
+    tile_pipeline<R, S::TA_LOG>(st, a, tile, [&](C *t) {
         C acc[S::PAIRS][S::RB];
 #pragma unroll
         for (int j = 0; j < S::PAIRS; ++j) {
@@ -379,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const Til
                 acc[j][rr] = czero<C>();
             const C *Ur = U + size_t(rb[j]) * S::RB * D;
             for (int col = 0; col < D; ++col) {
-                const C x = tile[swz(uint32_t(a.xc[col]) | xg[j])];
+                const C x = t[swz(uint32_t(a.xc[col]) | xg[j])];
 #pragma unroll
                 for (int rr = 0; rr < S::RB; ++rr)
                     acc[j][rr] = cmad(Ur[rr * D + col], x, acc[j][rr]);
@@ -390,19 +290,9 @@ __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const Til
         for (int j = 0; j < S::PAIRS; ++j)
 #pragma unroll
             for (int rr = 0; rr < S::RB; ++rr)
-                tile[swz(uint32_t(a.xc[rb[j] * S::RB + rr]) | xg[j])] = acc[j][rr];
+                t[swz(uint32_t(a.xc[rb[j] * S::RB + rr]) | xg[j])] = acc[j][rr];
         __syncthreads();
-#pragma unroll
-        for (int s = 0; s < S::OPT; ++s) {
-            uint64_t off = off_lo;
-#pragma unroll
-            for (int b = 8; b < S::TA_LOG; ++b)
-                if ((s >> (b - 8)) & 1)
-                    off |= a.dep[b];
-            v[base + off] = tile[swz(uint32_t(s * kThreads + tid))];
-        }
-        __syncthreads();
-    }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -499,14 +389,6 @@ void fill_u(R *dst, const cd *src, int count)
         dst[2 * i] = R(src[i].real());
         dst[2 * i + 1] = R(src[i].imag());
     }
-}
-
-uint64_t grid_for(uint64_t work, uint64_t per_block, uint64_t cap)
-{
-    uint64_t b = (work + per_block - 1) / per_block;
-    if (b < 1)
-        b = 1;
-    return b > cap ? cap : b;
 }
 
 }  // namespace
@@ -647,47 +529,9 @@ hipError_t launch_tile(void *st, int n, const void *d_U, const int *tgt, const i
     using S = TileShape<K>;
     if (n - c - K < S::M)
         return launch_gatek_direct<R, K>(st, n, d_U, tgt, ctl, c, s);
-    TileArgs a{};
-    // m lowest free bits
-    uint64_t used = 0;
-    for (int b = 0; b < K; ++b)
-        used |= uint64_t(1) << tgt[b];
-    for (int j = 0; j < c; ++j)
-        used |= uint64_t(1) << ctl[j];
-    std::vector<int> tilebits(tgt, tgt + K);
-    for (int p = 0, got = 0; got < S::M; ++p) {
-        if (!((used >> p) & 1)) {
-            tilebits.push_back(p);
-            ++got;
-        }
-    }
-    std::sort(tilebits.begin(), tilebits.end());
-    for (int b = 0; b < S::TA_LOG; ++b)
-        a.dep[b] = uint64_t(1) << tilebits[b];
-    // slot (x bit) of each target
-    int slot[SV_MAX_TARGETS];
-    for (int b = 0; b < K; ++b)
-        slot[b] = int(std::find(tilebits.begin(), tilebits.end(), tgt[b]) - tilebits.begin());
-    std::vector<int> sorted_slots(slot, slot + K);
-    std::sort(sorted_slots.begin(), sorted_slots.end());
-    a.ntslot = K;
-    for (int b = 0; b < K; ++b)
-        a.tslot_m[b] = (1u << sorted_slots[b]) - 1u;
-    for (int r = 0; r < (1 << K); ++r) {
-        uint32_t x = 0;
-        for (int b = 0; b < K; ++b)
-            if ((r >> b) & 1)
-                x |= 1u << slot[b];
-        a.xc[r] = uint16_t(x);
-    }
-    std::vector<int> outer(tilebits.begin(), tilebits.end());
-    outer.insert(outer.end(), ctl, ctl + c);
-    a.outer = make_insert_masks(outer);
-    for (int j = 0; j < c; ++j)
-        a.cmask |= uint64_t(1) << ctl[j];
-    a.ntiles = uint64_t(1) << (n - c - S::TA_LOG);
-    a.U = d_U;
-    const uint64_t grid = grid_for(a.ntiles, 1, uint64_t(1) << 20);
+    TileArgs a = make_tile_args(n, K, tgt, ctl, c, S::TA_LOG, d_U);
+    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_tile<R, K>), ~uint64_t(0) >> 1);
+    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
     hipLaunchKernelGGL((k_tile<R, K>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a);
     return hipGetLastError();
 }
@@ -711,8 +555,14 @@ hipError_t launch_tile_k(void *st, int n, const void *d_U, int k, const int *tgt
 
 int dense_path(int n, int dtype, int k, int c, int precision)
 {
-    (void)dtype;
     (void)precision;
+    static const bool no_mfma = [] {
+        const char *e = getenv("SV_NO_MFMA");
+        return e && *e && *e != '0';
+    }();
+    const int tl = mfma_tile_log(dtype, k);
+    if (!no_mfma && tl > 0 && n - c >= tl)
+        return SV_SWEEP_DENSE_MFMA;
     const int m = (k <= 5) ? 11 - k : 6;
     return (n - c - k < m) ? SV_SWEEP_GROUP : SV_SWEEP_DENSE;
 }
@@ -720,7 +570,8 @@ int dense_path(int n, int dtype, int k, int c, int precision)
 hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, const int *tgt,
                         const int *ctl, int c, int precision, hipStream_t s)
 {
-    (void)precision;
+    if (dense_path(n, dtype, k, c, precision) == SV_SWEEP_DENSE_MFMA)
+        return launch_dense_mfma(st, n, dtype, d_U, k, tgt, ctl, c, s);
     if (dtype == SV_C64)
         return launch_tile_k<float>(st, n, d_U, k, tgt, ctl, c, s);
     return launch_tile_k<double>(st, n, d_U, k, tgt, ctl, c, s);

@@ -72,6 +72,10 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
 // in the state's precision (complex float or double, row-major).
 hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, const int *tgt,
                         const int *ctl, int c, int precision, hipStream_t s);
+// Matrix-core path for k = 4..6 (tile of 2^mfma_tile_log amplitudes, -1 if none).
+int mfma_tile_log(int dtype, int k);
+hipError_t launch_dense_mfma(void *st, int n, int dtype, const void *d_U, int k, const int *tgt, const int *ctl,
+                             int c, hipStream_t s);
 // Which kernel launch_gatek uses (an sv_sweep_kind).
 int dense_path(int n, int dtype, int k, int c, int precision);
 
