@@ -30,6 +30,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["layered", "share", "batch"], default="layered",
+                    help="layered: 28-qubit random layered circuit (the headline line); share: 34q complex128 / "
+                         "35q complex64 share with 6-bit exchanges every 2 layers; batch: 512 HEA circuits "
+                         "of 10..22 qubits in one graph launch vs one launch per gate")
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--mode", choices=["plain", "greedy", "learned"], default="greedy")
@@ -65,6 +69,10 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "share":
+        return bench_share(args)
     n = args.qubits
     dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
     S = 8 if dtype == B.SV_C64 else 16
@@ -226,6 +234,127 @@ def main():
     }
     print(json.dumps(out), flush=True)
     sv.close()
+
+
+def bench_share(args):
+    """34q complex128 or 35q complex64 share: 10 layers (QFT ladder on the top 8
+    qubits, U3 on every qubit, CNOT matching) with the top 6 index bits exchanged
+    with the lowest 6 after every 2 layers."""
+    import torch
+
+    import workloads as W
+    from paper_2511_14664_amd import _binding as B
+
+    dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
+    n = 35 if dtype == B.SV_C64 else 34
+    ops = W.share_layers(n, 10, W.circuit_seed(3, 1))
+    segs, seg = [], []
+    for op in ops:
+        if isinstance(op, W.BitSwap):
+            segs.append((B.Circuit(seg), op))
+            seg = []
+        else:
+            seg.append(op)
+    if seg:
+        segs.append((B.Circuit(seg), None))
+    mode = B.SV_PLAN_PLAIN if args.mode == "plain" else B.SV_PLAN_GREEDY
+    opts = B.make_opts(mode, args.max_fused)
+    torch.cuda.empty_cache()
+    h = B.sv_create(n, dtype)
+    ngates = W.gate_count(ops)
+
+    def step():
+        B.sv_reset(h)
+        sweeps = 0
+        for circ, sw in segs:
+            sweeps += B.sv_apply_circuit(h, circ, opts)["sweeps"]
+            if sw is not None:
+                B.sv_swap_bits(h, sw.lo, sw.hi, sw.width)
+        B.sv_probabilities(h, list(range(n - 10, n)))
+        B.sv_sample(h, W.uniforms(7, 1000))
+        return sweeps
+
+    log(f"share: {n} qubits {args.dtype}, {ngates} gates, mode {args.mode}")
+    for _ in range(args.warmup):
+        step()
+    B.sv_profile_read(h)
+    B.sv_profile_enable(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sweeps = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.sv_profile_enable(h, False)
+    recs = B.sv_profile_read(h, 1 << 18)
+    B.sv_destroy(h)
+    ms = (t1 - t0) * 1e3 / args.steps
+    kb = sum(r["bytes"] for r in recs) / args.steps
+    kms = sum(r["ms"] for r in recs) / args.steps
+    swp = [r for r in recs if r["kind_name"] == "bitswap"]
+    out = {"workload": f"{n}-qubit {args.dtype} share, 10 layers + 5 exchanges, {args.mode}",
+           "ms_per_step": round(ms, 2), "gate_apps_per_s": round(ngates / (ms / 1e3), 2),
+           "sweeps_per_step": sweeps, "kernel_GB/s": round(kb / (kms / 1e3) / 1e9, 1),
+           "exchange_GB/s": round(sum(r["bytes"] for r in swp) / (sum(r["ms"] for r in swp) / 1e3) / 1e9, 1)
+           if swp else None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """512 hardware-efficient-ansatz circuits, 10..22 qubits, depth 8: one
+    graph-captured persistent launch vs one launch per gate."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2511_14664_amd import _binding as B
+
+    dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
+    hb = W.hea_batch(512, 10, 22, 8, W.circuit_seed(4, 1))
+    circs = [hb.circuit(i) for i in range(512)]
+    qs = [int(q) for q in hb.qubits]
+    masks = [[1 << i for i in range(q)] + [3 << i for i in range(q - 1)] for q in qs]
+    bt = B.Batch(circs, qs, masks)
+    h = B.sv_batch_create(dtype, bt)
+    t0 = time.perf_counter()
+    cfg = B.sv_batch_tune(h, 2)
+    tune_s = time.perf_counter() - t0
+    log(f"batch: tuned config {cfg} in {tune_s:.1f} s")
+    for _ in range(args.warmup):
+        B.sv_batch_run(h, bt)
+    walls, gms = [], []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        res = B.sv_batch_run(h, bt)
+        walls.append(time.perf_counter() - t0)
+        gms.append(B.sv_batch_last_ms(h))
+    B.sv_batch_destroy(h)
+    wall_ms = 1e3 * float(np.median(walls))
+    # baseline: every circuit on its own state, one launch per gate, then its read-out
+    zterms = [W.hea_z_terms(q) for q in qs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base = []
+    states = {}
+    for i in range(512):
+        q = qs[i]
+        if q not in states:
+            states[q] = B.sv_create(q, dtype)
+        s = states[q]
+        B.sv_reset(s)
+        B.sv_apply_circuit(s, bt.circs[i], B.make_opts(B.SV_PLAN_PLAIN))
+        base.append(B.sv_expect_pauli(s, zterms[i]))
+    torch.cuda.synchronize()
+    base_ms = (time.perf_counter() - t0) * 1e3
+    for s in states.values():
+        B.sv_destroy(s)
+    base = np.concatenate(base)
+    out = {"workload": f"512 HEA circuits, 10..22 qubits, depth 8, {args.dtype}", "gates": hb.num_gates(),
+           "config": cfg, "graph_ms": round(float(np.median(gms)), 3), "wall_ms": round(wall_ms, 3),
+           "ms_per_circuit": round(wall_ms / 512, 5), "per_gate_launch_ms": round(base_ms, 1),
+           "per_gate_ms_per_circuit": round(base_ms / 512, 5), "speedup": round(base_ms / wall_ms, 2),
+           "max_abs_diff_vs_per_gate": float(np.max(np.abs(res - base)))}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -238,6 +238,49 @@ int sv_profile_enable(sv_handle h, int enable);
  * `out` and their total count into *count; the record buffer is cleared. */
 int sv_profile_read(sv_handle h, sv_sweep_record *out, int max, int *count);
 
+/* ---- batches of small circuits in one persistent launch ----------------- */
+
+/* Many independent circuits of uneven width (a parameter sweep) run as one
+ * persistent kernel captured in a HIP graph.  Each circuit's state starts at
+ * |0...0>; its gates are applied and its Z-string expectation values
+ * <psi| Z^{mask} |psi> (FP64 accumulation) are returned.  A circuit that fits
+ * one LDS tile runs entirely in LDS; a wider one is cut into passes of LDS
+ * tiles ordered through a global work queue (paper Sec. 2.1: the state is 2^n
+ * amplitudes and every gate a sweep over them; here the sweeps of a pass are
+ * done on-chip). */
+typedef struct sv_batch *sv_batch_handle;
+
+/* Tile and fusion choice of a batch (picked by sv_batch_tune or set). */
+typedef struct sv_batch_config {
+    int32_t tile_bits;   /* log2 amplitudes per LDS tile: complex64 11..13, complex128 11..12 */
+    int32_t low_bits;    /* lowest physical bits every tile spans (contiguity), 0..4 */
+    int32_t fuse_width;  /* 1: merge runs of one-qubit gates; 2: fuse into <= 2-qubit blocks */
+    int32_t reserved;    /* must be 0 */
+} sv_batch_config;
+
+/* Create a batch of `ninst` circuits.  Circuit i has nqubits[i] qubits
+ * (1..30), gates[i][0..ngates[i]) and nterms[i] (0..64) Z masks zmasks[i][t]
+ * (bit q = Z on qubit q).  Supported gates: one target with at most one
+ * control, or a two-target SV_GATE_MATRIX without controls.  Later runs must
+ * pass gates of the same kinds on the same qubits (parameters may change).
+ * `stream` = hipStream_t to run on (NULL: the batch creates its own). */
+int sv_batch_create(int dtype, int ninst, const int *nqubits, const sv_gate *const *gates, const int *ngates,
+                    const uint64_t *const *zmasks, const int *nterms, void *stream, sv_batch_handle *out);
+
+/* Run the batch: gates = NULL reuses the last parameters, otherwise new
+ * gate lists of the created structure.  out receives sum_i nterms[i] values
+ * (circuit-major).  Synchronises. */
+int sv_batch_run(sv_batch_handle b, const sv_gate *const *gates, double *out);
+
+/* Time every candidate configuration `repeats` times with HIP events and keep
+ * the fastest (written to *chosen if not NULL). */
+int sv_batch_tune(sv_batch_handle b, int repeats, sv_batch_config *chosen);
+int sv_batch_set_config(sv_batch_handle b, const sv_batch_config *cfg);
+int sv_batch_get_config(sv_batch_handle b, sv_batch_config *cfg);
+/* Milliseconds of the last sv_batch_run's graph launch (HIP events). */
+int sv_batch_last_ms(sv_batch_handle b, double *ms);
+int sv_batch_destroy(sv_batch_handle b);
+
 /* ---- fusion plans (host only; no GPU needed) ---------------------------- */
 
 /* Build the sweep plan sv_apply_circuit would use for this gate list on an

@@ -324,3 +324,95 @@ def sv_profile_read(h: int, max_records: int = 1 << 16) -> List[dict]:
         d["kind_name"] = SWEEP_KIND.get(r.kind, str(r.kind))
         out.append(d)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+class sv_batch_config(ctypes.Structure):
+    _fields_ = [("tile_bits", ctypes.c_int32), ("low_bits", ctypes.c_int32),
+                ("fuse_width", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"tile_bits": self.tile_bits, "low_bits": self.low_bits, "fuse_width": self.fuse_width}
+
+
+_P = ctypes.c_void_p
+_lib.sv_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]
+_lib.sv_batch_create.restype = ctypes.c_int
+_lib.sv_batch_run.argtypes = [_P, _P, _P]
+_lib.sv_batch_run.restype = ctypes.c_int
+_lib.sv_batch_tune.argtypes = [_P, ctypes.c_int, ctypes.POINTER(sv_batch_config)]
+_lib.sv_batch_tune.restype = ctypes.c_int
+_lib.sv_batch_set_config.argtypes = [_P, ctypes.POINTER(sv_batch_config)]
+_lib.sv_batch_set_config.restype = ctypes.c_int
+_lib.sv_batch_get_config.argtypes = [_P, ctypes.POINTER(sv_batch_config)]
+_lib.sv_batch_get_config.restype = ctypes.c_int
+_lib.sv_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_double)]
+_lib.sv_batch_last_ms.restype = ctypes.c_int
+_lib.sv_batch_destroy.argtypes = [_P]
+_lib.sv_batch_destroy.restype = ctypes.c_int
+
+
+class Batch:
+    """Marshalled batch inputs (gate arrays and Z masks kept alive here)."""
+
+    def __init__(self, circuits: Sequence, qubits: Sequence[int], zmasks: Sequence[Sequence[int]]):
+        self.circs = [_as_circuit(c) for c in circuits]
+        self.ninst = len(self.circs)
+        self.q = np.ascontiguousarray(np.asarray(qubits, dtype=np.int32))
+        self.ng = np.ascontiguousarray(np.asarray([c.n_gates for c in self.circs], dtype=np.int32))
+        self.gptr = (ctypes.c_void_p * self.ninst)(*[ctypes.addressof(c.array) for c in self.circs])
+        self.z = [np.ascontiguousarray(np.asarray(list(z) or [0], dtype=np.uint64)) for z in zmasks]
+        self.nt = np.ascontiguousarray(np.asarray([len(z) for z in zmasks], dtype=np.int32))
+        self.zptr = (ctypes.c_void_p * self.ninst)(*[z.ctypes.data for z in self.z])
+        self.total_terms = int(self.nt.sum())
+
+    def gate_pointers(self, circuits=None):
+        if circuits is None:
+            return None
+        circs = [_as_circuit(c) for c in circuits]
+        self._keep_run = circs
+        return (ctypes.c_void_p * len(circs))(*[ctypes.addressof(c.array) for c in circs])
+
+
+def sv_batch_create(dtype: int, batch: Batch, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.sv_batch_create(dtype, batch.ninst, batch.q.ctypes.data, batch.gptr, batch.ng.ctypes.data,
+                                batch.zptr, batch.nt.ctypes.data, ctypes.c_void_p(stream or None),
+                                ctypes.byref(h)), "sv_batch_create")
+    return h.value
+
+
+def sv_batch_run(h: int, batch: Batch, circuits=None) -> np.ndarray:
+    out = np.empty(max(1, batch.total_terms), dtype=np.float64)
+    gp = batch.gate_pointers(circuits)
+    _check(_lib.sv_batch_run(ctypes.c_void_p(h), gp, out.ctypes.data), "sv_batch_run")
+    return out[:batch.total_terms]
+
+
+def sv_batch_tune(h: int, repeats: int = 2) -> dict:
+    c = sv_batch_config()
+    _check(_lib.sv_batch_tune(ctypes.c_void_p(h), repeats, ctypes.byref(c)), "sv_batch_tune")
+    return c.as_dict()
+
+
+def sv_batch_set_config(h: int, tile_bits: int, low_bits: int, fuse_width: int):
+    c = sv_batch_config(tile_bits, low_bits, fuse_width, 0)
+    _check(_lib.sv_batch_set_config(ctypes.c_void_p(h), ctypes.byref(c)), "sv_batch_set_config")
+
+
+def sv_batch_get_config(h: int) -> dict:
+    c = sv_batch_config()
+    _check(_lib.sv_batch_get_config(ctypes.c_void_p(h), ctypes.byref(c)), "sv_batch_get_config")
+    return c.as_dict()
+
+
+def sv_batch_last_ms(h: int) -> float:
+    v = ctypes.c_double()
+    _check(_lib.sv_batch_last_ms(ctypes.c_void_p(h), ctypes.byref(v)), "sv_batch_last_ms")
+    return v.value
+
+
+def sv_batch_destroy(h: int):
+    _check(_lib.sv_batch_destroy(ctypes.c_void_p(h)), "sv_batch_destroy")

@@ -15,6 +15,8 @@ SOURCES = [
     "sv_gates.hip",
     "sv_readout.hip",
     "sv_fused_mfma.hip",
+    "sv_batch.hip",
+    "sv_batch_host.cpp",
     "sv_plan.cpp",
     "sv_api.cpp",
 ]

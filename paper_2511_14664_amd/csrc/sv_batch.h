@@ -1,0 +1,76 @@
+// Shared host/device layout of a circuit batch (see sv_batch.hip / sv_batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sv {
+
+constexpr int kBatchMaxTileLog = 13;
+constexpr int kBatchMaxTerms = 64;
+
+struct BInst {
+    uint64_t state_off;  // amplitude offset into the batch state buffer (multi-pass circuits)
+    int32_t q;
+    int32_t npasses;
+    int32_t pass0;       // first entry in the pass table
+    int32_t nterms;
+    int32_t term0;       // first entry in the Z-mask table
+    int32_t out0;        // first output slot
+    int32_t part0;       // first partial-sum slot (multi-tile last pass)
+    int32_t pad;
+};
+
+struct BPass {
+    uint64_t dep[kBatchMaxTileLog];  // 2^(physical bit) of tile bit b
+    uint64_t ins[kBatchMaxTileLog];  // insert masks (ascending tile bits): tile index -> base
+    int32_t lp;                      // tile bits of this pass
+    int32_t step0;
+    int32_t nsteps;
+    uint32_t ntiles;
+    uint32_t need;                   // finished tiles of earlier passes required before start
+    int32_t last;                    // last pass: reduce expectation values instead of storing
+};
+
+// One in-LDS gate step.  type 0: dense one-qubit on tile bit a; 1: one-qubit
+// on tile bit a controlled by tile bit b; 2: dense two-qubit, matrix index bit
+// 0 on tile bit a and bit 1 on tile bit b.
+struct BStep {
+    uint32_t mat;  // offset of the matrix in complex elements
+    uint8_t type;
+    uint8_t a;
+    uint8_t b;
+    uint8_t pad;
+};
+
+struct BTask {
+    uint32_t inst;
+    uint32_t pass;  // pass index within the circuit
+    uint32_t tile;
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    void *states;
+    const BInst *inst;
+    const BPass *pass;
+    const BStep *steps;
+    const void *mats;
+    const BTask *tasks;
+    const uint64_t *zmasks;
+    double *partials;
+    double *out;
+    uint32_t *ctr;  // [0] queue head, [1] error, [2, 2+ninst) tiles done, then finish counts
+    uint32_t ntasks;
+    uint32_t ninst;
+    uint32_t spin_limit;
+    int32_t tile_log_max;
+};
+
+hipError_t launch_batch(int dtype, const BatchArgs &a, uint32_t grid, size_t lds, hipStream_t s);
+hipError_t launch_batch_fill(uint32_t *ctr, uint32_t n, hipStream_t s);
+// Persistent grid for the batch kernel with `lds` dynamic bytes per workgroup.
+uint32_t batch_grid(int dtype, size_t lds);
+
+}  // namespace sv

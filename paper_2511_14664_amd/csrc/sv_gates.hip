@@ -24,7 +24,7 @@ constexpr int kItems = 4;
 
 hipError_t check_grid(uint64_t blocks)
 {
-    return blocks > 0x7fffffffull ? hipErrorInvalidConfiguration : hipSuccess;
+    return blocks * kThreads > 0xffffffffull ? hipErrorInvalidConfiguration : hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -68,10 +68,12 @@ template <typename R, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Gate1Args<R> a)
 {
     using C = typename CT<R>::C;
-    const uint64_t u0 = uint64_t(blockIdx.x) * (kThreads * kItems) + threadIdx.x;
     C m00, m01, m10, m11;
     m00.x = a.u[0], m00.y = a.u[1], m01.x = a.u[2], m01.y = a.u[3];
     m10.x = a.u[4], m10.y = a.u[5], m11.x = a.u[6], m11.y = a.u[7];
+    const uint64_t chunk = uint64_t(kThreads) * kItems;
+    for (uint64_t u0 = uint64_t(blockIdx.x) * chunk + threadIdx.x; u0 - threadIdx.x < a.nunits;
+         u0 += uint64_t(gridDim.x) * chunk) {
     if constexpr (VEC) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 lo[kItems], hi[kItems];
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             v[ib[j]] = cmad(m11, hi[j], cmul(m10, lo[j]));
         }
     }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -142,9 +145,11 @@ template <typename R, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Diag1Args<R> a)
 {
     using C = typename CT<R>::C;
-    const uint64_t u0 = uint64_t(blockIdx.x) * (kThreads * kItems) + threadIdx.x;
     C d0, d1;
     d0.x = a.d[0], d0.y = a.d[1], d1.x = a.d[2], d1.y = a.d[3];
+    const uint64_t chunk = uint64_t(kThreads) * kItems;
+    for (uint64_t u0 = uint64_t(blockIdx.x) * chunk + threadIdx.x; u0 - threadIdx.x < a.nunits;
+         u0 += uint64_t(gridDim.x) * chunk) {
     if constexpr (VEC) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 x[kItems];
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
                 continue;
             v[ia[j]] = cmul((ia[j] & a.tbit) ? d1 : d0, x[j]);
         }
+    }
     }
 }
 
@@ -429,7 +435,7 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
         a.im = make_insert_masks(pos);
         fill_u(a.u, U, 4);
         a.nunits = vec ? ngroups / 2 : ngroups;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
         if (vec)
@@ -443,7 +449,7 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
         a.im = make_insert_masks(pos);
         fill_u(a.u, U, 4);
         a.nunits = ngroups;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL((k_gate1<double, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
@@ -474,7 +480,7 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
         a.im = make_insert_masks(pos);
         fill_u(a.d, dd, 2);
         a.nunits = vec ? nfree / 2 : nfree;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
         if (vec)
@@ -488,7 +494,7 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
         a.im = make_insert_masks(pos);
         fill_u(a.d, dd, 2);
         a.nunits = nfree;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, ~0ull);
+        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL((k_diag1<double, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);

@@ -52,6 +52,18 @@ int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_pl
 std::vector<Block> plan_plain(const std::vector<Block> &gates);
 std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax);
 
+// Structure of a greedy plan: member gate indices (in application order) and
+// the union of their qubits, per block.
+struct Group {
+    std::vector<int> members;
+    uint64_t qmask;
+};
+std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax);
+// Fuse gates into one block on the qubits of qmask (targets ascending); a
+// single member is returned unchanged.
+Block fuse(const std::vector<const Block *> &members, uint64_t qmask);
+uint64_t qubit_mask(const Block &b);
+
 // Algorithmic HBM bytes / flops of a sweep (physical bit positions).
 double block_bytes(int n, int dtype, const Block &b, const int *phys_t, const int *phys_c);
 double block_flops(int n, const Block &b);

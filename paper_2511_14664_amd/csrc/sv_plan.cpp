@@ -209,7 +209,7 @@ static void left_multiply(std::vector<cd> &M, int kb, const Block &g, const int 
     }
 }
 
-static Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
+Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
 {
     if (members.size() == 1)
         return *members[0];
@@ -248,7 +248,7 @@ static Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
     return out;
 }
 
-static uint64_t qubit_mask(const Block &b)
+uint64_t qubit_mask(const Block &b)
 {
     uint64_t m = 0;
     for (int j = 0; j < b.k; ++j)
@@ -266,7 +266,7 @@ static uint64_t qubit_mask(const Block &b)
 // it may be moved into the block the gate joins when that keeps the union
 // within kmax; this packs a layer of one-qubit gates into the entangling
 // gates that follow it.
-std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)
+std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
 {
     struct PB {
         std::vector<int> members;
@@ -320,14 +320,23 @@ std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)
             if ((gm >> q) & 1)
                 last[q] = target;
     }
-    std::vector<Block> out;
+    std::vector<Group> out;
     for (const PB &b : pb) {
         if (!b.alive || b.members.empty())
             continue;
+        out.push_back(Group{b.members, b.qmask});
+    }
+    return out;
+}
+
+std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)
+{
+    std::vector<Block> out;
+    for (const Group &g : group_greedy(gates, kmax)) {
         std::vector<const Block *> mem;
-        for (int i : b.members)
+        for (int i : g.members)
             mem.push_back(&gates[i]);
-        out.push_back(fuse(mem, b.qmask));
+        out.push_back(fuse(mem, g.qmask));
     }
     return out;
 }
