@@ -30,14 +30,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["layered", "share", "batch"], default="layered",
+    ap.add_argument("--workload", choices=["layered", "share", "batch", "su4"], default="layered",
                     help="layered: 28-qubit random layered circuit (the headline line); share: 34q complex128 / "
                          "35q complex64 share with 6-bit exchanges every 2 layers; batch: 512 HEA circuits "
-                         "of 10..22 qubits in one graph launch vs one launch per gate")
+                         "of 10..22 qubits in one graph launch vs one launch per gate; su4: 30-qubit U3 + "
+                         "SU(4) circuit, depth 40, greedy vs learned fusion plan")
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--mode", choices=["plain", "greedy", "learned"], default="greedy")
     ap.add_argument("--max-fused", type=int, default=5)
+    ap.add_argument("--precision", choices=["native", "bf16x3"], default="native")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (unfused) comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -73,19 +75,26 @@ def main():
         return bench_batch(args)
     if args.workload == "share":
         return bench_share(args)
+    if args.workload == "su4":
+        return bench_su4(args)
     n = args.qubits
     dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
     S = 8 if dtype == B.SV_C64 else 16
     gates = W.layered_u3_pairing(n, 20, W.circuit_seed(2, 1), "cx_or_cz")
     circ = B.Circuit(gates)
     mode = {"plain": B.SV_PLAN_PLAIN, "greedy": B.SV_PLAN_GREEDY, "learned": B.SV_PLAN_LEARNED}[args.mode]
-    opts = B.make_opts(mode, args.max_fused)
+    prec = B.SV_PREC_BF16X3 if args.precision == "bf16x3" else B.SV_PREC_NATIVE
+    opts = B.make_opts(mode, args.max_fused, prec)
     marg_q = list(range(n - 10, n))
     terms = W.hea_z_terms(n)[: 2 * 16]
     uni = W.uniforms(7, 1000)
 
     sv = svm.StateVector(n, dtype, device=0)
     stream = sv.stream
+    model = None
+    if args.mode == "learned":
+        model = train_cost_model(B, W)
+        B.sv_set_costmodel(sv.handle, model)
 
     def step(profile=False):
         B.sv_reset(sv.handle)
@@ -234,6 +243,79 @@ def main():
     }
     print(json.dumps(out), flush=True)
     sv.close()
+
+
+def train_cost_model(B, W):
+    """Cost model trained on sweep timings the library records on the
+    12-qubit complex128 and 28-qubit complex64/complex128 layered workloads
+    (greedy widths 1..6 and plain); untimed set-up."""
+    import numpy as np
+
+    Xs, ys = [], []
+    for n, dt, ent, cfg in ((12, B.SV_C128, "cx", 1), (28, B.SV_C64, "cx_or_cz", 2), (28, B.SV_C128, "cx_or_cz", 2)):
+        circ = B.Circuit(W.layered_u3_pairing(n, 20, W.circuit_seed(cfg, 1), ent))
+        h = B.sv_create(n, dt)
+        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_GREEDY, 3))
+        B.sv_profile_read(h)
+        B.sv_profile_enable(h, True)
+        for k in range(1, 7):
+            B.sv_reset(h)
+            B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_GREEDY, k))
+        B.sv_reset(h)
+        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PLAIN))
+        recs, cnt = B.sv_profile_read_raw(h)
+        Xs.append(B.sv_sweep_features(n, dt, recs, cnt))
+        ys.append(B.sv_sweep_targets(recs, cnt))
+        B.sv_destroy(h)
+    m = B.sv_costmodel_create(16)
+    loss = B.sv_costmodel_train(m, np.concatenate(Xs), np.concatenate(ys), 3000, 3e-3)
+    log(f"cost model trained on {sum(len(y) for y in ys)} sweeps, loss {loss:.4f}")
+    return m
+
+
+def bench_su4(args):
+    """30-qubit complex64 U3 + Haar SU(4) circuit (depth 40, 1800 gates): wall
+    time per circuit of the greedy plan and of the learned plan at equal
+    accuracy, and the cost model's prediction error."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2511_14664_amd import _binding as B
+
+    n = 30
+    prec = B.SV_PREC_BF16X3 if args.precision == "bf16x3" else B.SV_PREC_NATIVE
+    gates = W.u3_su4_layers(n, 40, W.circuit_seed(5, 1))
+    circ = B.Circuit(gates)
+    model = train_cost_model(B, W)
+    k, pred = B.sv_costmodel_rank(model, n, B.SV_C64, circ, 6)
+    res = {}
+    for name, opts in (("greedy", B.make_opts(B.SV_PLAN_GREEDY, args.max_fused, prec)),
+                       ("learned", B.make_opts(B.SV_PLAN_LEARNED, 6, prec))):
+        h = B.sv_create(n, B.SV_C64)
+        B.sv_set_costmodel(h, model)
+        for _ in range(args.warmup):
+            B.sv_reset(h)
+            B.sv_apply_circuit(h, circ, opts)
+        ts = []
+        for _ in range(args.steps):
+            B.sv_reset(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = B.sv_apply_circuit(h, circ, opts)
+            B.sv_synchronize(h)
+            ts.append(time.perf_counter() - t0)
+        amp = B.sv_copy_to_host(h, n, B.SV_C64, 0, 1 << 12)
+        res[name] = {"ms_per_circuit": round(1e3 * float(np.median(ts)), 2), "sweeps": st["sweeps"], "amp": amp}
+        B.sv_destroy(h)
+    B.sv_costmodel_destroy(model)
+    out = {"workload": f"30-qubit U3 + SU(4) circuit, depth 40, {len(gates)} gates, c64, {args.precision}",
+           "greedy_k": args.max_fused, "learned_k": k, "predicted_ms_by_width": [round(float(x), 1) for x in pred],
+           "greedy_ms": res["greedy"]["ms_per_circuit"], "greedy_sweeps": res["greedy"]["sweeps"],
+           "learned_ms": res["learned"]["ms_per_circuit"], "learned_sweeps": res["learned"]["sweeps"],
+           "gain": round(res["greedy"]["ms_per_circuit"] / res["learned"]["ms_per_circuit"], 3),
+           "max_abs_diff_first_4096_amps": float(np.max(np.abs(res["greedy"]["amp"] - res["learned"]["amp"])))}
+    print(json.dumps(out), flush=True)
 
 
 def bench_share(args):

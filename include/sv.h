@@ -101,8 +101,10 @@ typedef enum sv_plan_mode {
 
 typedef enum sv_precision {
     SV_PREC_NATIVE = 0,   /* complex64: FP32 arithmetic; complex128: FP64 */
-    SV_PREC_BF16X3 = 1    /* complex64 fused blocks: three-term BF16 split products on
-                             the matrix cores, FP32 accumulation */
+    SV_PREC_BF16X3 = 1    /* complex64 fused blocks of 5-6 qubits: three-term BF16 split
+                             products on the matrix cores, FP32 accumulation (relative
+                             error ~2^-16 per product); other blocks and complex128
+                             run as SV_PREC_NATIVE */
 } sv_precision;
 
 typedef struct sv_plan_opts {
@@ -213,7 +215,8 @@ typedef enum sv_sweep_kind {
     SV_SWEEP_DENSE = 2,    /* k-target dense block through the LDS tile (VALU) */
     SV_SWEEP_DENSE_MFMA = 3, /* k-target dense block on the matrix cores */
     SV_SWEEP_GROUP = 4,    /* k-target dense block, one group per thread (small n) */
-    SV_SWEEP_BITSWAP = 5   /* index-bit field exchange */
+    SV_SWEEP_BITSWAP = 5,  /* index-bit field exchange */
+    SV_SWEEP_DENSE_BF16X3 = 6 /* complex64 k-target block, three-term BF16 split on the matrix cores */
 } sv_sweep_kind;
 
 /* One timed sweep (physical bit positions). */
@@ -280,6 +283,59 @@ int sv_batch_get_config(sv_batch_handle b, sv_batch_config *cfg);
 /* Milliseconds of the last sv_batch_run's graph launch (HIP events). */
 int sv_batch_last_ms(sv_batch_handle b, double *ms);
 int sv_batch_destroy(sv_batch_handle b);
+
+/* ---- learned sweep cost model ------------------------------------------ */
+
+/* The best fusion width depends on the machine and the precision (paper Sec.
+ * 2.1; Sec. 2.2 quotes different defaults per GPU generation).  A small
+ * network learns the run time of one sweep from timings the library records
+ * itself (sv_profile_read) and ranks candidate fusion plans by their summed
+ * predicted time; SV_PLAN_LEARNED uses it, with the greedy plan as fallback.
+ *
+ * Network: SV_CM_FEATURES inputs -> SV_CM_HIDDEN ReLU -> SV_CM_HIDDEN ReLU ->
+ * 1 output = ln(milliseconds per GB of the sweep's algorithmic HBM traffic);
+ * a sweep's predicted time is exp(output) * bytes / 1e9.  Parameters (FP32), in this order:
+ * W1 [H x F row-major], b1 [H], W2 [H x H], b2 [H], w3 [H], b3 [1].
+ * Training (full-batch Adam on the mean squared error) and gradients run in
+ * FP32 on the GPU; prediction runs in FP16 with FP32 accumulation. */
+#define SV_CM_FEATURES 10
+#define SV_CM_HIDDEN 64
+
+typedef struct sv_costmodel *sv_costmodel_handle;
+
+/* Number of parameters (4929). */
+int sv_costmodel_num_params(int *count);
+/* New model with He-uniform weights drawn from `seed`, zero biases. */
+int sv_costmodel_create(uint64_t seed, sv_costmodel_handle *out);
+int sv_costmodel_get_params(sv_costmodel_handle m, float *out);
+int sv_costmodel_set_params(sv_costmodel_handle m, const float *in);
+/* Loss and gradient at the current parameters over x [n x F], y [n]. */
+int sv_costmodel_grad(sv_costmodel_handle m, const float *x, const float *y, int n, float *grad, float *loss);
+/* `epochs` full-batch Adam steps (b1 0.9, b2 0.999, eps 1e-8) with rate lr;
+ * the Adam moments persist across calls.  *final_loss (may be NULL) is the
+ * loss before the last step. */
+int sv_costmodel_train(sv_costmodel_handle m, const float *x, const float *y, int n, int epochs, float lr,
+                       float *final_loss);
+/* FP16 inference: out[i] = network output for feature row i. */
+int sv_costmodel_predict(sv_costmodel_handle m, const float *x, int n, float *out);
+int sv_costmodel_destroy(sv_costmodel_handle m);
+
+/* Feature rows (count x SV_CM_FEATURES) of recorded sweeps on an n-qubit
+ * state of dtype. */
+int sv_sweep_features(int n, int dtype, const sv_sweep_record *recs, int count, float *out);
+
+/* Training targets of recorded sweeps: out[i] = ln(ms_i / (bytes_i / 1e9)). */
+int sv_sweep_targets(const sv_sweep_record *recs, int count, float *out);
+
+/* Attach a model to a state (NULL detaches); SV_PLAN_LEARNED uses it. */
+int sv_set_costmodel(sv_handle h, sv_costmodel_handle m);
+
+/* Rank the candidate plans (greedy with widest block 1..max_fused) of a gate
+ * list by predicted run time.  predicted_ms[k-1] receives the prediction for
+ * width k (max_fused entries); *chosen the width with the smallest one, or
+ * max_fused if a prediction is not finite. */
+int sv_costmodel_rank(sv_costmodel_handle m, int n, int dtype, const sv_gate *gates, int ngates, int max_fused,
+                      int *chosen, float *predicted_ms);
 
 /* ---- fusion plans (host only; no GPU needed) ---------------------------- */
 

@@ -300,7 +300,8 @@ class sv_sweep_record(ctypes.Structure):
                 ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
-SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap"}
+SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap",
+              6: "dense_bf16x3"}
 
 _lib.sv_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
 _lib.sv_profile_enable.restype = ctypes.c_int
@@ -416,3 +417,122 @@ def sv_batch_last_ms(h: int) -> float:
 
 def sv_batch_destroy(h: int):
     _check(_lib.sv_batch_destroy(ctypes.c_void_p(h)), "sv_batch_destroy")
+
+
+def sv_profile_read_raw(h: int, max_records: int = 1 << 16):
+    """Recorded sweeps as an sv_sweep_record array (for sv_sweep_features)."""
+    buf = (sv_sweep_record * max_records)()
+    cnt = ctypes.c_int()
+    _check(_lib.sv_profile_read(ctypes.c_void_p(h), buf, max_records, ctypes.byref(cnt)), "sv_profile_read")
+    return buf, min(cnt.value, max_records)
+
+
+# ---------------------------------------------------------------------------
+# Learned cost model
+# ---------------------------------------------------------------------------
+SV_CM_FEATURES, SV_CM_HIDDEN = 10, 64
+_F32P = ctypes.POINTER(ctypes.c_float)
+for _name, _args in {
+    "sv_costmodel_num_params": [ctypes.POINTER(ctypes.c_int)],
+    "sv_costmodel_create": [ctypes.c_uint64, ctypes.POINTER(_P)],
+    "sv_costmodel_get_params": [_P, _P],
+    "sv_costmodel_set_params": [_P, _P],
+    "sv_costmodel_grad": [_P, _P, _P, ctypes.c_int, _P, _F32P],
+    "sv_costmodel_train": [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_float, _F32P],
+    "sv_costmodel_predict": [_P, _P, ctypes.c_int, _P],
+    "sv_costmodel_destroy": [_P],
+    "sv_sweep_features": [ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P],
+    "sv_sweep_targets": [_P, ctypes.c_int, _P],
+    "sv_set_costmodel": [_P, _P],
+    "sv_costmodel_rank": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sv_gate), ctypes.c_int, ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_int), _P],
+}.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = ctypes.c_int
+
+
+def sv_costmodel_num_params() -> int:
+    v = ctypes.c_int()
+    _check(_lib.sv_costmodel_num_params(ctypes.byref(v)), "sv_costmodel_num_params")
+    return v.value
+
+
+def sv_costmodel_create(seed: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.sv_costmodel_create(seed, ctypes.byref(h)), "sv_costmodel_create")
+    return h.value
+
+
+def sv_costmodel_get_params(m: int) -> np.ndarray:
+    out = np.empty(sv_costmodel_num_params(), dtype=np.float32)
+    _check(_lib.sv_costmodel_get_params(ctypes.c_void_p(m), out.ctypes.data), "sv_costmodel_get_params")
+    return out
+
+
+def sv_costmodel_set_params(m: int, p):
+    p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+    if p.size != sv_costmodel_num_params():
+        raise ValueError("wrong parameter count")
+    _check(_lib.sv_costmodel_set_params(ctypes.c_void_p(m), p.ctypes.data), "sv_costmodel_set_params")
+
+
+def _xy(x, y=None):
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1, SV_CM_FEATURES))
+    if y is not None:
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float32).ravel())
+    return x, y
+
+
+def sv_costmodel_grad(m: int, x, y):
+    x, y = _xy(x, y)
+    g = np.empty(sv_costmodel_num_params(), dtype=np.float32)
+    L = ctypes.c_float()
+    _check(_lib.sv_costmodel_grad(ctypes.c_void_p(m), x.ctypes.data, y.ctypes.data, x.shape[0], g.ctypes.data,
+                                  ctypes.byref(L)), "sv_costmodel_grad")
+    return float(L.value), g
+
+
+def sv_costmodel_train(m: int, x, y, epochs: int, lr: float) -> float:
+    x, y = _xy(x, y)
+    L = ctypes.c_float()
+    _check(_lib.sv_costmodel_train(ctypes.c_void_p(m), x.ctypes.data, y.ctypes.data, x.shape[0], epochs, lr,
+                                   ctypes.byref(L)), "sv_costmodel_train")
+    return float(L.value)
+
+
+def sv_costmodel_predict(m: int, x) -> np.ndarray:
+    x, _ = _xy(x)
+    out = np.empty(x.shape[0], dtype=np.float32)
+    _check(_lib.sv_costmodel_predict(ctypes.c_void_p(m), x.ctypes.data, x.shape[0], out.ctypes.data),
+           "sv_costmodel_predict")
+    return out
+
+
+def sv_costmodel_destroy(m: int):
+    _check(_lib.sv_costmodel_destroy(ctypes.c_void_p(m)), "sv_costmodel_destroy")
+
+
+def sv_sweep_features(n: int, dtype: int, records, count: int) -> np.ndarray:
+    out = np.empty((max(1, count), SV_CM_FEATURES), dtype=np.float32)
+    _check(_lib.sv_sweep_features(n, dtype, records, count, out.ctypes.data), "sv_sweep_features")
+    return out[:count]
+
+
+def sv_sweep_targets(records, count: int) -> np.ndarray:
+    out = np.empty(max(1, count), dtype=np.float32)
+    _check(_lib.sv_sweep_targets(records, count, out.ctypes.data), "sv_sweep_targets")
+    return out[:count]
+
+
+def sv_set_costmodel(h: int, m: Optional[int]):
+    _check(_lib.sv_set_costmodel(ctypes.c_void_p(h), ctypes.c_void_p(m or None)), "sv_set_costmodel")
+
+
+def sv_costmodel_rank(m: int, n: int, dtype: int, gates, max_fused: int = 6):
+    circ = _as_circuit(gates)
+    chosen = ctypes.c_int()
+    pred = np.zeros(max_fused, dtype=np.float32)
+    _check(_lib.sv_costmodel_rank(ctypes.c_void_p(m), n, dtype, circ.array, circ.n_gates, max_fused,
+                                  ctypes.byref(chosen), pred.ctypes.data), "sv_costmodel_rank")
+    return chosen.value, pred

@@ -17,6 +17,7 @@ SOURCES = [
     "sv_fused_mfma.hip",
     "sv_batch.hip",
     "sv_batch_host.cpp",
+    "sv_costmodel.hip",
     "sv_plan.cpp",
     "sv_api.cpp",
 ]

@@ -80,6 +80,8 @@ struct sv_state {
         hipEvent_t a, b;
     };
     std::vector<Pending> pending;
+    // cost model consulted by SV_PLAN_LEARNED (not owned)
+    sv_costmodel *model = nullptr;
 };
 
 struct sv_plan {
@@ -279,8 +281,55 @@ int prof_end(sv_state *h, sv_state::Pending &p)
     return SV_OK;
 }
 
-int run_blocks(sv_state *h, const std::vector<Block> &blocks, int precision, int ngates, sv_run_stats *st)
+// A dense 3-target block runs faster on the matrix cores as a 4-target one:
+// U (x) I on one extra free qubit (the lowest free physical bit >= 6, else the
+// lowest free one).
+Block pad_to_four(const sv_state *h, const Block &b)
 {
+    uint64_t used = 0;
+    for (int j = 0; j < b.k; ++j)
+        used |= uint64_t(1) << b.targets[j];
+    for (int j = 0; j < b.c; ++j)
+        used |= uint64_t(1) << b.controls[j];
+    int pick = -1, pick_any = -1;
+    for (int q = 0; q < h->n; ++q) {
+        if ((used >> q) & 1)
+            continue;
+        const int p = h->qmap[q];
+        if (pick_any < 0 || p < h->qmap[pick_any])
+            pick_any = q;
+        if (p >= 6 && (pick < 0 || p < h->qmap[pick]))
+            pick = q;
+    }
+    if (pick < 0)
+        pick = pick_any;
+    Block o = b;
+    o.k = 4;
+    o.targets[3] = pick;
+    o.U.assign(256, cd(0.0, 0.0));
+    for (int r = 0; r < 16; ++r)
+        for (int c = 0; c < 16; ++c)
+            if ((r >> 3) == (c >> 3))
+                o.U[size_t(r) * 16 + c] = b.U[size_t(r & 7) * 8 + (c & 7)];
+    return o;
+}
+
+int run_blocks(sv_state *h, const std::vector<Block> &blocks_in, int precision, int ngates, sv_run_stats *st)
+{
+    std::vector<Block> padded;
+    bool any = false;
+    for (const Block &b : blocks_in)
+        if (b.k == 3 && b.c + 4 < h->n && dense_path(h->n, h->dtype, 4, b.c, precision) == SV_SWEEP_DENSE_MFMA)
+            any = true;
+    if (any) {
+        padded.reserve(blocks_in.size());
+        for (const Block &b : blocks_in)
+            padded.push_back((b.k == 3 && b.c + 4 < h->n &&
+                              dense_path(h->n, h->dtype, 4, b.c, precision) == SV_SWEEP_DENSE_MFMA)
+                                 ? pad_to_four(h, b)
+                                 : b);
+    }
+    const std::vector<Block> &blocks = any ? padded : blocks_in;
     std::vector<int64_t> offs;
     int rc = upload_matrices(h, blocks, offs);
     if (rc != SV_OK)
@@ -604,11 +653,39 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
     if (opts)
         o = *opts;
     std::vector<Block> blocks;
-    rc = plan_circuit(h->n, h->dtype, gates, ngates, o, blocks);
-    if (rc != SV_OK)
-        return rc;
+    if (o.mode == SV_PLAN_LEARNED && h->model) {
+        sv_plan_opts plain = o;
+        plain.mode = SV_PLAN_PLAIN;
+        std::vector<Block> gates_b;
+        rc = plan_circuit(h->n, h->dtype, gates, ngates, plain, gates_b);
+        if (rc == SV_OK && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {
+            set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
+            rc = SV_EINVAL;
+        }
+        if (rc != SV_OK)
+            return rc;
+        DeviceGuard dg(h->device);
+        int k = o.max_fused;
+        rc = rank_plans(h->model, h->n, h->dtype, gates_b, o.max_fused, o.precision, k, nullptr);
+        if (rc != SV_OK)
+            return rc;
+        blocks = plan_greedy(gates_b, k);
+    } else {
+        rc = plan_circuit(h->n, h->dtype, gates, ngates, o, blocks);
+        if (rc != SV_OK)
+            return rc;
+    }
     DeviceGuard dg(h->device);
     return run_blocks(h, blocks, o.precision, ngates, stats);
+}
+
+int sv_set_costmodel(sv_handle h, sv_costmodel_handle m)
+{
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    h->model = m;
+    return SV_OK;
 }
 
 int sv_swap_bits(sv_handle h, int lo, int hi, int width)

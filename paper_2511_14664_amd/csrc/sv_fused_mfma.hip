@@ -32,6 +32,8 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 template <typename R, int K>
 struct MfmaShape;
 
+// 16x16x4 shapes on 2048-amplitude tiles: the U fragment, the accumulators
+// and the prefetched next tile all stay in registers at 4+ waves per SIMD.
 // complex64
 template <>
 struct MfmaShape<float, 4> {
@@ -39,11 +41,11 @@ struct MfmaShape<float, 4> {
 };
 template <>
 struct MfmaShape<float, 5> {
-    static constexpr int MT = 32, NT = 32, KT = 2, NACC = 16, TA_LOG = 12;
+    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
 };
 template <>
 struct MfmaShape<float, 6> {
-    static constexpr int MT = 32, NT = 32, KT = 2, NACC = 16, TA_LOG = 12;
+    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
 };
 // complex128
 template <>
@@ -56,7 +58,7 @@ struct MfmaShape<double, 5> {
 };
 template <>
 struct MfmaShape<double, 6> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 12;
+    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
 };
 
 template <typename R, int NACC>
@@ -188,15 +190,138 @@ hipError_t launch_mfma(void *st, int n, const void *d_U, const int *tgt, const i
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// complex64 with the three-term BF16 split (k = 5, 6).  Each FP32 operand x is
+// split as x = hi + lo with hi = bf16(x), lo = bf16(x - hi); a real product
+// X Y is taken as Xhi Yhi + Xhi Ylo + Xlo Yhi (the dropped Xlo Ylo term and
+// the rounding of lo leave a relative error of about 2^-16 per product), on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Operand layouts (lane l):
+// A[i = l % 32][k = 8 (l / 32) + e], B[k = 8 (l / 32) + e][j = l % 32], e < 8.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float *x, bf16x8 &hi, bf16x8 &lo)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = __bf16(x[e]);
+        hi[e] = h;
+        lo[e] = __bf16(x[e] - float(h));
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_dense_bf16x3(float *__restrict__ st, const TileArgs a)
+{
+    using C = float2;
+    constexpr int TA_LOG = 12;
+    constexpr int D = 1 << K;
+    constexpr int TA = 1 << TA_LOG;
+    constexpr int M = TA_LOG - K;
+    constexpr int NGS = (1 << M) / 32;
+    constexpr int NMT = D / 32;
+    constexpr int ITEMS = NGS * NMT;
+    constexpr int NKC = D / 16;  // k-chunks of 16
+    static_assert(ITEMS == 4, "one (group set, row block) per wave");
+
+    __shared__ C tile[TA];
+    const C *U = reinterpret_cast<const C *>(a.U);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int mt = wave % NMT;
+    const int gs = wave / NMT;
+    const int i = lane % 32, kb = 8 * (lane / 32);
+    const uint32_t xg = group_slot(uint32_t(gs * 32 + i), a);
+
+    bf16x8 urh[NKC], url[NKC], uih[NKC], uil[NKC];
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+        float re[8], im[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const C u = U[size_t(mt * 32 + i) * D + (kc * 16 + kb + e)];
+            re[e] = u.x;
+            im[e] = u.y;
+        }
+        split8(re, urh[kc], url[kc]);
+        split8(im, uih[kc], uil[kc]);
+    }
+
+    tile_pipeline<float, TA_LOG>(st, a, tile, [&](C *t) {
+        floatx16 accr = {}, acci = {};
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            float vr[8], vi[8], nvi[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const C x = t[swz(uint32_t(a.xc[kc * 16 + kb + e]) | xg)];
+                vr[e] = x.x;
+                vi[e] = x.y;
+                nvi[e] = -x.y;
+            }
+            bf16x8 vrh, vrl, vih, vil, nvih, nvil;
+            split8(vr, vrh, vrl);
+            split8(vi, vih, vil);
+            split8(nvi, nvih, nvil);
+            accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(urh[kc], vrh, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(urh[kc], vrl, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(url[kc], vrh, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uih[kc], nvih, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uih[kc], nvil, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uil[kc], nvih, accr, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(urh[kc], vih, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(urh[kc], vil, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(url[kc], vih, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uih[kc], vrh, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uih[kc], vrl, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uil[kc], vrh, acci, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = mt * 32 + acc_row<float, 32>(lane, r);
+            C y;
+            y.x = accr[r];
+            y.y = acci[r];
+            t[swz(uint32_t(a.xc[row]) | xg)] = y;
+        }
+        __syncthreads();
+    });
+}
+
+template <int K>
+hipError_t launch_bf16x3(void *st, int n, const void *d_U, const int *tgt, const int *ctl, int c, hipStream_t s)
+{
+    TileArgs a = make_tile_args(n, K, tgt, ctl, c, 12, d_U);
+    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_dense_bf16x3<K>), ~uint64_t(0) >> 1);
+    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
+    hipLaunchKernelGGL((k_dense_bf16x3<K>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dense_bf16x3(void *st, int n, const void *d_U, int k, const int *tgt, const int *ctl, int c,
+                               hipStream_t s)
+{
+    switch (k) {
+    case 5: return launch_bf16x3<5>(st, n, d_U, tgt, ctl, c, s);
+    case 6: return launch_bf16x3<6>(st, n, d_U, tgt, ctl, c, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
 }  // namespace
 
 int mfma_tile_log(int dtype, int k)
 {
     if (k < 4 || k > 6)
         return -1;
-    if (dtype == SV_C64)
-        return k == 4 ? MfmaShape<float, 4>::TA_LOG : MfmaShape<float, 5>::TA_LOG;
-    return k == 6 ? MfmaShape<double, 6>::TA_LOG : MfmaShape<double, 4>::TA_LOG;
+    (void)dtype;
+    return MfmaShape<float, 4>::TA_LOG;
 }
 
 hipError_t launch_dense_mfma(void *st, int n, int dtype, const void *d_U, int k, const int *tgt, const int *ctl,

@@ -561,11 +561,12 @@ hipError_t launch_tile_k(void *st, int n, const void *d_U, int k, const int *tgt
 
 int dense_path(int n, int dtype, int k, int c, int precision)
 {
-    (void)precision;
     static const bool no_mfma = [] {
         const char *e = getenv("SV_NO_MFMA");
         return e && *e && *e != '0';
     }();
+    if (!no_mfma && precision == SV_PREC_BF16X3 && dtype == SV_C64 && (k == 5 || k == 6) && n - c >= 12)
+        return SV_SWEEP_DENSE_BF16X3;
     const int tl = mfma_tile_log(dtype, k);
     if (!no_mfma && tl > 0 && n - c >= tl)
         return SV_SWEEP_DENSE_MFMA;
@@ -576,12 +577,56 @@ int dense_path(int n, int dtype, int k, int c, int precision)
 hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, const int *tgt,
                         const int *ctl, int c, int precision, hipStream_t s)
 {
-    if (dense_path(n, dtype, k, c, precision) == SV_SWEEP_DENSE_MFMA)
+    const int path = dense_path(n, dtype, k, c, precision);
+    if (path == SV_SWEEP_DENSE_BF16X3)
+        return launch_dense_bf16x3(st, n, d_U, k, tgt, ctl, c, s);
+    if (path == SV_SWEEP_DENSE_MFMA)
         return launch_dense_mfma(st, n, dtype, d_U, k, tgt, ctl, c, s);
     if (dtype == SV_C64)
         return launch_tile_k<float>(st, n, d_U, k, tgt, ctl, c, s);
     return launch_tile_k<double>(st, n, d_U, k, tgt, ctl, c, s);
 }
+
+namespace {
+
+// Bit-field exchange on the pipelined tile driver: the tile is read into LDS
+// in memory order, permuted inside LDS, and written back in memory order.
+template <typename R, int TLOG>
+__global__ __launch_bounds__(kThreads) void k_bitswap_p(R *__restrict__ st, const TileArgs a, int L, int w)
+{
+    using C = typename CT<R>::C;
+    constexpr int TA = 1 << TLOG;
+    constexpr int OPT = TA / kThreads;
+    __shared__ C tile[TA];
+    const int tid = threadIdx.x;
+    const uint32_t wm = (1u << w) - 1u;
+    const uint32_t fmask = (wm << L) | (wm << (L + w));
+    tile_pipeline<R, TLOG>(st, a, tile, [&](C *t) {
+        C tmp[OPT];
+#pragma unroll
+        for (int s = 0; s < OPT; ++s) {
+            const uint32_t y = uint32_t(s * kThreads + tid);
+            const uint32_t f1 = (y >> L) & wm, f2 = (y >> (L + w)) & wm;
+            tmp[s] = t[swz((y & ~fmask) | (f1 << (L + w)) | (f2 << L))];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < OPT; ++s)
+            t[swz(uint32_t(s * kThreads + tid))] = tmp[s];
+        __syncthreads();
+    });
+}
+
+template <typename R, int TLOG>
+hipError_t launch_bitswap_p(void *st, const TileArgs &a, int L, int w, hipStream_t s)
+{
+    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_bitswap_p<R, TLOG>), ~uint64_t(0) >> 1);
+    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
+    hipLaunchKernelGGL((k_bitswap_p<R, TLOG>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a, L, w);
+    return hipGetLastError();
+}
+
+}  // namespace
 
 hipError_t launch_bitswap(void *st, int n, int dtype, int lo, int hi, int w, hipStream_t s)
 {
@@ -602,6 +647,24 @@ hipError_t launch_bitswap(void *st, int n, int dtype, int lo, int hi, int w, hip
         a.dep[b] = uint64_t(1) << tilebits[b];
     a.outer = make_insert_masks(tilebits);
     a.ntiles = uint64_t(1) << (n - a.tlog);
+    if (a.tlog >= 9) {
+        TileArgs t{};
+        t.ntiles = a.ntiles;
+        t.outer = a.outer;
+        for (int b = 0; b < a.tlog; ++b)
+            t.dep[b] = a.dep[b];
+        switch (a.tlog * 2 + (dtype == SV_C64 ? 0 : 1)) {
+        case 18: return launch_bitswap_p<float, 9>(st, t, a.L, w, s);
+        case 19: return launch_bitswap_p<double, 9>(st, t, a.L, w, s);
+        case 20: return launch_bitswap_p<float, 10>(st, t, a.L, w, s);
+        case 21: return launch_bitswap_p<double, 10>(st, t, a.L, w, s);
+        case 22: return launch_bitswap_p<float, 11>(st, t, a.L, w, s);
+        case 23: return launch_bitswap_p<double, 11>(st, t, a.L, w, s);
+        case 24: return launch_bitswap_p<float, 12>(st, t, a.L, w, s);
+        case 25: return launch_bitswap_p<double, 12>(st, t, a.L, w, s);
+        default: break;
+        }
+    }
     const uint64_t grid = grid_for(a.ntiles, 1, uint64_t(1) << 20);
     if (dtype == SV_C64)
         hipLaunchKernelGGL(k_bitswap<float>, dim3(grid), dim3(kThreads), 0, s, (float *)st, a);

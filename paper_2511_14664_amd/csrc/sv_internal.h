@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <complex>
 #include <cstdint>
 #include <string>
@@ -68,6 +69,13 @@ uint64_t qubit_mask(const Block &b);
 double block_bytes(int n, int dtype, const Block &b, const int *phys_t, const int *phys_c);
 double block_flops(int n, const Block &b);
 
+// Learned cost model (sv_costmodel.hip): feature row of a sweep, the record
+// a plan block would produce, and ranking of greedy plans of width 1..max_fused.
+void sweep_features(int n, int dtype, const sv_sweep_record &r, float *f);
+sv_sweep_record block_record(int n, int dtype, const Block &b, int precision);
+int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gates, int max_fused, int precision,
+               int &chosen, float *pred_ms);
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (device code in the .hip sources).  All pointers are
 // device pointers unless named h_*.  Qubit positions are PHYSICAL bits.
@@ -88,6 +96,9 @@ hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, cons
 int mfma_tile_log(int dtype, int k);
 hipError_t launch_dense_mfma(void *st, int n, int dtype, const void *d_U, int k, const int *tgt, const int *ctl,
                              int c, hipStream_t s);
+// complex64 k = 5, 6 with the three-term BF16 split (needs n - c >= 12).
+hipError_t launch_dense_bf16x3(void *st, int n, const void *d_U, int k, const int *tgt, const int *ctl, int c,
+                               hipStream_t s);
 // Which kernel launch_gatek uses (an sv_sweep_kind).
 int dense_path(int n, int dtype, int k, int c, int precision);
 

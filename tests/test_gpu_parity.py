@@ -357,3 +357,41 @@ def test_statevector_on_torch_memory_and_stream():
             sv.apply_circuit(gates, mode=B.SV_PLAN_GREEDY, max_fused=4)
             assert maxerr(sv.to_host(), want) <= 1e-12
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# complex64 fused blocks with the three-term BF16 split on the matrix cores
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kmax", [5, 6])
+def test_bf16x3_fused_circuits(kmax):
+    n = 16
+    gates = (W.layered_u3_pairing(n, 8, 9, "cx_or_cz") + W.u3_su4_layers(n, 4, 4))
+    want = oracle.run(gates, n)
+    with State(n, B.SV_C64) as s:
+        B.sv_profile_enable(s.h, True)
+        st = B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_GREEDY, kmax, B.SV_PREC_BF16X3))
+        kinds = {r["kind_name"] for r in B.sv_profile_read(s.h)}
+        assert "dense_bf16x3" in kinds
+        e = maxerr(s.host(), want)
+        say(f"bf16x3 kmax={kmax}: {st['sweeps']} sweeps, max|d amp| = {e:.2e}")
+        assert e <= TOL[B.SV_C64]
+
+
+def test_bf16x3_single_blocks_every_placement():
+    n = 14
+    rng = np.random.default_rng(21)
+    psi = W.random_state(n, 22)
+    with State(n, B.SV_C64) as s:
+        for k in (5, 6):
+            for tg in (list(range(k)), list(range(n - k, n)), [int(x) for x in rng.permutation(n)[:k]]):
+                for ctl in ([], [q for q in range(n) if q not in tg][:1]):
+                    if n - len(ctl) < 12:
+                        continue
+                    U = W.haar_unitary(rng, 1 << k)
+                    ref = s.load(psi)
+                    gate = Gate("matrix", tuple(tg), tuple(ctl), (), U)
+                    B.sv_apply_circuit(s.h, [gate], B.make_opts(B.SV_PLAN_PLAIN, 1, B.SV_PREC_BF16X3))
+                    want = oracle.apply_matrix(ref.copy(), U, tg, ctl)
+                    e = maxerr(s.host(), want)
+                    # one block: relative error ~2^-16 of amplitudes of size ~2^-7
+                    assert e <= 1e-6, (k, tg, ctl, e)
