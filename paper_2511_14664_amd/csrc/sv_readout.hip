@@ -4,6 +4,7 @@
 // amplitude precision, with a fixed reduction order (no atomics), so results
 // are reproducible run to run.
 #include <algorithm>
+#include <type_traits>
 
 #include "sv_internal.h"
 
@@ -173,17 +174,29 @@ __global__ __launch_bounds__(kThreads) void k_expect_z(const R *__restrict__ st,
     for (int t = 0; t < kMaxZ; ++t)
         acc[t] = 0.0;
     const uint64_t stride = uint64_t(gridDim.x) * kThreads;
-    for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < a.nelem; i += stride) {
-        const double p = prob(v[i]);
+    // four independent loads in flight per thread
+    for (uint64_t i0 = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i0 < a.nelem; i0 += 4 * stride) {
+        double p[4];
+        uint64_t ii[4];
 #pragma unroll
-        for (int t = 0; t < kMaxZ; ++t)
-            if (t < a.nt)
-                acc[t] += (__popcll(i & a.z[t]) & 1) ? -p : p;
+        for (int u = 0; u < 4; ++u) {
+            ii[u] = i0 + uint64_t(u) * stride;
+            p[u] = ii[u] < a.nelem ? prob(v[ii[u]]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < kMaxZ; ++t)
+                if (t < a.nt)
+                    acc[t] += (__popcll(ii[u] & a.z[t]) & 1) ? -p[u] : p[u];
     }
-    for (int t = 0; t < a.nt; ++t) {
-        const double s = block_sum(acc[t], sh);
-        if (threadIdx.x == 0)
-            part[uint64_t(t) * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+    for (int t = 0; t < kMaxZ; ++t) {
+        if (t < a.nt) {
+            const double s = block_sum(acc[t], sh);
+            if (threadIdx.x == 0)
+                part[uint64_t(t) * gridDim.x + blockIdx.x] = s;
+        }
     }
 }
 
@@ -328,6 +341,60 @@ __global__ __launch_bounds__(kThreads) void k_sample_search(const R *__restrict_
         out[s] = int64_t(base + uint64_t(lastnz >= 0 ? lastnz : bsz - 1));
 }
 
+// Two-stage marginal for bins above a high bit: stage 1 sums contiguous
+// segments of 2^s amplitudes (16-byte loads, four independent FP64
+// accumulators per thread, fixed-order tree); stage 2 maps segment sums to
+// bins.  Every amplitude is read exactly once, in address order.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_segment_sums(const R *__restrict__ st, double *__restrict__ seg,
+                                                           int s)
+{
+    __shared__ double sh[4];
+    const uint64_t base = uint64_t(blockIdx.x) << s;
+    const uint32_t len = 1u << s;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if constexpr (std::is_same<R, float>::value) {
+        const float4 *v4 = reinterpret_cast<const float4 *>(st) + (base >> 1);
+        for (uint32_t e = threadIdx.x; e < len / 2; e += 2 * kThreads) {
+            const float4 q = v4[e];
+            a0 += double(q.x) * q.x + double(q.y) * q.y;
+            a1 += double(q.z) * q.z + double(q.w) * q.w;
+            if (e + kThreads < len / 2) {
+                const float4 r = v4[e + kThreads];
+                a2 += double(r.x) * r.x + double(r.y) * r.y;
+                a3 += double(r.z) * r.z + double(r.w) * r.w;
+            }
+        }
+    } else {
+        const double2 *v2 = reinterpret_cast<const double2 *>(st) + base;
+        for (uint32_t e = threadIdx.x; e < len; e += 2 * kThreads) {
+            const double2 q = v2[e];
+            a0 += q.x * q.x + q.y * q.y;
+            if (e + kThreads < len) {
+                const double2 r = v2[e + kThreads];
+                a1 += r.x * r.x + r.y * r.y;
+            }
+        }
+    }
+    const double t = block_sum((a0 + a1) + (a2 + a3), sh);
+    if (threadIdx.x == 0)
+        seg[blockIdx.x] = t;
+}
+
+// out[x] = sum over r of p[dep(x, Q') | ins(r, Q')] on a FP64 array of 2^nb values.
+__global__ __launch_bounds__(kThreads) void k_marg_doubles(const double *__restrict__ p, double *__restrict__ out,
+                                                           const MargArgs a)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * kThreads;
+    for (uint64_t x = uint64_t(blockIdx.x) * kThreads + threadIdx.x; x < a.nbins; x += stride) {
+        const uint64_t xq = dep_x(x, a);
+        double acc = 0.0;
+        for (uint64_t r = 0; r < a.rest; ++r)
+            acc += p[xq | insert_zeros(r, a.rest_im)];
+        out[x] = acc;
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -365,7 +432,9 @@ MargPlan marg_plan(int n, int m)
 uint64_t marginal_scratch_doubles(int n, int m)
 {
     MargPlan p = marg_plan(n, m);
-    return p.rmajor ? (uint64_t(1) << m) * p.chunks : 1;
+    const uint64_t old = p.rmajor ? (uint64_t(1) << m) * p.chunks : 1;
+    const uint64_t seg = n >= 12 ? (uint64_t(1) << (n - 12)) : 1;
+    return std::max(old, seg);
 }
 
 hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, int m, double *d_scratch,
@@ -373,6 +442,36 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
 {
     if (m < 0 || m > kMaxQ || m > n)
         return hipErrorInvalidValue;
+    // segment path: every bin bit at or above bit 12
+    int b0 = n;
+    for (int b = 0; b < m; ++b)
+        b0 = std::min(b0, phys_q[b]);
+    if (n >= 12 && b0 >= 12) {
+        const int sb = std::min(b0, 16);
+        const uint64_t nseg = uint64_t(1) << (n - sb);
+        if (dtype == SV_C64)
+            hipLaunchKernelGGL(k_segment_sums<float>, dim3(uint32_t(nseg)), dim3(kThreads), 0, s, (const float *)st,
+                               d_scratch, sb);
+        else
+            hipLaunchKernelGGL(k_segment_sums<double>, dim3(uint32_t(nseg)), dim3(kThreads), 0, s, (const double *)st,
+                               d_scratch, sb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        MargArgs a2{};
+        a2.m = m;
+        a2.rest = uint64_t(1) << (n - sb - m);
+        a2.nbins = uint32_t(1u << m);
+        std::vector<int> q2(phys_q, phys_q + m);
+        for (int b = 0; b < m; ++b) {
+            q2[b] -= sb;
+            a2.qbit[b] = uint64_t(1) << q2[b];
+        }
+        a2.rest_im = make_masks(q2);
+        const uint64_t g = std::min<uint64_t>((uint64_t(a2.nbins) + kThreads - 1) / kThreads, 1u << 20);
+        hipLaunchKernelGGL(k_marg_doubles, dim3(g), dim3(kThreads), 0, s, d_scratch, d_out, a2);
+        return hipGetLastError();
+    }
     MargArgs a{};
     a.m = m;
     a.rest = uint64_t(1) << (n - m);
@@ -406,10 +505,10 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
 }
 
 namespace {
-constexpr uint32_t kExpGrid = 1024;
+constexpr uint32_t kExpGrid = 4096;
 uint32_t exp_grid(int n)
 {
-    const uint64_t need = ((uint64_t(1) << n) + kThreads * 8 - 1) / (kThreads * 8);
+    const uint64_t need = ((uint64_t(1) << n) + kThreads * 16 - 1) / (kThreads * 16);
     return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(kExpGrid, need)));
 }
 }  // namespace
