@@ -266,6 +266,46 @@ uint64_t qubit_mask(const Block &b)
 // it may be moved into the block the gate joins when that keeps the union
 // within kmax; this packs a layer of one-qubit gates into the entangling
 // gates that follow it.
+// Second pass over the block sequence: block j joins an earlier block i when
+// their union stays within kmax qubits and every block between them acts on
+// qubits disjoint from j's (so j commutes back to i); or, symmetrically, i
+// joins j when everything between is disjoint from i.  Repeats until no
+// merge applies.
+static void merge_groups(std::vector<Group> &g, int kmax)
+{
+    auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (size_t i = 0; i < g.size() && !changed; ++i) {
+            uint64_t between = 0;  // union of qubits of blocks strictly between i and j
+            for (size_t j = i + 1; j < g.size(); ++j) {
+                if (popc(g[i].qmask | g[j].qmask) <= kmax) {
+                    if ((between & g[j].qmask) == 0) {
+                        // move j back into i: members of j follow those of i
+                        g[i].members.insert(g[i].members.end(), g[j].members.begin(), g[j].members.end());
+                        g[i].qmask |= g[j].qmask;
+                        g.erase(g.begin() + long(j));
+                        changed = true;
+                        break;
+                    }
+                    if ((between & g[i].qmask) == 0) {
+                        // move i forward into j: members of i precede those of j
+                        g[j].members.insert(g[j].members.begin(), g[i].members.begin(), g[i].members.end());
+                        g[j].qmask |= g[i].qmask;
+                        g.erase(g.begin() + long(i));
+                        changed = true;
+                        break;
+                    }
+                }
+                between |= g[j].qmask;
+                if (popc(between | g[i].qmask) > 64)
+                    break;
+            }
+        }
+    }
+}
+
 std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
 {
     struct PB {
@@ -326,6 +366,7 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
             continue;
         out.push_back(Group{b.members, b.qmask});
     }
+    merge_groups(out, kmax);
     return out;
 }
 

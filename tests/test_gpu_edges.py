@@ -1,0 +1,102 @@
+"""Edge cases on the GPU: tiny states, every kernel path at its size threshold,
+empty inputs, and argument errors on a live handle (rejected before launch)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import Gate
+
+from paper_2511_14664_amd import _binding as B
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.SV_C128: 1e-12, B.SV_C64: 2e-5}
+
+
+@pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_tiny_states_every_gate(dtype, n):
+    rng = np.random.default_rng(n)
+    gates = []
+    for name in ("h", "x", "y", "z", "s", "t", "rx", "ry", "rz", "p", "u3"):
+        q = int(rng.integers(n))
+        ctl = tuple(x for x in range(n) if x != q)[:1] if n > 1 else ()
+        gates.append(Gate(name, (q,), (), tuple(rng.uniform(0, 6, W.N_PARAMS[name]))))
+        if ctl:
+            gates.append(Gate(name, (q,), ctl, tuple(rng.uniform(0, 6, W.N_PARAMS[name]))))
+    for k in range(2, n + 1):
+        gates.append(Gate("matrix", tuple(int(x) for x in rng.permutation(n)[:k]), (), (), W.haar_unitary(rng, 1 << k)))
+    want = oracle.run(gates, n)
+    for mode in (B.SV_PLAN_PLAIN, B.SV_PLAN_GREEDY):
+        h = B.sv_create(n, dtype)
+        try:
+            B.sv_apply_circuit(h, gates, B.make_opts(mode, min(6, n)))
+            got = B.sv_copy_to_host(h, n, dtype).astype(np.complex128)
+            assert np.max(np.abs(got - want)) <= TOL[dtype]
+            assert abs(B.sv_probabilities(h, [])[0] - 1) < 1e-5
+            assert np.max(np.abs(B.sv_probabilities(h, list(range(n))) - oracle.probabilities(got))) < 1e-12
+            s = B.sv_sample(h, W.uniforms(1, 50))
+            assert np.all((s >= 0) & (s < (1 << n)))
+        finally:
+            B.sv_destroy(h)
+
+
+@pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64], ids=["c128", "c64"])
+def test_paths_at_their_thresholds(dtype):
+    """n - c just at and just below the LDS-tile / matrix-core thresholds."""
+    rng = np.random.default_rng(3)
+    for n in (10, 11, 12):
+        psi = W.random_state(n, n)
+        h = B.sv_create(n, dtype)
+        try:
+            for k in (2, 3, 4, 5, 6):
+                for c in (0, 1):
+                    if k + c > n:
+                        continue
+                    qs = [int(x) for x in rng.permutation(n)]
+                    U = W.haar_unitary(rng, 1 << k)
+                    B.sv_copy_from_host(h, dtype, psi)
+                    ref = np.asarray(psi, dtype=B.amp_dtype(dtype)).astype(np.complex128)
+                    B.sv_apply_gate(h, U, qs[:k], qs[k:k + c])
+                    want = oracle.apply_matrix(ref.copy(), U, qs[:k], qs[k:k + c])
+                    got = B.sv_copy_to_host(h, n, dtype).astype(np.complex128)
+                    assert np.max(np.abs(got - want)) <= TOL[dtype] / 10, (n, k, c)
+        finally:
+            B.sv_destroy(h)
+
+
+def test_empty_inputs_and_errors_on_a_live_handle():
+    n = 8
+    h = B.sv_create(n, B.SV_C64)
+    try:
+        st = B.sv_apply_circuit(h, [])
+        assert st["sweeps"] == 0
+        assert B.sv_expect_pauli(h, []).size == 0
+        assert B.sv_sample(h, np.array([])).size == 0
+        for bad in ([Gate("h", (n,))], [Gate("x", (0,), (0,))]):
+            with pytest.raises(B.SvError) as e:
+                B.sv_apply_circuit(h, bad)
+            assert e.value.code == B.SV_EINVAL
+        with pytest.raises(B.SvError):
+            B.sv_swap_bits(h, 0, 3, 4)  # overlapping fields
+        with pytest.raises(B.SvError):
+            B.sv_swap_bits(h, 0, 4, 7)  # width > 6
+        with pytest.raises(B.SvError):
+            B.sv_expect_pauli(h, ["ZZ"])  # wrong length
+        with pytest.raises(B.SvError):
+            B.sv_expect_pauli(h, ["ZZZZZZZQ"])
+        with pytest.raises(B.SvError):
+            B.sv_sample(h, np.array([0.5, -0.1]))
+        with pytest.raises(B.SvError):
+            B.sv_probabilities(h, [1, 1])
+        with pytest.raises(B.SvError):
+            B.sv_copy_to_host(h, n, B.SV_C64, 250, 10)
+        B.sv_swap_bits(h, 0, 4, 3)
+        with pytest.raises(B.SvError):
+            B.sv_copy_from_host(h, B.SV_C64, np.zeros(4, np.complex64), 0)  # partial copy, relaid out
+        # the state is still |0...0> after all the rejected calls
+        p = B.sv_probabilities(h, list(range(n)))
+        assert p[0] == 1.0 and np.sum(p) == 1.0
+    finally:
+        B.sv_destroy(h)
