@@ -762,7 +762,7 @@ int sv_probabilities(sv_handle h, const int *qubits, int m, double *out)
     }
     DeviceGuard dg(h->device);
     const uint64_t nbins = uint64_t(1) << m;
-    const uint64_t part = marginal_scratch_doubles(h->n, m);
+    const uint64_t part = marginal_scratch_doubles(h->n, m, phys);
     rc = ensure_scratch(h, (part + nbins) * sizeof(double));
     if (rc != SV_OK)
         return rc;
@@ -810,44 +810,45 @@ int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *o
     if (rc != SV_OK)
         return rc;
     double *d_res = h->d_scratch + part;
-    // Z-only strings in batches of 16 (slot 2*t holds the value)
-    std::vector<int> zterms;
+    // Device results: the Z-only strings' values first (one double each, in
+    // order of appearance), then (Re, Im) of each general string.  Every
+    // launch is queued, then one copy and one wait.
+    std::vector<int> zterms, xyterms;
     for (int t = 0; t < nterms; ++t)
-        if (xs[t] == 0)
-            zterms.push_back(t);
-    std::vector<double> zvals(zterms.size());
-    // results of a batch land in d_res[0..nb) then are moved on the host
-    std::vector<double> host(2 * size_t(nterms), 0.0);
-    for (size_t s = 0; s < zterms.size(); s += 16) {
-        const int nb = int(std::min<size_t>(16, zterms.size() - s));
-        uint64_t z[16];
+        (xs[t] == 0 ? zterms : xyterms).push_back(t);
+    const int zb = expect_z_batch();
+    for (size_t s = 0; s < zterms.size(); s += size_t(zb)) {
+        const int nb = int(std::min<size_t>(size_t(zb), zterms.size() - s));
+        std::vector<uint64_t> z(static_cast<size_t>(nb));
         for (int j = 0; j < nb; ++j)
             z[j] = yzs[zterms[s + j]];
-        hipError_t e = launch_expect_z(h->d_state, h->n, h->dtype, z, nb, h->d_scratch, d_res, h->stream);
+        hipError_t e = launch_expect_z(h->d_state, h->n, h->dtype, z.data(), nb, h->d_scratch, d_res + s, h->stream);
         if (e != hipSuccess) {
             set_error("Z expectation launch failed: %s", hipGetErrorString(e));
             return SV_EDEVICE;
         }
-        HIP_TRY(hipMemcpyAsync(h->h_pinned, d_res, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        const double *pv = static_cast<const double *>(h->h_pinned);
-        for (int j = 0; j < nb; ++j)
-            out[zterms[s + j]] = pv[j];
     }
-    for (int t = 0; t < nterms; ++t) {
-        if (xs[t] == 0)
-            continue;
-        hipError_t e = launch_expect_xy(h->d_state, h->n, h->dtype, xs[t], yzs[t], h->d_scratch, d_res, h->stream);
+    const size_t nz = zterms.size();
+    for (size_t q = 0; q < xyterms.size(); ++q) {
+        const int t = xyterms[q];
+        hipError_t e = launch_expect_xy(h->d_state, h->n, h->dtype, xs[t], yzs[t], h->d_scratch, d_res + nz + 2 * q,
+                                        h->stream);
         if (e != hipSuccess) {
             set_error("Pauli expectation launch failed: %s", hipGetErrorString(e));
             return SV_EDEVICE;
         }
-        HIP_TRY(hipMemcpyAsync(h->h_pinned, d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        const double *pv = static_cast<const double *>(h->h_pinned);
-        const cd S(pv[0], pv[1]);
+    }
+    const size_t nres = nz + 2 * xyterms.size();
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_res, nres * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double *pv = static_cast<const double *>(h->h_pinned);
+    for (size_t j = 0; j < nz; ++j)
+        out[zterms[j]] = pv[j];
+    static const cd ipow[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    for (size_t q = 0; q < xyterms.size(); ++q) {
+        const int t = xyterms[q];
+        const cd S(pv[nz + 2 * q], pv[nz + 2 * q + 1]);
         // multiply by i^(number of Y)
-        static const cd ipow[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
         out[t] = (ipow[nys[t] & 3] * S).real();
     }
     return SV_OK;

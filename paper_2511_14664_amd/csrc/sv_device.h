@@ -168,166 +168,149 @@ __device__ __forceinline__ uint64_t tile_low_offset(int tid, const TileArgs &a)
     return off;
 }
 
-template <int TA_LOG>
-__device__ __forceinline__ uint64_t tile_high_offset(int s, const TileArgs &a)
+// ---------------------------------------------------------------------------
+// Streaming global access.  State sweeps touch every byte exactly once, so
+// loads and stores carry the nontemporal hint: lines are not kept in L2 or
+// the memory-side cache for reuse that never comes.
+// ---------------------------------------------------------------------------
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 ld_nt(const float2 *p)
 {
-    uint64_t off = 0;
-#pragma unroll
-    for (int b = 8; b < TA_LOG; ++b)
-        if ((s >> (b - 8)) & 1)
-            off |= a.dep[b];
-    return off;
+    const f32x2 q = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
+    return make_float2(q.x, q.y);
+}
+__device__ __forceinline__ double2 ld_nt(const double2 *p)
+{
+    const f64x2 q = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+    return make_double2(q.x, q.y);
+}
+__device__ __forceinline__ float4 ld_nt(const float4 *p)
+{
+    const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    return make_float4(q.x, q.y, q.z, q.w);
+}
+__device__ __forceinline__ void st_nt(float2 *p, float2 v)
+{
+    __builtin_nontemporal_store(f32x2{v.x, v.y}, reinterpret_cast<f32x2 *>(p));
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v)
+{
+    __builtin_nontemporal_store(f64x2{v.x, v.y}, reinterpret_cast<f64x2 *>(p));
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 v)
+{
+    __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<f32x4 *>(p));
 }
 
 // ---------------------------------------------------------------------------
-// Software-pipelined sweep over LDS tiles.  Each workgroup walks tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...; the global loads of the next tile
-// are issued into registers before the current tile is computed, so HBM
-// traffic overlaps the arithmetic.  For complex64 with physical bit 0 inside
-// the tile, amplitude pairs are moved with 16-byte accesses.
+// Sweep over LDS tiles, one tile per workgroup: load (all of the
+// workgroup's global loads in flight at once) -> LDS -> compute -> store.
+// Latency is hidden by the other resident workgroups of the CU rather than by
+// a register prefetch of the next tile, which keeps register use low and
+// residency high.  The grid is 2-D (tile = blockIdx.y * gridDim.x +
+// blockIdx.x, see tile_grid) so that no workgroup loops: a loop would let the
+// compiler hoist the per-tile constants into registers.  PAIR (complex64
+// with physical bit 0 inside the tile) moves amplitude pairs as 16-byte
+// accesses.
 //
 // compute(tile) must read the tile, __syncthreads(), write its results back
 // into the same LDS slots and __syncthreads() again.
 // ---------------------------------------------------------------------------
-template <typename R, int TA_LOG, typename F>
-__device__ __forceinline__ void tile_pipeline(R *__restrict__ st, const TileArgs &a, typename CT<R>::C *tile,
-                                              F &&compute)
+template <typename R, int TA_LOG, bool PAIR, typename F>
+__device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a, typename CT<R>::C *tile,
+                                           F &&compute)
 {
     using C = typename CT<R>::C;
     constexpr int TA = 1 << TA_LOG;
     constexpr int OPT = TA / kThreads;
     static_assert(OPT >= 2 && OPT % 2 == 0, "tile smaller than two elements per thread");
-    C *v = reinterpret_cast<C *>(st);
+    static_assert(!PAIR || std::is_same<R, float>::value, "16-byte pairs are complex64 only");
+    constexpr int LO = PAIR ? 1 : 0;  // tile bits below the thread bits
     const int tid = threadIdx.x;
-    // pair mode: x and x+1 are adjacent amplitudes (16 bytes for complex64)
-    constexpr bool CAN_PAIR = std::is_same<R, float>::value;
-    const bool pair = CAN_PAIR && a.dep[0] == 1;
     uint64_t off_lo = 0;
-    if (pair) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
-            if ((tid >> b) & 1)
-                off_lo |= a.dep[b + 1];
-    } else {
-        off_lo = tile_low_offset(tid, a);
-    }
-    auto hi_off = [&](int s) -> uint64_t {
-        uint64_t off = 0;
-        if (pair) {
+    for (int b = 0; b < 8; ++b)
+        if ((tid >> b) & 1)
+            off_lo |= a.dep[b + LO];
+    auto offset = [&](int s) -> uint64_t {
+        uint64_t off = off_lo;
 #pragma unroll
-            for (int b = 9; b < TA_LOG; ++b)
-                if ((s >> (b - 9)) & 1)
-                    off |= a.dep[b];
-        } else {
-#pragma unroll
-            for (int b = 8; b < TA_LOG; ++b)
-                if ((s >> (b - 8)) & 1)
-                    off |= a.dep[b];
-        }
+        for (int b = 8 + LO; b < TA_LOG; ++b)
+            if ((s >> (b - 8 - LO)) & 1)
+                off |= a.dep[b];
         return off;
     };
-    R bre[OPT], bim[OPT];  // separate scalars keep the prefetch in registers
-    auto load = [&](uint64_t base) {
-        if constexpr (CAN_PAIR) {
-            if (pair) {
-                const float4 *v4 = reinterpret_cast<const float4 *>(st);
-#pragma unroll
-                for (int s = 0; s < OPT / 2; ++s) {
-                    const float4 q = v4[(base + (off_lo | hi_off(s))) >> 1];
-                    bre[2 * s] = q.x;
-                    bim[2 * s] = q.y;
-                    bre[2 * s + 1] = q.z;
-                    bim[2 * s + 1] = q.w;
-                }
-                return;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < OPT; ++s) {
-            const C q = v[base + (off_lo | hi_off(s))];
-            bre[s] = q.x;
-            bim[s] = q.y;
-        }
-    };
-    auto to_lds = [&]() {
-        if constexpr (CAN_PAIR) {
-            if (pair) {
-#pragma unroll
-                for (int s = 0; s < OPT / 2; ++s) {
-                    const uint32_t x = 2u * uint32_t(s * kThreads + tid);
-                    C lo, hi;
-                    lo.x = bre[2 * s];
-                    lo.y = bim[2 * s];
-                    hi.x = bre[2 * s + 1];
-                    hi.y = bim[2 * s + 1];
-                    tile[swz(x)] = lo;
-                    tile[swz(x + 1)] = hi;
-                }
-                return;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < OPT; ++s) {
-            C q;
-            q.x = bre[s];
-            q.y = bim[s];
-            tile[swz(uint32_t(s * kThreads + tid))] = q;
-        }
-    };
-    auto store = [&](uint64_t base) {
-        if constexpr (CAN_PAIR) {
-            if (pair) {
-                float4 *v4 = reinterpret_cast<float4 *>(st);
-#pragma unroll
-                for (int s = 0; s < OPT / 2; ++s) {
-                    const uint32_t x = 2u * uint32_t(s * kThreads + tid);
-                    const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
-                    v4[(base + (off_lo | hi_off(s))) >> 1] = make_float4(lo.x, lo.y, hi.x, hi.y);
-                }
-                return;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < OPT; ++s)
-            v[base + (off_lo | hi_off(s))] = tile[swz(uint32_t(s * kThreads + tid))];
-    };
-
-    uint64_t o = blockIdx.x;
+    const uint64_t o = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
     if (o >= a.ntiles)
         return;
-    uint64_t base = insert_zeros(o, a.outer) | a.cmask;
-    load(base);
-    for (;;) {
-        to_lds();
-        __syncthreads();
-        const uint64_t o_next = o + gridDim.x;
-        const bool more = o_next < a.ntiles;
-        uint64_t base_next = 0;
-        if (more) {
-            base_next = insert_zeros(o_next, a.outer) | a.cmask;
-            load(base_next);
+    const uint64_t base = insert_zeros(o, a.outer) | a.cmask;
+    {
+        if constexpr (PAIR) {
+            const float4 *v4 = reinterpret_cast<const float4 *>(st);
+            float4 q[OPT / 2];
+#pragma unroll
+            for (int s = 0; s < OPT / 2; ++s)
+                q[s] = ld_nt(&v4[(base + offset(s)) >> 1]);
+#pragma unroll
+            for (int s = 0; s < OPT / 2; ++s) {
+                const uint32_t x = 2u * uint32_t(s * kThreads + tid);
+                tile[swz(x)] = make_float2(q[s].x, q[s].y);
+                tile[swz(x + 1)] = make_float2(q[s].z, q[s].w);
+            }
+        } else {
+            const C *v = reinterpret_cast<const C *>(st);
+            R qr[OPT], qi[OPT];  // scalar arrays: vector-typed ones go to scratch
+#pragma unroll
+            for (int s = 0; s < OPT; ++s) {
+                const C q = ld_nt(&v[base + offset(s)]);
+                qr[s] = q.x;
+                qi[s] = q.y;
+            }
+#pragma unroll
+            for (int s = 0; s < OPT; ++s) {
+                C q;
+                q.x = qr[s];
+                q.y = qi[s];
+                tile[swz(uint32_t(s * kThreads + tid))] = q;
+            }
         }
+        __syncthreads();
         compute(tile);
-        store(base);
-        if (!more)
-            break;
-        __syncthreads();  // stores have read the tile before it is refilled
-        o = o_next;
-        base = base_next;
+        if constexpr (PAIR) {
+            float4 *v4 = reinterpret_cast<float4 *>(st);
+#pragma unroll
+            for (int s = 0; s < OPT / 2; ++s) {
+                const uint32_t x = 2u * uint32_t(s * kThreads + tid);
+                const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
+                st_nt(&v4[(base + offset(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
+            }
+        } else {
+            C *v = reinterpret_cast<C *>(st);
+#pragma unroll
+            for (int s = 0; s < OPT; ++s)
+                st_nt(&v[base + offset(s)], tile[swz(uint32_t(s * kThreads + tid))]);
+        }
     }
 }
 
-// Number of workgroups that keep every CU busy for a persistent kernel.
-inline uint64_t persistent_grid(const void *kernel, uint64_t ntiles)
+// Whether a tile_sweep over these tile arguments moves 16-byte amplitude
+// pairs (complex64 with physical bit 0 in the tile).
+inline bool tile_pairs(int dtype, const TileArgs &a)
 {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu <= 0)
-        per_cu = 1;
-    const uint64_t g = uint64_t(cus) * uint64_t(per_cu);
-    return ntiles < g ? (ntiles > 0 ? ntiles : 1) : g;
+    return dtype == SV_C64 && a.dep[0] == 1;
+}
+
+// Grid of a tile_sweep launch: one workgroup per tile, at most 2^22 along x
+// (the thread count per dimension stays below 2^32), the rest along y.
+inline dim3 tile_grid(uint64_t ntiles)
+{
+    const uint64_t cap = uint64_t(1) << 22;
+    const uint64_t x = ntiles < 1 ? 1 : (ntiles > cap ? cap : ntiles);
+    const uint64_t y = (ntiles + x - 1) / x;
+    return dim3(uint32_t(x), uint32_t(y < 1 ? 1 : y));
 }
 
 inline uint64_t grid_for(uint64_t work, uint64_t per_block, uint64_t cap)

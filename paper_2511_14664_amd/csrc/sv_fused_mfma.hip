@@ -4,19 +4,22 @@
 // bits) by the block's 2^k x 2^k unitary: for a tile of G groups this is the
 // complex GEMM Y = U V with V the 2^k x G matrix of gathered amplitudes, the
 // dense contraction that gate fusion creates (paper Sec. 2.1: fusion raises
-// the linear-algebra dimension and the arithmetic intensity of a sweep).  In
-// real arithmetic Yr = Ur Vr - Ui Vi and Yi = Ur Vi + Ui Vr: four real
-// MFMA products per k-step.
+// the linear-algebra dimension and the arithmetic intensity of a sweep).
 //
-// complex64 / FP32: v_mfma_f32_32x32x2f32 (k = 5, 6) and v_mfma_f32_16x16x4f32
-// (k = 4), FP32 accumulation.  complex128 / FP64: v_mfma_f64_16x16x4f64.
+// The complex product takes three real GEMMs (Gauss):
+//     P1 = Ur Vr,  P2 = Ui Vi,  P3 = (Ur + Ui)(Vr + Vi),
+//     Yr = P1 - P2,  Yi = P3 - P1 - P2,
+// on v_mfma_f32_16x16x4f32 (complex64, FP32 accumulation) or
+// v_mfma_f64_16x16x4f64 (complex128).  At k = 5 a complex64 sweep carries
+// about as many matrix-core cycles as HBM cycles with four real products, so
+// the fourth product is worth removing; the extra rounding is a few units in
+// the last place of |U||V|.
 //
-// Data path per workgroup (4 waves): the tile (targets + m lowest free bits)
-// is loaded coalesced into LDS, each wave multiplies one (group set, row
-// block) pair with its U fragment held in registers for the whole kernel,
-// results go back to LDS and out with coalesced stores.  Operand layouts
-// (lane l): A[i = l % MT][kk = l / MT], B[kk = l / NT][j = l % NT]; the
-// accumulator layouts are given by acc_row().
+// Data path per workgroup (4 waves): one tile (the k targets + the lowest
+// free bits) is loaded from HBM into LDS, each wave multiplies its (group
+// set, row block) pairs, results go back to LDS and out (tile_sweep).
+// Operand layouts (lane l): A[i = l % 16][kk = l / 16], B[kk = l / 16][j =
+// l % 16]; the accumulator layouts are given by acc_row().
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -29,68 +32,39 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// log2 of the tile (amplitudes) for each precision and width, by measurement
+// on MI355X (28 qubits, targets low / middle / high / mixed): 32 KiB complex64
+// tiles give 1 KiB contiguous runs when the targets are high qubits; complex128
+// keeps 16-32 KiB tiles so that four workgroups stay resident per CU.
 template <typename R, int K>
-struct MfmaShape;
-
-// 16x16x4 shapes on 2048-amplitude tiles: the U fragment, the accumulators
-// and the prefetched next tile all stay in registers at 4+ waves per SIMD.
-// complex64
-template <>
-struct MfmaShape<float, 4> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
+struct MfmaTile {
+    static constexpr int TA_LOG = 12;
+};
+template <int K>
+struct MfmaTile<double, K> {
+    static constexpr int TA_LOG = 11;
 };
 template <>
-struct MfmaShape<float, 5> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
-};
-template <>
-struct MfmaShape<float, 6> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
-};
-// complex128
-template <>
-struct MfmaShape<double, 4> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
-};
-template <>
-struct MfmaShape<double, 5> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
-};
-template <>
-struct MfmaShape<double, 6> {
-    static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4, TA_LOG = 11;
+struct MfmaTile<double, 4> {
+    static constexpr int TA_LOG = 10;
 };
 
-template <typename R, int NACC>
-struct Acc;
+template <typename R>
+struct Acc4;
 template <>
-struct Acc<float, 16> {
-    using T = floatx16;
-};
-template <>
-struct Acc<float, 4> {
+struct Acc4<float> {
     using T = floatx4;
 };
 template <>
-struct Acc<double, 4> {
+struct Acc4<double> {
     using T = doublex4;
 };
 
-template <typename R, int MT, typename A>
-__device__ __forceinline__ A mfma(R a, R b, A c);
-
-template <>
-__device__ __forceinline__ floatx16 mfma<float, 32, floatx16>(float a, float b, floatx16 c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
-template <>
-__device__ __forceinline__ floatx4 mfma<float, 16, floatx4>(float a, float b, floatx4 c)
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-template <>
-__device__ __forceinline__ doublex4 mfma<double, 16, doublex4>(double a, double b, doublex4 c)
+__device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -108,85 +82,106 @@ __device__ __forceinline__ int acc_row(int l, int r)
         return 4 * (l / 16) + r;
 }
 
-template <typename R, int K>
+template <typename R, int K, int TA_LOG, bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_dense_mfma(R *__restrict__ st, const TileArgs a)
 {
     using C = typename CT<R>::C;
-    using S = MfmaShape<R, K>;
-    using AccT = typename Acc<R, S::NACC>::T;
+    using AccT = typename Acc4<R>::T;
+    constexpr int MT = 16, NT = 16, KT = 4;
     constexpr int D = 1 << K;
-    constexpr int TA = 1 << S::TA_LOG;
-    constexpr int M = S::TA_LOG - K;          // group bits
-    constexpr int NGS = (1 << M) / S::NT;     // group sets per tile
-    constexpr int NMT = D / S::MT;            // row blocks
-    constexpr int ITEMS = NGS * NMT;          // (group set, row block) pairs
+    constexpr int M = TA_LOG - K;          // group bits
+    constexpr int NGS = (1 << M) / NT;     // group sets per tile
+    constexpr int NMT = D / MT;            // row blocks
+    constexpr int ITEMS = NGS * NMT;       // (group set, row block) pairs
     constexpr int PER_WAVE = ITEMS / 4;
-    constexpr int NS = D / S::KT;             // k-steps
+    constexpr int NS = D / KT;             // k-steps
     static_assert(ITEMS % 4 == 0 && PER_WAVE >= 1, "tile shape");
     static_assert(4 % NMT == 0, "row blocks per tile must divide the 4 waves");
 
-    __shared__ C tile[TA];
+    __shared__ C tile[1 << TA_LOG];
     const C *U = reinterpret_cast<const C *>(a.U);
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-    const int ai = lane % S::MT, akk = lane / S::MT;   // A operand coordinates
-    const int bj = lane % S::NT, bkk = lane / S::NT;   // B operand coordinates
+    const int ai = lane % MT, akk = lane / MT;   // A operand coordinates
+    const int bj = lane % NT, bkk = lane / NT;   // B operand coordinates
 
-    // Each wave keeps one row block (its U fragment stays in registers) and
-    // takes every (4 / NMT)-th group set.
-    const int mt = wave % NMT;
+    // Each wave keeps one row block and takes every (4 / NMT)-th group set.
+    // Everything the products need besides the tile is fetched here, before
+    // the tile's loads, so that its latency hides under theirs: the U
+    // fragment of this lane, and the per-lane halves of the slot table.  Slot
+    // lookups split as xc[r] = xc[r_lo] | xc[r_hi] (the deposit of disjoint
+    // bits of r); the halves indexed by a compile-time or wave-uniform value
+    // are scalar loads.
+    const int mt = __builtin_amdgcn_readfirstlane(wave % NMT);
+    R ur[NS], ui[NS];
+    {
+        const C *Urow = U + size_t(mt * MT + ai) * D + akk;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const C u = Urow[s * KT];
+            ur[s] = u.x;
+            ui[s] = u.y;
+        }
+    }
+    constexpr bool F64 = std::is_same<R, double>::value;
+    const uint32_t xb_lane = a.xc[bkk];                            // k-step bits 0..1
+    const uint32_t xo_lane = a.xc[F64 ? (lane / 16) : 4 * (lane / 16)];  // output row, lane part
+    const uint32_t xo_mt = a.xc[mt * MT];                          // output row, row-block part
     uint32_t xg[PER_WAVE];
 #pragma unroll
     for (int j = 0; j < PER_WAVE; ++j)
-        xg[j] = group_slot(uint32_t((wave / NMT + (4 / NMT) * j) * S::NT + bj), a);
-    R ur[NS], ui[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const C u = U[size_t(mt * S::MT + ai) * D + (s * S::KT + akk)];
-        ur[s] = u.x;
-        ui[s] = u.y;
-    }
+        xg[j] = group_slot(uint32_t((wave / NMT + (4 / NMT) * j) * NT + bj), a);
 
-    tile_pipeline<R, S::TA_LOG>(st, a, tile, [&](C *t) {
-        AccT accr[PER_WAVE], acci[PER_WAVE];
+    tile_sweep<R, TA_LOG, PAIR>(st, a, tile, [&](C *t) {
+        AccT p1[PER_WAVE], p2[PER_WAVE], p3[PER_WAVE];
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
-            accr[j] = AccT{};
-            acci[j] = AccT{};
+            p1[j] = AccT{};
+            p2[j] = AccT{};
+            p3[j] = AccT{};
+        }
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const C x = t[swz(uint32_t(a.xc[s * S::KT + bkk]) | xg[j])];
-                accr[j] = mfma<R, S::MT, AccT>(ur[s], x.x, accr[j]);
-                acci[j] = mfma<R, S::MT, AccT>(ur[s], x.y, acci[j]);
-                accr[j] = mfma<R, S::MT, AccT>(ui[s], -x.y, accr[j]);
-                acci[j] = mfma<R, S::MT, AccT>(ui[s], x.x, acci[j]);
+        for (int s = 0; s < NS; ++s) {
+            const uint32_t xs = uint32_t(a.xc[s * KT]) | xb_lane;
+            const R us = ur[s] + ui[s];
+#pragma unroll
+            for (int j = 0; j < PER_WAVE; ++j) {
+                const C x = t[swz(xs | xg[j])];
+                p1[j] = mfma16(ur[s], x.x, p1[j]);
+                p2[j] = mfma16(ui[s], x.y, p2[j]);
+                p3[j] = mfma16(us, x.x + x.y, p3[j]);
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < PER_WAVE; ++j) {
+        for (int r = 0; r < 4; ++r) {
+            // acc_row<R, 16>(lane, r) = lane part | register part
+            const uint32_t xrow = xo_mt | xo_lane | uint32_t(a.xc[F64 ? 4 * r : r]);
 #pragma unroll
-            for (int r = 0; r < S::NACC; ++r) {
-                const int row = mt * S::MT + acc_row<R, S::MT>(lane, r);
+            for (int j = 0; j < PER_WAVE; ++j) {
                 C y;
-                y.x = accr[j][r];
-                y.y = acci[j][r];
-                t[swz(uint32_t(a.xc[row]) | xg[j])] = y;
+                y.x = p1[j][r] - p2[j][r];
+                y.y = p3[j][r] - p1[j][r] - p2[j][r];
+                t[swz(xrow | xg[j])] = y;
             }
         }
         __syncthreads();
     });
 }
 
-template <typename R, int K>
+template <typename R, int K, int TA_LOG = MfmaTile<R, K>::TA_LOG>
 hipError_t launch_mfma(void *st, int n, const void *d_U, const int *tgt, const int *ctl, int c, hipStream_t s)
 {
-    using S = MfmaShape<R, K>;
-    TileArgs a = make_tile_args(n, K, tgt, ctl, c, S::TA_LOG, d_U);
-    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_dense_mfma<R, K>), ~uint64_t(0) >> 1);
-    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
-    hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a);
+    if (n - c < TA_LOG)
+        return hipErrorInvalidValue;
+    TileArgs a = make_tile_args(n, K, tgt, ctl, c, TA_LOG, d_U);
+    const dim3 grid = tile_grid(a.ntiles);
+    if (tile_pairs(std::is_same<R, float>::value ? SV_C64 : SV_C128, a))
+        hipLaunchKernelGGL((k_dense_mfma<R, K, TA_LOG, std::is_same<R, float>::value>), grid, dim3(kThreads), 0, s,
+                           (R *)st, a);
+    else
+        hipLaunchKernelGGL((k_dense_mfma<R, K, TA_LOG, false>), grid, dim3(kThreads), 0, s, (R *)st, a);
     return hipGetLastError();
 }
 
@@ -211,7 +206,7 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &hi, bf16x8 &lo)
     }
 }
 
-template <int K>
+template <int K, bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_dense_bf16x3(float *__restrict__ st, const TileArgs a)
 {
     using C = float2;
@@ -249,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_bf16x3(float *__restrict__ s
         split8(im, uih[kc], uil[kc]);
     }
 
-    tile_pipeline<float, TA_LOG>(st, a, tile, [&](C *t) {
+    tile_sweep<float, TA_LOG, PAIR>(st, a, tile, [&](C *t) {
         floatx16 accr = {}, acci = {};
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
@@ -294,10 +289,14 @@ __global__ __launch_bounds__(kThreads) void k_dense_bf16x3(float *__restrict__ s
 template <int K>
 hipError_t launch_bf16x3(void *st, int n, const void *d_U, const int *tgt, const int *ctl, int c, hipStream_t s)
 {
+    if (n - c < 12)
+        return hipErrorInvalidValue;
     TileArgs a = make_tile_args(n, K, tgt, ctl, c, 12, d_U);
-    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_dense_bf16x3<K>), ~uint64_t(0) >> 1);
-    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
-    hipLaunchKernelGGL((k_dense_bf16x3<K>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+    const dim3 grid = tile_grid(a.ntiles);
+    if (tile_pairs(SV_C64, a))
+        hipLaunchKernelGGL((k_dense_bf16x3<K, true>), grid, dim3(kThreads), 0, s, (float *)st, a);
+    else
+        hipLaunchKernelGGL((k_dense_bf16x3<K, false>), grid, dim3(kThreads), 0, s, (float *)st, a);
     return hipGetLastError();
 }
 
@@ -313,15 +312,22 @@ hipError_t launch_dense_bf16x3(void *st, int n, const void *d_U, int k, const in
     }
 }
 
-namespace {
-}  // namespace
-
 int mfma_tile_log(int dtype, int k)
 {
-    if (k < 4 || k > 6)
-        return -1;
-    (void)dtype;
-    return MfmaShape<float, 4>::TA_LOG;
+    if (dtype == SV_C64) {
+        switch (k) {
+        case 4: return MfmaTile<float, 4>::TA_LOG;
+        case 5: return MfmaTile<float, 5>::TA_LOG;
+        case 6: return MfmaTile<float, 6>::TA_LOG;
+        default: return -1;
+        }
+    }
+    switch (k) {
+    case 4: return MfmaTile<double, 4>::TA_LOG;
+    case 5: return MfmaTile<double, 5>::TA_LOG;
+    case 6: return MfmaTile<double, 6>::TA_LOG;
+    default: return -1;
+    }
 }
 
 hipError_t launch_dense_mfma(void *st, int n, int dtype, const void *d_U, int k, const int *tgt, const int *ctl,

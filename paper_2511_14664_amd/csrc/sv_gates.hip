@@ -50,10 +50,37 @@ __global__ __launch_bounds__(kThreads) void k_reset(R *__restrict__ st, uint64_t
 }
 
 // ---------------------------------------------------------------------------
+// Global access of the one-target sweeps.  NT: streaming (nontemporal) hint,
+// used only when each store instruction covers whole 128-byte lines; where
+// lanes write every other half-line, the two halves must meet in L2 first.
+// ---------------------------------------------------------------------------
+template <bool NT, typename T>
+__device__ __forceinline__ T ldg(const T *p)
+{
+    if constexpr (NT)
+        return ld_nt(p);
+    else
+        return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stg(T *p, T v)
+{
+    if constexpr (NT)
+        st_nt(p, v);
+    else
+        *p = v;
+}
+
+// Access modes of a one-target sweep.
+enum : int {
+    kScalar = 0,  // one amplitude per access
+    kVec = 1,     // complex64, index bit 0 free: two adjacent groups per 16-byte access
+    kT0 = 2,      // complex64, target bit 0: the pair (i0, i0 + 1) is one 16-byte access
+};
+
+// ---------------------------------------------------------------------------
 // One-target dense gate (controls allowed).  Group g enumerates the indices
 // whose target bit is 0 and control bits are 1; pair (i0, i0 | 2^t).
-// VEC: complex64 with index bit 0 free -> each thread takes two adjacent
-// groups with 16-byte loads.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Gate1Args {
@@ -64,7 +91,7 @@ struct Gate1Args {
     R u[8];  // u00, u01, u10, u11 as (re, im)
 };
 
-template <typename R, bool VEC>
+template <typename R, int MODE, bool NT>
 __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Gate1Args<R> a)
 {
     using C = typename CT<R>::C;
@@ -74,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
     const uint64_t chunk = uint64_t(kThreads) * kItems;
     for (uint64_t u0 = uint64_t(blockIdx.x) * chunk + threadIdx.x; u0 - threadIdx.x < a.nunits;
          u0 += uint64_t(gridDim.x) * chunk) {
-    if constexpr (VEC) {
+    if constexpr (MODE == kVec) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 lo[kItems], hi[kItems];
         uint64_t ia[kItems], ib[kItems];
@@ -86,8 +113,8 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
                 const uint64_t i0 = insert_zeros(u << 1, a.im) | a.cmask;
                 ia[j] = i0 >> 1;
                 ib[j] = (i0 | a.tbit) >> 1;
-                lo[j] = v[ia[j]];
-                hi[j] = v[ib[j]];
+                lo[j] = ldg<NT>(&v[ia[j]]);
+                hi[j] = ldg<NT>(&v[ib[j]]);
             }
         }
 #pragma unroll
@@ -98,8 +125,29 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             C h0 = make_float2(hi[j].x, hi[j].y), h1 = make_float2(hi[j].z, hi[j].w);
             C a0 = cmad(m01, h0, cmul(m00, l0)), b0 = cmad(m11, h0, cmul(m10, l0));
             C a1 = cmad(m01, h1, cmul(m00, l1)), b1 = cmad(m11, h1, cmul(m10, l1));
-            v[ia[j]] = make_float4(a0.x, a0.y, a1.x, a1.y);
-            v[ib[j]] = make_float4(b0.x, b0.y, b1.x, b1.y);
+            stg<NT>(&v[ia[j]], make_float4(a0.x, a0.y, a1.x, a1.y));
+            stg<NT>(&v[ib[j]], make_float4(b0.x, b0.y, b1.x, b1.y));
+        }
+    } else if constexpr (MODE == kT0) {
+        float4 *v = reinterpret_cast<float4 *>(st);
+        float4 x[kItems];
+        uint64_t ia[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint64_t u = u0 + uint64_t(j) * kThreads;
+            ia[j] = ~uint64_t(0);
+            if (u < a.nunits) {
+                ia[j] = (insert_zeros(u, a.im) | a.cmask) >> 1;
+                x[j] = ldg<NT>(&v[ia[j]]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (ia[j] == ~uint64_t(0))
+                continue;
+            const C l = make_float2(x[j].x, x[j].y), h = make_float2(x[j].z, x[j].w);
+            const C y0 = cmad(m01, h, cmul(m00, l)), y1 = cmad(m11, h, cmul(m10, l));
+            stg<NT>(&v[ia[j]], make_float4(y0.x, y0.y, y1.x, y1.y));
         }
     } else {
         C *v = reinterpret_cast<C *>(st);
@@ -112,16 +160,16 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             if (u < a.nunits) {
                 ia[j] = insert_zeros(u, a.im) | a.cmask;
                 ib[j] = ia[j] | a.tbit;
-                lo[j] = v[ia[j]];
-                hi[j] = v[ib[j]];
+                lo[j] = ldg<NT>(&v[ia[j]]);
+                hi[j] = ldg<NT>(&v[ib[j]]);
             }
         }
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             if (ia[j] == ~uint64_t(0))
                 continue;
-            v[ia[j]] = cmad(m01, hi[j], cmul(m00, lo[j]));
-            v[ib[j]] = cmad(m11, hi[j], cmul(m10, lo[j]));
+            stg<NT>(&v[ia[j]], cmad(m01, hi[j], cmul(m00, lo[j])));
+            stg<NT>(&v[ib[j]], cmad(m11, hi[j], cmul(m10, lo[j])));
         }
     }
     }
@@ -141,7 +189,7 @@ struct Diag1Args {
     R d[4];  // d0, d1 as (re, im)
 };
 
-template <typename R, bool VEC>
+template <typename R, bool VEC, bool NT>
 __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Diag1Args<R> a)
 {
     using C = typename CT<R>::C;
@@ -160,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
             ia[j] = ~uint64_t(0);
             if (u < a.nunits) {
                 ia[j] = insert_zeros(u << 1, a.im) | a.fixed;
-                x[j] = v[ia[j] >> 1];
+                x[j] = ldg<NT>(&v[ia[j] >> 1]);
             }
         }
 #pragma unroll
@@ -169,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
                 continue;
             const C f = (ia[j] & a.tbit) ? d1 : d0;
             C p0 = cmul(f, make_float2(x[j].x, x[j].y)), p1 = cmul(f, make_float2(x[j].z, x[j].w));
-            v[ia[j] >> 1] = make_float4(p0.x, p0.y, p1.x, p1.y);
+            stg<NT>(&v[ia[j] >> 1], make_float4(p0.x, p0.y, p1.x, p1.y));
         }
     } else {
         C *v = reinterpret_cast<C *>(st);
@@ -181,17 +229,29 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
             ia[j] = ~uint64_t(0);
             if (u < a.nunits) {
                 ia[j] = insert_zeros(u, a.im) | a.fixed;
-                x[j] = v[ia[j]];
+                x[j] = ldg<NT>(&v[ia[j]]);
             }
         }
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             if (ia[j] == ~uint64_t(0))
                 continue;
-            v[ia[j]] = cmul((ia[j] & a.tbit) ? d1 : d0, x[j]);
+            stg<NT>(&v[ia[j]], cmul((ia[j] & a.tbit) ? d1 : d0, x[j]));
         }
     }
     }
+}
+
+// Whether a one-target sweep's store instructions cover whole 128-byte lines:
+// lanes are contiguous over the index bits below the lowest fixed or target
+// position that the access vector does not absorb.
+inline bool full_lines(const std::vector<int> &pos, int n, int absorbed, int amp_bytes)
+{
+    int p = n;
+    for (int q : pos)
+        if (q != absorbed)
+            p = std::min(p, q);
+    return (uint64_t(amp_bytes) << p) >= 128;
 }
 
 // ---------------------------------------------------------------------------
@@ -255,7 +315,7 @@ struct TileShape {
     static constexpr int GCH = (1 << M) / 64;
 };
 
-template <typename R, int K>
+template <typename R, int K, bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const TileArgs a)
 {
     using C = typename CT<R>::C;
@@ -276,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(R *__restrict__ st, const Til
         xg[j] = group_slot(uint32_t((p % S::GCH) * 64 + lane), a);
     }
 
-    tile_pipeline<R, S::TA_LOG>(st, a, tile, [&](C *t) {
+    tile_sweep<R, S::TA_LOG, PAIR>(st, a, tile, [&](C *t) {
         C acc[S::PAIRS][S::RB];
 #pragma unroll
         for (int j = 0; j < S::PAIRS; ++j) {
@@ -427,22 +487,30 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
     for (int j = 0; j < c; ++j)
         cmask |= uint64_t(1) << ctl[j];
     const uint64_t ngroups = uint64_t(1) << (n - 1 - c);
-    const bool vec = dtype == SV_C64 && std::find(pos.begin(), pos.end(), 0) == pos.end() && ngroups >= 2;
     if (dtype == SV_C64) {
+        const bool bit0_free = std::find(pos.begin(), pos.end(), 0) == pos.end();
+        const int mode = (bit0_free && ngroups >= 2) ? kVec : (t == 0 ? kT0 : kScalar);
+        const bool nt = full_lines(pos, n, mode == kT0 ? 0 : -1, 8);
         Gate1Args<float> a{};
         a.cmask = cmask;
         a.tbit = uint64_t(1) << t;
         a.im = make_insert_masks(pos);
         fill_u(a.u, U, 4);
-        a.nunits = vec ? ngroups / 2 : ngroups;
+        a.nunits = mode == kVec ? ngroups / 2 : ngroups;
         const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
-        if (vec)
-            hipLaunchKernelGGL((k_gate1<float, true>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
-        else
-            hipLaunchKernelGGL((k_gate1<float, false>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+        float *p = (float *)st;
+        switch (mode * 2 + (nt ? 1 : 0)) {
+        case kVec * 2 + 1: hipLaunchKernelGGL((k_gate1<float, kVec, true>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        case kVec * 2: hipLaunchKernelGGL((k_gate1<float, kVec, false>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        case kT0 * 2 + 1: hipLaunchKernelGGL((k_gate1<float, kT0, true>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        case kT0 * 2: hipLaunchKernelGGL((k_gate1<float, kT0, false>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        case kScalar * 2 + 1: hipLaunchKernelGGL((k_gate1<float, kScalar, true>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        default: hipLaunchKernelGGL((k_gate1<float, kScalar, false>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        }
     } else {
+        const bool nt = full_lines(pos, n, -1, 16);
         Gate1Args<double> a{};
         a.cmask = cmask;
         a.tbit = uint64_t(1) << t;
@@ -452,7 +520,10 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
         const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL((k_gate1<double, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+        if (nt)
+            hipLaunchKernelGGL((k_gate1<double, kScalar, true>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+        else
+            hipLaunchKernelGGL((k_gate1<double, kScalar, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
     }
     return hipGetLastError();
 }
@@ -472,6 +543,7 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
     const uint64_t nfree = uint64_t(1) << (n - int(pos.size()));
     const bool vec = dtype == SV_C64 && std::find(pos.begin(), pos.end(), 0) == pos.end() && t != 0 &&
                      nfree >= 2;
+    const bool nt = full_lines(pos, n, -1, dtype == SV_C64 ? 8 : 16);
     const cd dd[2] = {d0, d1};
     if (dtype == SV_C64) {
         Diag1Args<float> a{};
@@ -483,10 +555,15 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
         const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
-        if (vec)
-            hipLaunchKernelGGL((k_diag1<float, true>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+        float *p = (float *)st;
+        if (vec && nt)
+            hipLaunchKernelGGL((k_diag1<float, true, true>), dim3(grid), dim3(kThreads), 0, s, p, a);
+        else if (vec)
+            hipLaunchKernelGGL((k_diag1<float, true, false>), dim3(grid), dim3(kThreads), 0, s, p, a);
+        else if (nt)
+            hipLaunchKernelGGL((k_diag1<float, false, true>), dim3(grid), dim3(kThreads), 0, s, p, a);
         else
-            hipLaunchKernelGGL((k_diag1<float, false>), dim3(grid), dim3(kThreads), 0, s, (float *)st, a);
+            hipLaunchKernelGGL((k_diag1<float, false, false>), dim3(grid), dim3(kThreads), 0, s, p, a);
     } else {
         Diag1Args<double> a{};
         a.fixed = fixed;
@@ -497,7 +574,10 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
         const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
         if (check_grid(grid) != hipSuccess)
             return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL((k_diag1<double, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+        if (nt)
+            hipLaunchKernelGGL((k_diag1<double, false, true>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+        else
+            hipLaunchKernelGGL((k_diag1<double, false, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
     }
     return hipGetLastError();
 }
@@ -536,9 +616,11 @@ hipError_t launch_tile(void *st, int n, const void *d_U, const int *tgt, const i
     if (n - c - K < S::M)
         return launch_gatek_direct<R, K>(st, n, d_U, tgt, ctl, c, s);
     TileArgs a = make_tile_args(n, K, tgt, ctl, c, S::TA_LOG, d_U);
-    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_tile<R, K>), ~uint64_t(0) >> 1);
-    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
-    hipLaunchKernelGGL((k_tile<R, K>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a);
+    const dim3 grid = tile_grid(a.ntiles);
+    if (tile_pairs(std::is_same<R, float>::value ? SV_C64 : SV_C128, a))
+        hipLaunchKernelGGL((k_tile<R, K, std::is_same<R, float>::value>), grid, dim3(kThreads), 0, s, (R *)st, a);
+    else
+        hipLaunchKernelGGL((k_tile<R, K, false>), grid, dim3(kThreads), 0, s, (R *)st, a);
     return hipGetLastError();
 }
 
@@ -589,9 +671,9 @@ hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, cons
 
 namespace {
 
-// Bit-field exchange on the pipelined tile driver: the tile is read into LDS
+// Bit-field exchange on the LDS tile driver: the tile is read into LDS
 // in memory order, permuted inside LDS, and written back in memory order.
-template <typename R, int TLOG>
+template <typename R, int TLOG, bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_bitswap_p(R *__restrict__ st, const TileArgs a, int L, int w)
 {
     using C = typename CT<R>::C;
@@ -601,18 +683,24 @@ __global__ __launch_bounds__(kThreads) void k_bitswap_p(R *__restrict__ st, cons
     const int tid = threadIdx.x;
     const uint32_t wm = (1u << w) - 1u;
     const uint32_t fmask = (wm << L) | (wm << (L + w));
-    tile_pipeline<R, TLOG>(st, a, tile, [&](C *t) {
-        C tmp[OPT];
+    tile_sweep<R, TLOG, PAIR>(st, a, tile, [&](C *t) {
+        R tr[OPT], ti[OPT];
 #pragma unroll
         for (int s = 0; s < OPT; ++s) {
             const uint32_t y = uint32_t(s * kThreads + tid);
             const uint32_t f1 = (y >> L) & wm, f2 = (y >> (L + w)) & wm;
-            tmp[s] = t[swz((y & ~fmask) | (f1 << (L + w)) | (f2 << L))];
+            const C q = t[swz((y & ~fmask) | (f1 << (L + w)) | (f2 << L))];
+            tr[s] = q.x;
+            ti[s] = q.y;
         }
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < OPT; ++s)
-            t[swz(uint32_t(s * kThreads + tid))] = tmp[s];
+        for (int s = 0; s < OPT; ++s) {
+            C q;
+            q.x = tr[s];
+            q.y = ti[s];
+            t[swz(uint32_t(s * kThreads + tid))] = q;
+        }
         __syncthreads();
     });
 }
@@ -620,9 +708,12 @@ __global__ __launch_bounds__(kThreads) void k_bitswap_p(R *__restrict__ st, cons
 template <typename R, int TLOG>
 hipError_t launch_bitswap_p(void *st, const TileArgs &a, int L, int w, hipStream_t s)
 {
-    static const uint64_t full = persistent_grid(reinterpret_cast<const void *>(&k_bitswap_p<R, TLOG>), ~uint64_t(0) >> 1);
-    const uint64_t grid = std::min<uint64_t>(full, a.ntiles);
-    hipLaunchKernelGGL((k_bitswap_p<R, TLOG>), dim3(grid), dim3(kThreads), 0, s, (R *)st, a, L, w);
+    const dim3 grid = tile_grid(a.ntiles);
+    if (tile_pairs(std::is_same<R, float>::value ? SV_C64 : SV_C128, a))
+        hipLaunchKernelGGL((k_bitswap_p<R, TLOG, std::is_same<R, float>::value>), grid, dim3(kThreads), 0, s, (R *)st,
+                           a, L, w);
+    else
+        hipLaunchKernelGGL((k_bitswap_p<R, TLOG, false>), grid, dim3(kThreads), 0, s, (R *)st, a, L, w);
     return hipGetLastError();
 }
 

@@ -109,10 +109,12 @@ hipError_t launch_gather_logical(const void *st, void *dst, int n, int dtype, co
 
 // Readouts.  Scratch layout is the launcher's business; sizes are checked by
 // the caller through the *_scratch_doubles helpers.
-uint64_t marginal_scratch_doubles(int n, int m);
+uint64_t marginal_scratch_doubles(int n, int m, const int *phys_q);
 hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, int m,
                            double *d_scratch, double *d_out, hipStream_t s);
 uint64_t expect_scratch_doubles(int n);
+// Z strings per launch_expect_z call.
+int expect_z_batch();
 hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zmasks, int nt,
                            double *d_scratch, double *d_out, hipStream_t s);
 hipError_t launch_expect_xy(const void *st, int n, int dtype, uint64_t xmask, uint64_t yzmask,

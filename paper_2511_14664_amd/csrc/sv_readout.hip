@@ -152,48 +152,61 @@ __global__ __launch_bounds__(kThreads) void k_sum_rows(const double *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Z-string expectations: sum_i |a_i|^2 (-1)^popcount(i & z_t), up to 16
+// Z-string expectations: sum_i |a_i|^2 (-1)^popcount(i & z_t), up to kMaxZ
 // strings per pass.  part[t * gridDim + block].
+//
+// Every index a thread visits is h + threadIdx.x with h a multiple of 256
+// that is the same across the workgroup, so the sign factors as
+// (-1)^popcount(h & z_t) * (-1)^popcount(threadIdx.x & z_t).  The first
+// factors of all strings form one wave-uniform word per h: lane t computes
+// the parity for string t and a ballot collects them.  The second factor is
+// applied once at the end.  Per amplitude and string the work is one FP64
+// FMA with a scalar +-1 operand.
 // ---------------------------------------------------------------------------
-constexpr int kMaxZ = 16;
+constexpr int kMaxZ = 32;
 struct ExpZArgs {
     uint64_t nelem;
     int nt;
     uint64_t z[kMaxZ];
 };
 
-template <typename R>
+template <typename R, int NZ>
 __global__ __launch_bounds__(kThreads) void k_expect_z(const R *__restrict__ st, double *__restrict__ part,
                                                        const ExpZArgs a)
 {
+    static_assert(NZ <= 64 && NZ <= kMaxZ, "one string per lane");
     using C = typename CT<R>::C;
+    constexpr int U = 4;  // independent loads in flight per thread
     __shared__ double sh[4];
     const C *v = reinterpret_cast<const C *>(st);
-    double acc[kMaxZ];
+    const int lane = threadIdx.x & 63;
+    const uint64_t zl = lane < NZ ? a.z[lane] : 0;  // the string whose parity this lane reports
+    double acc[NZ];
 #pragma unroll
-    for (int t = 0; t < kMaxZ; ++t)
+    for (int t = 0; t < NZ; ++t)
         acc[t] = 0.0;
-    const uint64_t stride = uint64_t(gridDim.x) * kThreads;
-    // four independent loads in flight per thread
-    for (uint64_t i0 = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i0 < a.nelem; i0 += 4 * stride) {
-        double p[4];
-        uint64_t ii[4];
+    const uint64_t chunk = uint64_t(U) * kThreads;
+    for (uint64_t h0 = uint64_t(blockIdx.x) * chunk; h0 < a.nelem; h0 += uint64_t(gridDim.x) * chunk) {
+        double p[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ii[u] = i0 + uint64_t(u) * stride;
-            p[u] = ii[u] < a.nelem ? prob(v[ii[u]]) : 0.0;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = h0 + uint64_t(u) * kThreads + threadIdx.x;
+            p[u] = i < a.nelem ? prob(v[i]) : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < U; ++u) {
+            const uint64_t h = h0 + uint64_t(u) * kThreads;  // workgroup-uniform
+            const uint64_t sgn = __ballot((__popcll(h & zl) & 1) != 0);
 #pragma unroll
-            for (int t = 0; t < kMaxZ; ++t)
-                if (t < a.nt)
-                    acc[t] += (__popcll(ii[u] & a.z[t]) & 1) ? -p[u] : p[u];
+            for (int t = 0; t < NZ; ++t)
+                acc[t] = fma(((sgn >> t) & 1) ? -1.0 : 1.0, p[u], acc[t]);
+        }
     }
 #pragma unroll
-    for (int t = 0; t < kMaxZ; ++t) {
+    for (int t = 0; t < NZ; ++t) {
         if (t < a.nt) {
-            const double s = block_sum(acc[t], sh);
+            const double r = (__popc(threadIdx.x & uint32_t(a.z[t])) & 1) ? -acc[t] : acc[t];
+            const double s = block_sum(r, sh);
             if (threadIdx.x == 0)
                 part[uint64_t(t) * gridDim.x + blockIdx.x] = s;
         }
@@ -395,6 +408,135 @@ __global__ __launch_bounds__(kThreads) void k_marg_doubles(const double *__restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Marginal, stage 1 for bins with low index bits: fold each 4096-amplitude
+// segment (index bits 0..11) onto its 2^lb bins (the bin bits among bits
+// 0..11), summing 2^F consecutive segments per workgroup.
+// red[(block << lb) | bin] = sum over the workgroup's segments and the
+// segment's non-bin bits.  The probabilities of a segment go to LDS; each
+// bin is summed by G consecutive lanes over interleaved rest indices and
+// combined by a fixed shuffle tree, so the order of every sum is fixed.
+// ---------------------------------------------------------------------------
+constexpr int kSegLog = 12;
+struct FoldArgs {
+    uint32_t binmask;   // bin bits among the segment's 12 bits
+    uint32_t restmask;  // the other segment bits
+    int lb;             // popcount(binmask)
+    int F;              // log2 segments per workgroup
+};
+
+// x-th value (ascending) of the integers whose set bits lie in mask.
+__device__ __forceinline__ uint32_t deposit(uint32_t x, uint32_t mask)
+{
+    uint32_t r = 0;
+    for (uint32_t m = mask; x && m; m &= m - 1, x >>= 1)
+        if (x & 1)
+            r |= m & (~m + 1);
+    return r;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st, double *__restrict__ red,
+                                                        const FoldArgs a)
+{
+    constexpr int SEG = 1 << kSegLog;
+    constexpr int MAXB = SEG / kThreads;  // bins per thread when every thread owns whole bins
+    __shared__ double pr[SEG];
+    const int tid = threadIdx.x;
+    const int B = 1 << a.lb;
+    const int E = SEG >> a.lb;  // segment indices per bin
+    const int G = B >= kThreads ? 1 : min(64, kThreads / B);
+    const int gi = tid % G;
+    const int bin0 = tid / G;
+    const bool owner_mode = B >= kThreads;
+    double acc[MAXB];
+#pragma unroll
+    for (int k = 0; k < MAXB; ++k)
+        acc[k] = 0.0;
+    // rest enumeration for the group mode: x_r = deposit(r, restmask), r = gi, gi + G, ...
+    const uint32_t x_first = deposit(uint32_t(gi), a.restmask);
+    const uint32_t x_step = deposit(uint32_t(G), a.restmask);
+    const uint32_t d_bin0 = deposit(uint32_t(bin0), a.binmask);
+    for (uint32_t j = 0; j < (1u << a.F); ++j) {
+        const uint64_t base = ((uint64_t(blockIdx.x) << a.F) | j) << kSegLog;
+        if constexpr (std::is_same<R, float>::value) {
+            const float4 *v4 = reinterpret_cast<const float4 *>(st) + (base >> 1);
+#pragma unroll
+            for (int k = 0; k < SEG / (2 * kThreads); ++k) {
+                const float4 q = v4[tid + k * kThreads];
+                const int e = 2 * (tid + k * kThreads);
+                pr[e] = double(q.x) * q.x + double(q.y) * q.y;
+                pr[e + 1] = double(q.z) * q.z + double(q.w) * q.w;
+            }
+        } else {
+            const double2 *v2 = reinterpret_cast<const double2 *>(st) + base;
+#pragma unroll
+            for (int k = 0; k < SEG / kThreads; ++k) {
+                const double2 q = v2[tid + k * kThreads];
+                pr[tid + k * kThreads] = q.x * q.x + q.y * q.y;
+            }
+        }
+        __syncthreads();
+        if (owner_mode) {
+            // bins tid, tid + 256, ...; E <= 16 indices each, ascending
+#pragma unroll
+            for (int k = 0; k < MAXB; ++k) {
+                const int bin = tid + k * kThreads;
+                if (bin < B) {
+                    const uint32_t db = deposit(uint32_t(bin), a.binmask);
+                    double sacc = 0.0;
+                    uint32_t x = 0;
+                    for (int r = 0; r < E; ++r) {
+                        sacc += pr[db | x];
+                        x = ((x | ~a.restmask) + 1u) & a.restmask;
+                    }
+                    acc[k] += sacc;
+                }
+            }
+        } else if (bin0 < B) {
+            double sacc = 0.0;
+            uint32_t x = x_first;
+            for (int r = gi; r < E; r += G) {
+                sacc += pr[d_bin0 | x];
+                x = ((x | ~a.restmask) + x_step) & a.restmask;
+            }
+            for (int off = 1; off < G; off <<= 1)
+                sacc += __shfl_xor(sacc, off, 64);
+            acc[0] += sacc;
+        }
+        __syncthreads();
+    }
+    const uint64_t out0 = uint64_t(blockIdx.x) << a.lb;
+    if (owner_mode) {
+#pragma unroll
+        for (int k = 0; k < MAXB; ++k)
+            if (tid + k * kThreads < B)
+                red[out0 + tid + k * kThreads] = acc[k];
+    } else if (bin0 < B && gi == 0) {
+        red[out0 + bin0] = acc[0];
+    }
+}
+
+// Row-major bin sums over an array of doubles (stage 2 of the folded
+// marginal): block (chunk, x) sums one bin over a contiguous rest range.
+__global__ __launch_bounds__(kThreads) void k_marg_rmajor_d(const double *__restrict__ p, double *__restrict__ part,
+                                                            const MargArgs a)
+{
+    __shared__ double sh[4];
+    const uint64_t x = blockIdx.y;
+    const uint64_t xq = dep_x(x, a);
+    const uint64_t r0 = uint64_t(blockIdx.x) * a.per_chunk;
+    uint64_t r1 = r0 + a.per_chunk;
+    if (r1 > a.rest)
+        r1 = a.rest;
+    double acc = 0.0;
+    for (uint64_t r = r0 + threadIdx.x; r < r1; r += kThreads)
+        acc += p[xq | insert_zeros(r, a.rest_im)];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        part[x * a.chunks + blockIdx.x] = acc;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -429,12 +571,82 @@ MargPlan marg_plan(int n, int m)
 
 }  // namespace
 
-uint64_t marginal_scratch_doubles(int n, int m)
+namespace {
+
+// Route of a marginal: direct (row- or bin-major over the state), segment
+// sums (every bin bit >= 12), or a segment fold (some bin bit < 12) followed
+// by row- or bin-major sums over the folded array.
+struct MargRoute {
+    int kind;             // 0 direct, 1 segment sums, 2 fold
+    int sb;               // segment bits (kind 1)
+    FoldArgs fold;        // kind 2
+    int n2;               // bits of the folded array (kind 2)
+    std::vector<int> q2;  // bin positions in the folded array (kind 2)
+    MargPlan p2;          // plan over the folded array (kind 2)
+    uint64_t red;         // doubles of the folded / segment array
+    uint64_t scratch;     // doubles of scratch in all
+};
+
+constexpr uint64_t kMaxFolded = uint64_t(1) << 24;  // doubles
+
+MargRoute marg_route(int n, int m, const int *phys_q)
 {
-    MargPlan p = marg_plan(n, m);
-    const uint64_t old = p.rmajor ? (uint64_t(1) << m) * p.chunks : 1;
-    const uint64_t seg = n >= 12 ? (uint64_t(1) << (n - 12)) : 1;
-    return std::max(old, seg);
+    MargRoute r{};
+    int b0 = n;
+    uint32_t binmask = 0;
+    uint64_t hibins = 0;
+    for (int b = 0; b < m; ++b) {
+        b0 = std::min(b0, phys_q[b]);
+        if (phys_q[b] < kSegLog)
+            binmask |= 1u << phys_q[b];
+        else
+            hibins |= uint64_t(1) << phys_q[b];
+    }
+    if (n >= kSegLog && b0 >= kSegLog) {
+        r.kind = 1;
+        r.sb = std::min(b0, 16);
+        r.red = uint64_t(1) << (n - r.sb);
+        r.scratch = r.red;
+        return r;
+    }
+    const int lb = __builtin_popcount(binmask);
+    if (n >= kSegLog + 2 && lb <= 10) {
+        // fold F more segment bits per workgroup (non-bin bits just above 12)
+        // until the folded array is at most kMaxFolded doubles
+        int F = 0;
+        while (F < n - kSegLog - 1 && !((hibins >> (kSegLog + F)) & 1) &&
+               (uint64_t(1) << (n - kSegLog - F + lb)) > kMaxFolded)
+            ++F;
+        const int n2 = n - kSegLog - F + lb;
+        if ((uint64_t(1) << n2) <= 4 * kMaxFolded) {
+            r.kind = 2;
+            r.fold.binmask = binmask;
+            r.fold.restmask = ((1u << kSegLog) - 1u) & ~binmask;
+            r.fold.lb = lb;
+            r.fold.F = F;
+            r.n2 = n2;
+            r.red = uint64_t(1) << n2;
+            r.q2.resize(size_t(m));
+            for (int b = 0; b < m; ++b) {
+                const int q = phys_q[b];
+                r.q2[size_t(b)] = q < kSegLog ? __builtin_popcount(binmask & ((1u << q) - 1u)) : lb + q - kSegLog - F;
+            }
+            r.p2 = marg_plan(n2, m);
+            r.scratch = r.red + (r.p2.rmajor ? (uint64_t(1) << m) * r.p2.chunks : 0);
+            return r;
+        }
+    }
+    const MargPlan p = marg_plan(n, m);
+    r.kind = 0;
+    r.scratch = p.rmajor ? (uint64_t(1) << m) * p.chunks : 1;
+    return r;
+}
+
+}  // namespace
+
+uint64_t marginal_scratch_doubles(int n, int m, const int *phys_q)
+{
+    return std::max<uint64_t>(1, marg_route(n, m, phys_q).scratch);
 }
 
 hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, int m, double *d_scratch,
@@ -442,12 +654,9 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
 {
     if (m < 0 || m > kMaxQ || m > n)
         return hipErrorInvalidValue;
-    // segment path: every bin bit at or above bit 12
-    int b0 = n;
-    for (int b = 0; b < m; ++b)
-        b0 = std::min(b0, phys_q[b]);
-    if (n >= 12 && b0 >= 12) {
-        const int sb = std::min(b0, 16);
+    const MargRoute route = marg_route(n, m, phys_q);
+    if (route.kind == 1) {
+        const int sb = route.sb;
         const uint64_t nseg = uint64_t(1) << (n - sb);
         if (dtype == SV_C64)
             hipLaunchKernelGGL(k_segment_sums<float>, dim3(uint32_t(nseg)), dim3(kThreads), 0, s, (const float *)st,
@@ -470,6 +679,41 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
         a2.rest_im = make_masks(q2);
         const uint64_t g = std::min<uint64_t>((uint64_t(a2.nbins) + kThreads - 1) / kThreads, 1u << 20);
         hipLaunchKernelGGL(k_marg_doubles, dim3(g), dim3(kThreads), 0, s, d_scratch, d_out, a2);
+        return hipGetLastError();
+    }
+    if (route.kind == 2) {
+        const uint64_t nblk = uint64_t(1) << (n - kSegLog - route.fold.F);
+        if (dtype == SV_C64)
+            hipLaunchKernelGGL(k_marg_fold<float>, dim3(uint32_t(nblk)), dim3(kThreads), 0, s, (const float *)st,
+                               d_scratch, route.fold);
+        else
+            hipLaunchKernelGGL(k_marg_fold<double>, dim3(uint32_t(nblk)), dim3(kThreads), 0, s, (const double *)st,
+                               d_scratch, route.fold);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        MargArgs a2{};
+        a2.m = m;
+        a2.rest = uint64_t(1) << (route.n2 - m);
+        a2.nbins = uint32_t(1u << m);
+        for (int b = 0; b < m; ++b)
+            a2.qbit[b] = uint64_t(1) << route.q2[size_t(b)];
+        a2.rest_im = make_masks(route.q2);
+        a2.chunks = route.p2.chunks;
+        a2.per_chunk = route.p2.per_chunk;
+        const double *red = d_scratch;
+        if (route.p2.rmajor) {
+            double *part = d_scratch + route.red;
+            hipLaunchKernelGGL(k_marg_rmajor_d, dim3(a2.chunks, a2.nbins), dim3(kThreads), 0, s, red, part, a2);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+            const uint64_t g = (uint64_t(a2.nbins) + kThreads - 1) / kThreads;
+            hipLaunchKernelGGL(k_sum_rows, dim3(g), dim3(kThreads), 0, s, part, d_out, uint64_t(a2.nbins), a2.chunks);
+        } else {
+            const uint64_t g = std::min<uint64_t>((uint64_t(a2.nbins) + kThreads - 1) / kThreads, 1u << 20);
+            hipLaunchKernelGGL(k_marg_doubles, dim3(g), dim3(kThreads), 0, s, red, d_out, a2);
+        }
         return hipGetLastError();
     }
     MargArgs a{};
@@ -519,6 +763,11 @@ uint64_t expect_scratch_doubles(int n)
     return uint64_t(kMaxZ) * kExpGrid;
 }
 
+int expect_z_batch()
+{
+    return kMaxZ;
+}
+
 hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zmasks, int nt, double *d_scratch,
                            double *d_out, hipStream_t s)
 {
@@ -530,10 +779,24 @@ hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zma
     for (int t = 0; t < nt; ++t)
         a.z[t] = zmasks[t];
     const uint32_t grid = exp_grid(n);
-    if (dtype == SV_C64)
-        hipLaunchKernelGGL(k_expect_z<float>, dim3(grid), dim3(kThreads), 0, s, (const float *)st, d_scratch, a);
-    else
-        hipLaunchKernelGGL(k_expect_z<double>, dim3(grid), dim3(kThreads), 0, s, (const double *)st, d_scratch, a);
+    const dim3 g(grid), b(kThreads);
+    if (dtype == SV_C64) {
+        const float *p = (const float *)st;
+        if (nt <= 8)
+            hipLaunchKernelGGL((k_expect_z<float, 8>), g, b, 0, s, p, d_scratch, a);
+        else if (nt <= 16)
+            hipLaunchKernelGGL((k_expect_z<float, 16>), g, b, 0, s, p, d_scratch, a);
+        else
+            hipLaunchKernelGGL((k_expect_z<float, 32>), g, b, 0, s, p, d_scratch, a);
+    } else {
+        const double *p = (const double *)st;
+        if (nt <= 8)
+            hipLaunchKernelGGL((k_expect_z<double, 8>), g, b, 0, s, p, d_scratch, a);
+        else if (nt <= 16)
+            hipLaunchKernelGGL((k_expect_z<double, 16>), g, b, 0, s, p, d_scratch, a);
+        else
+            hipLaunchKernelGGL((k_expect_z<double, 32>), g, b, 0, s, p, d_scratch, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

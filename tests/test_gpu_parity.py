@@ -215,6 +215,9 @@ def test_marginals(dtype, n):
     with State(n, dtype) as s:
         ref = s.load(psi)
         qsets = [[], [0], [n - 1], list(range(n)), list(range(n))[::-1]]
+        # low bins (segment fold), low + high bins, one low bin, many low bins
+        qsets += [[q for q in Q if q < n] for Q in ([5, 4, 3, 2, 1, 0], [0, 13], [1], [3, 7, 11, 19],
+                                                      list(range(10)), [11, 0, 16, 6, 12])]
         for m in (2, 3, min(7, n), min(12, n)):
             qsets.append([int(x) for x in rng.permutation(n)[:m]])
         for Q in qsets:
@@ -222,6 +225,35 @@ def test_marginals(dtype, n):
             got = B.sv_probabilities(s.h, Q)
             want = oracle.probabilities(ref, Q)
             assert maxerr(got, want) <= 1e-12 * max(1.0, float(np.max(want))), Q
+
+
+def test_marginal_folding_several_segments_per_workgroup():
+    # 27 qubits with 10 bin bits below bit 12: the folded array would exceed
+    # 2^24 doubles, so each workgroup folds two 4096-amplitude segments
+    n = 27
+    rng = np.random.default_rng(5)
+    with State(n, B.SV_C64) as s:
+        B.sv_apply_circuit(s.h, W.layered_u3_pairing(n, 2, W.circuit_seed(3, 1), "cx"))
+        amp = s.host()
+        for Q in (list(range(10)), [9, 3, 0, 22, 1, 2, 4, 5, 6, 7, 8], [int(x) for x in rng.permutation(12)[:10]] + [26]):
+            say(f"marginal n={n} c64 Q={Q}")
+            got = B.sv_probabilities(s.h, Q)
+            want = oracle.probabilities(amp, Q)
+            assert maxerr(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_z_string_expectations_in_batches(dtype):
+    n = 20
+    rng = np.random.default_rng(11)
+    psi = W.random_state(n, 23)
+    terms = ["".join(rng.choice(list("IZ"), size=n)) for _ in range(45)] + ["I" * n]
+    with State(n, dtype) as s:
+        ref = s.load(psi)
+        for sub in (terms, terms[:7], terms[:16], terms[:33]):
+            got = B.sv_expect_pauli(s.h, sub)
+            want = np.array([oracle.expect_pauli(ref, t).real for t in sub])
+            assert maxerr(got, want) <= 1e-12
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
