@@ -174,27 +174,27 @@ int ensure_pinned(sv_state *h, uint64_t bytes)
     return SV_OK;
 }
 
-// Upload the matrices of all blocks with k >= 2 (in the state's precision)
-// into the device arena; offsets[i] = byte offset of block i (or -1).
-int upload_matrices(sv_state *h, const std::vector<Block> &blocks, std::vector<int64_t> &offsets)
+// Device bytes of a block's matrix in the state's precision (256-aligned),
+// 0 for one-target blocks (their 2x2 matrix travels as kernel arguments).
+uint64_t matrix_bytes(const sv_state *h, int k)
 {
-    offsets.assign(blocks.size(), -1);
-    const uint64_t S = amp_bytes(h->dtype);
-    uint64_t total = 0;
-    for (size_t i = 0; i < blocks.size(); ++i) {
-        if (blocks[i].k < 2)
-            continue;
-        offsets[i] = int64_t(total);
-        const uint64_t d = uint64_t(1) << blocks[i].k;
-        total += (d * d * S + 255) & ~uint64_t(255);
-    }
-    if (total == 0)
-        return SV_OK;
-    // staging buffer may still be read by the previous upload
+    if (k < 2)
+        return 0;
+    const uint64_t d = uint64_t(1) << k;
+    return (d * d * amp_bytes(h->dtype) + 255) & ~uint64_t(255);
+}
+
+// Make the pinned staging buffer and the device arena hold `total` bytes; the
+// staging buffer is free to overwrite on return (the previous call's uploads
+// have been read).
+int ensure_arena(sv_state *h, uint64_t total)
+{
     if (h->arena_pending) {
         HIP_TRY(hipEventSynchronize(h->arena_done));
         h->arena_pending = false;
     }
+    if (total == 0)
+        return SV_OK;
     if (total > h->h_arena_bytes) {
         if (h->h_arena)
             HIP_TRY(hipHostFree(h->h_arena));
@@ -221,29 +221,36 @@ int upload_matrices(sv_state *h, const std::vector<Block> &blocks, std::vector<i
         }
         h->arena_bytes = total;
     }
-    char *stage = static_cast<char *>(h->h_arena);
-    for (size_t i = 0; i < blocks.size(); ++i) {
-        if (offsets[i] < 0)
-            continue;
-        const Block &b = blocks[i];
-        const size_t dd = size_t(1) << (2 * b.k);
-        if (h->dtype == SV_C64) {
-            float *dst = reinterpret_cast<float *>(stage + offsets[i]);
-            for (size_t j = 0; j < dd; ++j) {
-                dst[2 * j] = float(b.U[j].real());
-                dst[2 * j + 1] = float(b.U[j].imag());
-            }
-        } else {
-            double *dst = reinterpret_cast<double *>(stage + offsets[i]);
-            for (size_t j = 0; j < dd; ++j) {
-                dst[2 * j] = b.U[j].real();
-                dst[2 * j + 1] = b.U[j].imag();
-            }
+    return SV_OK;
+}
+
+// Write block b's matrix into the staging buffer at byte offset off.
+void stage_matrix(sv_state *h, const Block &b, uint64_t off)
+{
+    char *stage = static_cast<char *>(h->h_arena) + off;
+    const size_t dd = size_t(1) << (2 * b.k);
+    if (h->dtype == SV_C64) {
+        float *dst = reinterpret_cast<float *>(stage);
+        for (size_t j = 0; j < dd; ++j) {
+            dst[2 * j] = float(b.U[j].real());
+            dst[2 * j + 1] = float(b.U[j].imag());
+        }
+    } else {
+        double *dst = reinterpret_cast<double *>(stage);
+        for (size_t j = 0; j < dd; ++j) {
+            dst[2 * j] = b.U[j].real();
+            dst[2 * j + 1] = b.U[j].imag();
         }
     }
-    HIP_TRY(hipMemcpyAsync(h->d_arena, h->h_arena, total, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipEventRecord(h->arena_done, h->stream));
-    h->arena_pending = true;
+}
+
+// Queue the copy of staging bytes [lo, hi) to the device arena.
+int upload_range(sv_state *h, uint64_t lo, uint64_t hi)
+{
+    if (hi <= lo)
+        return SV_OK;
+    HIP_TRY(hipMemcpyAsync(static_cast<char *>(h->d_arena) + lo, static_cast<const char *>(h->h_arena) + lo, hi - lo,
+                           hipMemcpyHostToDevice, h->stream));
     return SV_OK;
 }
 
@@ -314,75 +321,144 @@ Block pad_to_four(const sv_state *h, const Block &b)
     return o;
 }
 
+bool padded_exec(const sv_state *h, const Block &b, int precision)
+{
+    return b.k == 3 && pads_to_four(h->n, h->dtype, b.c, precision);
+}
+
+// Launch one block's sweep (its matrix, if any, already at dU on the device)
+// and account for it.
+int launch_block(sv_state *h, const Block &b, const void *dU, int precision, size_t index, sv_run_stats &acc)
+{
+    int pt[SV_MAX_TARGETS], pc[SV_MAX_CONTROLS];
+    for (int j = 0; j < b.k; ++j)
+        pt[j] = h->qmap[b.targets[j]];
+    for (int j = 0; j < b.c; ++j)
+        pc[j] = h->qmap[b.controls[j]];
+    sv_state::Pending pr{};
+    pr.rec.k = b.k;
+    pr.rec.c = b.c;
+    pr.rec.lowest_target = *std::min_element(pt, pt + b.k);
+    pr.rec.highest_target = *std::max_element(pt, pt + b.k);
+    pr.rec.num_gates = b.ngates;
+    pr.rec.bytes = block_bytes(h->n, h->dtype, b, pt, pc);
+    pr.rec.flops = block_flops(h->n, b);
+    pr.rec.kind = (b.k == 1 && b.diag) ? SV_SWEEP_DIAG1
+                  : (b.k == 1)         ? SV_SWEEP_GATE1
+                                       : dense_path(h->n, h->dtype, b.k, b.c, precision);
+    int rc = prof_begin(h, pr);
+    if (rc != SV_OK)
+        return rc;
+    hipError_t e;
+    if (b.k == 1 && b.diag) {
+        e = launch_diag1(h->d_state, h->n, h->dtype, b.U[0], b.U[3], pt[0], pc, b.c, h->stream);
+    } else if (b.k == 1) {
+        cd u[4] = {b.U[0], b.U[1], b.U[2], b.U[3]};
+        e = launch_gate1(h->d_state, h->n, h->dtype, u, pt[0], pc, b.c, h->stream);
+    } else {
+        e = launch_gatek(h->d_state, h->n, h->dtype, dU, b.k, pt, pc, b.c, precision, h->stream);
+    }
+    if (e != hipSuccess) {
+        set_error("gate sweep %zu launch failed: %s", index, hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    rc = prof_end(h, pr);
+    if (rc != SV_OK)
+        return rc;
+    acc.sweeps += 1;
+    if (b.ngates > 1)
+        acc.fused_blocks += 1;
+    acc.algorithmic_bytes += pr.rec.bytes;
+    acc.flops += pr.rec.flops;
+    return SV_OK;
+}
+
+// Run already formed blocks: all matrices in one upload, then every sweep.
 int run_blocks(sv_state *h, const std::vector<Block> &blocks_in, int precision, int ngates, sv_run_stats *st)
 {
-    std::vector<Block> padded;
-    bool any = false;
-    for (const Block &b : blocks_in)
-        if (b.k == 3 && b.c + 4 < h->n && dense_path(h->n, h->dtype, 4, b.c, precision) == SV_SWEEP_DENSE_MFMA)
-            any = true;
-    if (any) {
-        padded.reserve(blocks_in.size());
-        for (const Block &b : blocks_in)
-            padded.push_back((b.k == 3 && b.c + 4 < h->n &&
-                              dense_path(h->n, h->dtype, 4, b.c, precision) == SV_SWEEP_DENSE_MFMA)
-                                 ? pad_to_four(h, b)
-                                 : b);
+    std::vector<Block> blocks;
+    blocks.reserve(blocks_in.size());
+    std::vector<uint64_t> offs(blocks_in.size(), 0);
+    uint64_t total = 0;
+    for (size_t i = 0; i < blocks_in.size(); ++i) {
+        blocks.push_back(padded_exec(h, blocks_in[i], precision) ? pad_to_four(h, blocks_in[i]) : blocks_in[i]);
+        offs[i] = total;
+        total += matrix_bytes(h, blocks.back().k);
     }
-    const std::vector<Block> &blocks = any ? padded : blocks_in;
-    std::vector<int64_t> offs;
-    int rc = upload_matrices(h, blocks, offs);
+    int rc = ensure_arena(h, total);
+    if (rc != SV_OK)
+        return rc;
+    for (size_t i = 0; i < blocks.size(); ++i)
+        if (blocks[i].k >= 2)
+            stage_matrix(h, blocks[i], offs[i]);
+    rc = upload_range(h, 0, total);
     if (rc != SV_OK)
         return rc;
     sv_run_stats acc{};
     acc.gates = ngates;
-    for (size_t i = 0; i < blocks.size(); ++i) {
-        const Block &b = blocks[i];
-        int pt[SV_MAX_TARGETS], pc[SV_MAX_CONTROLS];
-        for (int j = 0; j < b.k; ++j)
-            pt[j] = h->qmap[b.targets[j]];
-        for (int j = 0; j < b.c; ++j)
-            pc[j] = h->qmap[b.controls[j]];
-        sv_state::Pending pr{};
-        pr.rec.k = b.k;
-        pr.rec.c = b.c;
-        pr.rec.lowest_target = *std::min_element(pt, pt + b.k);
-        pr.rec.highest_target = *std::max_element(pt, pt + b.k);
-        pr.rec.num_gates = b.ngates;
-        pr.rec.bytes = block_bytes(h->n, h->dtype, b, pt, pc);
-        pr.rec.flops = block_flops(h->n, b);
-        pr.rec.kind = (b.k == 1 && b.diag) ? SV_SWEEP_DIAG1
-                      : (b.k == 1)         ? SV_SWEEP_GATE1
-                                           : dense_path(h->n, h->dtype, b.k, b.c, precision);
-        rc = prof_begin(h, pr);
-        if (rc != SV_OK)
-            return rc;
-        hipError_t e;
-        if (b.k == 1 && b.diag) {
-            e = launch_diag1(h->d_state, h->n, h->dtype, b.U[0], b.U[3], pt[0], pc, b.c, h->stream);
-        } else if (b.k == 1) {
-            cd u[4] = {b.U[0], b.U[1], b.U[2], b.U[3]};
-            e = launch_gate1(h->d_state, h->n, h->dtype, u, pt[0], pc, b.c, h->stream);
-        } else {
-            const void *dU = static_cast<const char *>(h->d_arena) + offs[i];
-            e = launch_gatek(h->d_state, h->n, h->dtype, dU, b.k, pt, pc, b.c, precision, h->stream);
-        }
-        if (e != hipSuccess) {
-            set_error("gate sweep %zu launch failed: %s", i, hipGetErrorString(e));
-            return SV_EDEVICE;
-        }
-        rc = prof_end(h, pr);
-        if (rc != SV_OK)
-            return rc;
-        acc.sweeps += 1;
-        if (b.ngates > 1)
-            acc.fused_blocks += 1;
-        acc.algorithmic_bytes += pr.rec.bytes;
-        acc.flops += pr.rec.flops;
+    for (size_t i = 0; i < blocks.size() && rc == SV_OK; ++i)
+        rc = launch_block(h, blocks[i], static_cast<const char *>(h->d_arena) + offs[i], precision, i, acc);
+    if (total > 0) {
+        HIP_TRY(hipEventRecord(h->arena_done, h->stream));
+        h->arena_pending = true;
     }
-    if (st)
+    if (rc == SV_OK && st)
         *st = acc;
-    return SV_OK;
+    return rc;
+}
+
+// Run a grouped circuit: the blocks are formed, uploaded and launched in
+// chunks of 1, 2, 4, ... blocks, so the host fuses the later blocks while the
+// GPU is already sweeping the earlier ones.  Chunk c's matrices go up in one
+// copy queued before chunk c's sweeps (all on the handle's stream).
+int run_groups(sv_state *h, const std::vector<Block> &gates, const std::vector<Group> &groups, int precision,
+               int ngates, sv_run_stats *st)
+{
+    const size_t nb = groups.size();
+    std::vector<uint64_t> offs(nb, 0);
+    uint64_t total = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        const Group &g = groups[i];
+        const Block &first = gates[size_t(g.members[0])];
+        const int k = g.members.size() == 1 ? first.k : __builtin_popcountll(g.qmask);
+        const int c = g.members.size() == 1 ? first.c : 0;
+        const bool pad = k == 3 && pads_to_four(h->n, h->dtype, c, precision);
+        offs[i] = total;
+        total += matrix_bytes(h, pad ? 4 : k);
+    }
+    int rc = ensure_arena(h, total);
+    if (rc != SV_OK)
+        return rc;
+    sv_run_stats acc{};
+    acc.gates = ngates;
+    std::vector<const Block *> mem;
+    std::vector<Block> chunk;
+    for (size_t next = 0, size = 1; next < nb && rc == SV_OK; next += size, size *= 2) {
+        const size_t end = std::min(nb, next + size);
+        chunk.clear();
+        for (size_t i = next; i < end; ++i) {
+            mem.clear();
+            for (int m : groups[i].members)
+                mem.push_back(&gates[size_t(m)]);
+            Block b = fuse(mem, groups[i].qmask);
+            if (padded_exec(h, b, precision))
+                b = pad_to_four(h, b);
+            if (b.k >= 2)
+                stage_matrix(h, b, offs[i]);
+            chunk.push_back(std::move(b));
+        }
+        const uint64_t hi = end < nb ? offs[end] : total;
+        rc = upload_range(h, offs[next], hi);
+        for (size_t i = next; i < end && rc == SV_OK; ++i)
+            rc = launch_block(h, chunk[i - next], static_cast<const char *>(h->d_arena) + offs[i], precision, i, acc);
+    }
+    if (total > 0) {
+        HIP_TRY(hipEventRecord(h->arena_done, h->stream));
+        h->arena_pending = true;
+    }
+    if (rc == SV_OK && st)
+        *st = acc;
+    return rc;
 }
 
 int parse_pauli(const sv_state *h, const char *term, uint64_t &x, uint64_t &yz, int &ny)
@@ -652,31 +728,37 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
     sv_plan_opts o{};
     if (opts)
         o = *opts;
-    std::vector<Block> blocks;
-    if (o.mode == SV_PLAN_LEARNED && h->model) {
-        sv_plan_opts plain = o;
-        plain.mode = SV_PLAN_PLAIN;
-        std::vector<Block> gates_b;
-        rc = plan_circuit(h->n, h->dtype, gates, ngates, plain, gates_b);
-        if (rc == SV_OK && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {
-            set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
-            rc = SV_EINVAL;
-        }
-        if (rc != SV_OK)
-            return rc;
-        DeviceGuard dg(h->device);
-        int k = o.max_fused;
-        rc = rank_plans(h->model, h->n, h->dtype, gates_b, o.max_fused, o.precision, k, nullptr);
-        if (rc != SV_OK)
-            return rc;
-        blocks = plan_greedy(gates_b, k);
-    } else {
-        rc = plan_circuit(h->n, h->dtype, gates, ngates, o, blocks);
-        if (rc != SV_OK)
-            return rc;
+    // gates as one-gate blocks (validated), then grouped by the plan mode
+    sv_plan_opts plain = o;
+    plain.mode = SV_PLAN_PLAIN;
+    std::vector<Block> gates_b;
+    rc = plan_circuit(h->n, h->dtype, gates, ngates, plain, gates_b);
+    if (rc != SV_OK)
+        return rc;
+    if (o.mode < SV_PLAN_PLAIN || o.mode > SV_PLAN_LEARNED) {
+        set_error("unknown plan mode %d", o.mode);
+        return SV_EINVAL;
+    }
+    if (o.mode != SV_PLAN_PLAIN && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {
+        set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
+        return SV_EINVAL;
     }
     DeviceGuard dg(h->device);
-    return run_blocks(h, blocks, o.precision, ngates, stats);
+    std::vector<Group> groups;
+    if (o.mode == SV_PLAN_PLAIN) {
+        groups.reserve(gates_b.size());
+        for (size_t i = 0; i < gates_b.size(); ++i)
+            groups.push_back(Group{std::vector<int>(1, int(i)), qubit_mask(gates_b[i])});
+    } else {
+        int k = o.max_fused;
+        if (o.mode == SV_PLAN_LEARNED && h->model) {
+            rc = rank_plans(h->model, h->n, h->dtype, gates_b, o.max_fused, o.precision, k, nullptr);
+            if (rc != SV_OK)
+                return rc;
+        }
+        groups = group_greedy(gates_b, k);
+    }
+    return run_groups(h, gates_b, groups, o.precision, ngates, stats);
 }
 
 int sv_set_costmodel(sv_handle h, sv_costmodel_handle m)

@@ -363,7 +363,21 @@ int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gate
     std::vector<int> owner;
     std::vector<double> gbytes;
     for (int k = 1; k <= max_fused; ++k) {
-        for (const Block &b : plan_greedy(gates, k)) {
+        for (const Group &g : group_greedy(gates, k)) {
+            // the sweep this group becomes: its shape, padded to four targets
+            // where execution pads (the pad is the lowest free qubit >= 6)
+            Block b = group_shape(gates, g);
+            if (b.k == 3 && pads_to_four(n, dtype, b.c, precision)) {
+                uint64_t used = qubit_mask(b);
+                int pick = -1;
+                for (int q = 0; q < n && pick < 0; ++q)
+                    if (q >= 6 && !((used >> q) & 1))
+                        pick = q;
+                for (int q = 0; q < n && pick < 0; ++q)
+                    if (!((used >> q) & 1))
+                        pick = q;
+                b.targets[b.k++] = pick;
+            }
             float f[F];
             const sv_sweep_record r = block_record(n, dtype, b, precision);
             sweep_features(n, dtype, r, f);

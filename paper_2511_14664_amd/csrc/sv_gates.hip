@@ -656,6 +656,11 @@ int dense_path(int n, int dtype, int k, int c, int precision)
     return (n - c - k < m) ? SV_SWEEP_GROUP : SV_SWEEP_DENSE;
 }
 
+bool pads_to_four(int n, int dtype, int c, int precision)
+{
+    return c + 4 < n && dense_path(n, dtype, 4, c, precision) == SV_SWEEP_DENSE_MFMA;
+}
+
 hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, const int *tgt,
                         const int *ctl, int c, int precision, hipStream_t s)
 {

@@ -63,6 +63,9 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax);
 // Fuse gates into one block on the qubits of qmask (targets ascending); a
 // single member is returned unchanged.
 Block fuse(const std::vector<const Block *> &members, uint64_t qmask);
+// The block a group becomes, without its matrix when it spans two or more
+// qubits (targets, controls, width, gate count and diagonality only).
+Block group_shape(const std::vector<Block> &gates, const Group &g);
 uint64_t qubit_mask(const Block &b);
 
 // Algorithmic HBM bytes / flops of a sweep (physical bit positions).
@@ -100,6 +103,9 @@ hipError_t launch_dense_mfma(void *st, int n, int dtype, const void *d_U, int k,
 hipError_t launch_dense_bf16x3(void *st, int n, const void *d_U, int k, const int *tgt, const int *ctl, int c,
                                hipStream_t s);
 // Which kernel launch_gatek uses (an sv_sweep_kind).
+// Whether a dense 3-target block runs as a 4-target one (U (x) I) because the
+// matrix-core path then applies.
+bool pads_to_four(int n, int dtype, int c, int precision);
 int dense_path(int n, int dtype, int k, int c, int precision);
 
 hipError_t launch_bitswap(void *st, int n, int dtype, int lo, int hi, int w, hipStream_t s);

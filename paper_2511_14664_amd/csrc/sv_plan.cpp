@@ -174,9 +174,13 @@ std::vector<Block> plan_plain(const std::vector<Block> &gates)
     return gates;
 }
 
-// Apply gate `g` (qubits given as positions inside a kb-bit block index) to
-// every column of the d x d column-major matrix M:  M <- G M.
-static void left_multiply(std::vector<cd> &M, int kb, const Block &g, const int *tpos, const int *cpos)
+// Left-multiply the d x d matrix M (row-major, split into real and imaginary
+// parts) by gate g acting on block positions tpos (targets) and cpos
+// (controls): for every row set {base | off_j} (target bits of base zero,
+// control bits one) the rows mix through g's matrix.  The row updates run
+// across all d columns at once, so the inner loops are unit-stride and
+// vectorise; complex products are written out (no library complex calls).
+static void left_multiply(double *Mr, double *Mi, int kb, const Block &g, const int *tpos, const int *cpos)
 {
     const int d = 1 << kb, kg = g.k, dg = 1 << kg;
     int mt = 0, mc = 0;
@@ -184,26 +188,72 @@ static void left_multiply(std::vector<cd> &M, int kb, const Block &g, const int 
         mt |= 1 << tpos[b];
     for (int j = 0; j < g.c; ++j)
         mc |= 1 << cpos[j];
-    cd v[64];
-    int idx[64];
-    for (int col = 0; col < d; ++col) {
-        cd *a = &M[size_t(col) * d];
-        for (int base = 0; base < d; ++base) {
-            if ((base & mt) != 0 || (base & mc) != mc)
-                continue;
+    int off[64];
+    for (int j = 0; j < dg; ++j) {
+        off[j] = 0;
+        for (int b = 0; b < kg; ++b)
+            if ((j >> b) & 1)
+                off[j] |= 1 << tpos[b];
+    }
+    double ur[64 * 64], ui[64 * 64];
+    for (int j = 0; j < dg * dg; ++j) {
+        ur[j] = g.U[size_t(j)].real();
+        ui[j] = g.U[size_t(j)].imag();
+    }
+    for (int base = 0; base < d; ++base) {
+        if ((base & mt) != 0 || (base & mc) != mc)
+            continue;
+        if (dg == 2) {
+            double *r0 = Mr + size_t(base | off[0]) * d, *i0 = Mi + size_t(base | off[0]) * d;
+            double *r1 = Mr + size_t(base | off[1]) * d, *i1 = Mi + size_t(base | off[1]) * d;
+            for (int c = 0; c < d; ++c) {
+                const double ar = r0[c], ai = i0[c], br = r1[c], bi = i1[c];
+                r0[c] = (ur[0] * ar - ui[0] * ai) + (ur[1] * br - ui[1] * bi);
+                i0[c] = (ur[0] * ai + ui[0] * ar) + (ur[1] * bi + ui[1] * br);
+                r1[c] = (ur[2] * ar - ui[2] * ai) + (ur[3] * br - ui[3] * bi);
+                i1[c] = (ur[2] * ai + ui[2] * ar) + (ur[3] * bi + ui[3] * br);
+            }
+            continue;
+        }
+        if (dg == 4) {
+            double *r[4], *im[4];
+            for (int j = 0; j < 4; ++j) {
+                r[j] = Mr + size_t(base | off[j]) * d;
+                im[j] = Mi + size_t(base | off[j]) * d;
+            }
+            for (int c = 0; c < d; ++c) {
+                const double a0 = r[0][c], b0 = im[0][c], a1 = r[1][c], b1 = im[1][c];
+                const double a2 = r[2][c], b2 = im[2][c], a3 = r[3][c], b3 = im[3][c];
+                for (int q = 0; q < 4; ++q) {
+                    const double *xr = ur + 4 * q, *xi = ui + 4 * q;
+                    r[q][c] = ((xr[0] * a0 - xi[0] * b0) + (xr[1] * a1 - xi[1] * b1)) +
+                              ((xr[2] * a2 - xi[2] * b2) + (xr[3] * a3 - xi[3] * b3));
+                    im[q][c] = ((xr[0] * b0 + xi[0] * a0) + (xr[1] * b1 + xi[1] * a1)) +
+                               ((xr[2] * b2 + xi[2] * a2) + (xr[3] * b3 + xi[3] * a3));
+                }
+            }
+            continue;
+        }
+        double *rr[64], *ri[64];
+        for (int j = 0; j < dg; ++j) {
+            rr[j] = Mr + size_t(base | off[j]) * d;
+            ri[j] = Mi + size_t(base | off[j]) * d;
+        }
+        double vr[64], vi[64];
+        for (int c = 0; c < d; ++c) {
             for (int j = 0; j < dg; ++j) {
-                int off = 0;
-                for (int b = 0; b < kg; ++b)
-                    if ((j >> b) & 1)
-                        off |= 1 << tpos[b];
-                idx[j] = base | off;
-                v[j] = a[idx[j]];
+                vr[j] = rr[j][c];
+                vi[j] = ri[j][c];
             }
             for (int r = 0; r < dg; ++r) {
-                cd acc(0.0, 0.0);
-                for (int c2 = 0; c2 < dg; ++c2)
-                    acc += g.U[size_t(r) * dg + c2] * v[c2];
-                a[idx[r]] = acc;
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < dg; ++j) {
+                    const double a = ur[r * dg + j], b = ui[r * dg + j];
+                    sr += a * vr[j] - b * vi[j];
+                    si += a * vi[j] + b * vr[j];
+                }
+                rr[r][c] = sr;
+                ri[r][c] = si;
             }
         }
     }
@@ -224,9 +274,9 @@ Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
     out.k = kb;
     out.c = 0;
     const int d = 1 << kb;
-    std::vector<cd> M(size_t(d) * d, cd(0.0, 0.0));  // column-major
+    std::vector<double> Mr(size_t(d) * d, 0.0), Mi(size_t(d) * d, 0.0);  // row-major
     for (int i = 0; i < d; ++i)
-        M[size_t(i) * d + i] = 1.0;
+        Mr[size_t(i) * d + i] = 1.0;
     bool diag = true;
     int ng = 0;
     for (const Block *g : members) {
@@ -235,16 +285,37 @@ Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
             tpos[b] = pos[g->targets[b]];
         for (int j = 0; j < g->c; ++j)
             cpos[j] = pos[g->controls[j]];
-        left_multiply(M, kb, *g, tpos, cpos);
+        left_multiply(Mr.data(), Mi.data(), kb, *g, tpos, cpos);
         diag = diag && g->diag;
         ng += g->ngates;
     }
-    out.U.assign(size_t(d) * d, cd(0.0, 0.0));
-    for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c)
-            out.U[size_t(r) * d + c] = M[size_t(c) * d + r];
+    out.U.resize(size_t(d) * d);
+    for (size_t j = 0; j < out.U.size(); ++j)
+        out.U[j] = cd(Mr[j], Mi[j]);
     out.diag = diag;
     out.ngates = ng;
+    return out;
+}
+
+Block group_shape(const std::vector<Block> &gates, const Group &g)
+{
+    if (g.members.size() == 1)
+        return gates[size_t(g.members[0])];
+    if (__builtin_popcountll(g.qmask) < 2) {
+        std::vector<const Block *> mem;
+        for (int i : g.members)
+            mem.push_back(&gates[size_t(i)]);
+        return fuse(mem, g.qmask);
+    }
+    Block out;
+    for (int q = 0; q < 64; ++q)
+        if ((g.qmask >> q) & 1)
+            out.targets[out.k++] = q;
+    out.diag = true;
+    for (int i : g.members) {
+        out.diag = out.diag && gates[size_t(i)].diag;
+        out.ngates += gates[size_t(i)].ngates;
+    }
     return out;
 }
 
