@@ -37,7 +37,8 @@ def parse():
                          "SU(4) circuit, depth 40, greedy vs learned fusion plan")
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
-    ap.add_argument("--mode", choices=["plain", "greedy", "learned"], default="greedy")
+    ap.add_argument("--mode", choices=["plain", "greedy", "learned", "passes"], default="passes")
+    ap.add_argument("--pass-qubits", type=int, default=8, help="qubits per LDS pass (--mode passes)")
     ap.add_argument("--max-fused", type=int, default=5)
     ap.add_argument("--precision", choices=["native", "bf16x3"], default="native")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (unfused) comparison run")
@@ -82,9 +83,10 @@ def main():
     S = 8 if dtype == B.SV_C64 else 16
     gates = W.layered_u3_pairing(n, 20, W.circuit_seed(2, 1), "cx_or_cz")
     circ = B.Circuit(gates)
-    mode = {"plain": B.SV_PLAN_PLAIN, "greedy": B.SV_PLAN_GREEDY, "learned": B.SV_PLAN_LEARNED}[args.mode]
+    mode = {"plain": B.SV_PLAN_PLAIN, "greedy": B.SV_PLAN_GREEDY, "learned": B.SV_PLAN_LEARNED,
+            "passes": B.SV_PLAN_PASSES}[args.mode]
     prec = B.SV_PREC_BF16X3 if args.precision == "bf16x3" else B.SV_PREC_NATIVE
-    opts = B.make_opts(mode, args.max_fused, prec)
+    opts = B.make_opts(mode, args.max_fused, prec, args.pass_qubits if args.mode == "passes" else 0)
     marg_q = list(range(n - 10, n))
     terms = W.hea_z_terms(n)[: 2 * 16]
     uni = W.uniforms(7, 1000)
@@ -129,7 +131,8 @@ def main():
     # per-kernel-class totals from the live HIP-event records
     classes = {}
     for r in recs:
-        key = (r["kind_name"], r["k"])
+        # every pass moves the whole state whatever its width: one class
+        key = (r["kind_name"], None if r["kind_name"] == "pass" else r["k"])
         c = classes.setdefault(key, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0})
         c["ms"] += r["ms"]
         c["bytes"] += r["bytes"]
@@ -142,7 +145,8 @@ def main():
     avg_ms = dom["ms"] / dom["launches"]
     avg_bytes = dom["bytes"] / dom["launches"]
     achieved = avg_bytes / (avg_ms / 1e3) / 1e9
-    breakdown = {f"{k[0]}_k{k[1]}": {"launches_per_step": v["launches"] / args.steps,
+    cname = lambda k: k[0] if k[1] is None else f"{k[0]}_k{k[1]}"
+    breakdown = {cname(k): {"launches_per_step": v["launches"] / args.steps,
                                       "ms_per_step": round(v["ms"] / args.steps, 4),
                                       "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
                  for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms"])}
@@ -226,8 +230,10 @@ def main():
         "dtype": "fp32" if dtype == B.SV_C64 else "fp64",
         "data": "synthetic",
         "config": {"workload": f"{n}-qubit random layered circuit (U3 on every qubit + CNOT/CZ on a random "
-                               f"matching, depth 20, {len(gates)} gates), {args.dtype}, {args.mode} fusion "
-                               f"<= {args.max_fused} qubits, + 6-bit index exchange, 10-qubit marginal, "
+                               f"matching, depth 20, {len(gates)} gates), {args.dtype}, "
+                               + (f"LDS passes of <= {args.pass_qubits} qubits (fused 4-qubit blocks on the matrix "
+                                  f"cores)" if args.mode == "passes" else f"{args.mode} fusion <= {args.max_fused} qubits")
+                               + f", + 6-bit index exchange, 10-qubit marginal, "
                                f"{len(terms)} Z-string expectations, 1000 shots",
                    "qubits": n, "state_bytes": S << n, "gates": len(gates),
                    "sweeps_per_step": stats["sweeps"] if stats else None, "parallelism": "single GPU"},
@@ -235,7 +241,7 @@ def main():
         "sweep_ms_per_step": round(sweep_ms, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"{dom_key[0]} k={dom_key[1]}", "avg_launch_ms": round(avg_ms, 5),
+                     "kernel": cname(dom_key), "avg_launch_ms": round(avg_ms, 5),
                      "bytes_per_launch": avg_bytes},
         "kernels": breakdown,
         "plain": plain,
@@ -247,23 +253,30 @@ def main():
 
 
 def counter_traffic(dom_key, n, dtype, args):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy), used only
-    while the kernel's sources are byte-identical to the profiled ones."""
+    """HBM bytes per launch of the dominant kernel class from a committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the same workload (calibrated
+    against a plain copy), used only while the kernel's sources are
+    byte-identical to the profiled ones."""
+    import glob
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "dense_mfma_k5_28q_c64_layered.json")
-    if dom_key != ("dense_mfma", 5) or n != 28 or dtype != 0 or args.precision != "native" or not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    h = hashlib.sha256()
-    for src in d["kernel_sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != d["kernel_sources_sha256"]:
-        return None
-    return round(d["kernels"][d["kernel"]], 1)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.json"))):
+        with open(path) as f:
+            d = json.load(f)
+        sweep = d.get("sweep")
+        if sweep is None or (sweep[0], sweep[1]) != (dom_key[0], dom_key[1]):
+            continue
+        if d.get("qubits") != n or d.get("dtype") != ("c64" if dtype == 0 else "c128") or \
+                d.get("precision") != args.precision or d.get("mode") != args.mode:
+            continue
+        h = hashlib.sha256()
+        for src in d["kernel_sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != d["kernel_sources_sha256"]:
+            continue
+        return round(d["kernels"][d["kernel"]], 1)
+    return None
 
 
 def train_cost_model(B, W):
@@ -360,8 +373,8 @@ def bench_share(args):
             seg.append(op)
     if seg:
         segs.append((B.Circuit(seg), None))
-    mode = B.SV_PLAN_PLAIN if args.mode == "plain" else B.SV_PLAN_GREEDY
-    opts = B.make_opts(mode, args.max_fused)
+    mode = {"plain": B.SV_PLAN_PLAIN, "passes": B.SV_PLAN_PASSES}.get(args.mode, B.SV_PLAN_GREEDY)
+    opts = B.make_opts(mode, args.max_fused, B.SV_PREC_NATIVE, args.pass_qubits if args.mode == "passes" else 0)
     torch.cuda.empty_cache()
     h = B.sv_create(n, dtype)
     ngates = W.gate_count(ops)

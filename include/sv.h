@@ -95,8 +95,14 @@ typedef struct sv_gate {
 typedef enum sv_plan_mode {
     SV_PLAN_PLAIN = 0,    /* one sweep per gate */
     SV_PLAN_GREEDY = 1,   /* greedy dependency-aware fusion into <= max_fused-qubit blocks */
-    SV_PLAN_LEARNED = 2   /* candidate fusion plans ranked by the attached cost model;
+    SV_PLAN_LEARNED = 2,  /* candidate fusion plans ranked by the attached cost model;
                              falls back to SV_PLAN_GREEDY without a usable model */
+    SV_PLAN_PASSES = 3    /* greedy dependency-aware grouping into passes of <= pass_qubits
+                             qubits; a pass moves the state through LDS once and applies
+                             its gates there as a sequence of fused 4-qubit blocks on the
+                             matrix cores (gates on more than 4 qubits, and states below
+                             the pass tile, run as greedy <= max_fused-qubit sweeps).
+                             sv_apply_circuit only. */
 } sv_plan_mode;
 
 typedef enum sv_precision {
@@ -108,10 +114,10 @@ typedef enum sv_precision {
 } sv_precision;
 
 typedef struct sv_plan_opts {
-    int32_t mode;        /* sv_plan_mode */
-    int32_t max_fused;   /* 1..6: widest fused block (greedy / learned) */
-    int32_t precision;   /* sv_precision */
-    int32_t reserved;    /* must be 0 */
+    int32_t mode;         /* sv_plan_mode */
+    int32_t max_fused;    /* 1..6: widest fused block (greedy / learned; passes' fallback) */
+    int32_t precision;    /* sv_precision */
+    int32_t pass_qubits;  /* SV_PLAN_PASSES: 4..8 qubits per pass, 0 for 8; else must be 0 */
 } sv_plan_opts;
 
 /* Counters filled by sv_apply_circuit / sv_apply_plan (may be NULL). */
@@ -216,7 +222,8 @@ typedef enum sv_sweep_kind {
     SV_SWEEP_DENSE_MFMA = 3, /* k-target dense block on the matrix cores */
     SV_SWEEP_GROUP = 4,    /* k-target dense block, one group per thread (small n) */
     SV_SWEEP_BITSWAP = 5,  /* index-bit field exchange */
-    SV_SWEEP_DENSE_BF16X3 = 6 /* complex64 k-target block, three-term BF16 split on the matrix cores */
+    SV_SWEEP_DENSE_BF16X3 = 6, /* complex64 k-target block, three-term BF16 split on the matrix cores */
+    SV_SWEEP_PASS = 7      /* LDS pass: fused 4-qubit blocks on the pass's qubits (k = pass qubits) */
 } sv_sweep_kind;
 
 /* One timed sweep (physical bit positions). */

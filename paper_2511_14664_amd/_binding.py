@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4
 SV_C64, SV_C128 = 0, 1
-SV_PLAN_PLAIN, SV_PLAN_GREEDY, SV_PLAN_LEARNED = 0, 1, 2
+SV_PLAN_PLAIN, SV_PLAN_GREEDY, SV_PLAN_LEARNED, SV_PLAN_PASSES = 0, 1, 2, 3
 SV_PREC_NATIVE, SV_PREC_BF16X3 = 0, 1
 SV_MAX_TARGETS, SV_MAX_CONTROLS = 6, 8
 
@@ -45,7 +45,7 @@ class sv_gate(ctypes.Structure):
 
 class sv_plan_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_fused", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("pass_qubits", ctypes.c_int32)]
 
 
 class sv_run_stats(ctypes.Structure):
@@ -143,8 +143,9 @@ class Circuit:
                 s.matrix = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_opts(mode: int = SV_PLAN_PLAIN, max_fused: int = 5, precision: int = SV_PREC_NATIVE) -> sv_plan_opts:
-    return sv_plan_opts(mode, max_fused, precision, 0)
+def make_opts(mode: int = SV_PLAN_PLAIN, max_fused: int = 5, precision: int = SV_PREC_NATIVE,
+              pass_qubits: int = 0) -> sv_plan_opts:
+    return sv_plan_opts(mode, max_fused, precision, pass_qubits)
 
 
 def _as_circuit(gates) -> Circuit:
@@ -301,7 +302,7 @@ class sv_sweep_record(ctypes.Structure):
 
 
 SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap",
-              6: "dense_bf16x3"}
+              6: "dense_bf16x3", 7: "pass"}
 
 _lib.sv_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
 _lib.sv_profile_enable.restype = ctypes.c_int

@@ -15,6 +15,7 @@ SOURCES = [
     "sv_gates.hip",
     "sv_readout.hip",
     "sv_fused_mfma.hip",
+    "sv_pass.hip",
     "sv_batch.hip",
     "sv_batch_host.cpp",
     "sv_costmodel.hip",

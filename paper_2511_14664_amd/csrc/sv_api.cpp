@@ -461,6 +461,219 @@ int run_groups(sv_state *h, const std::vector<Block> &gates, const std::vector<G
     return rc;
 }
 
+// One pass of an SV_PLAN_PASSES plan: its gates grouped into sub-blocks of at
+// most four qubits (pass kernel) or, when some gate is wider or the state is
+// below the pass tile, into ordinary <= max_fused sweeps.
+struct PassWork {
+    bool kernel = false;
+    uint64_t qmask = 0;      // logical qubits of the pass
+    std::vector<Group> subs; // members index the circuit's gate list
+    uint64_t off = 0;        // arena range of the pass: [off, off + bytes)
+    uint64_t bytes = 0;
+    int ngates = 0;
+};
+
+// Stage a kernel pass (descriptors, then the 16 x 16 matrices) and launch it.
+int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWork &w, bool launch, size_t index,
+                      sv_run_stats &acc)
+{
+    uint64_t phys = 0;
+    int lo = h->n, hi = -1;
+    for (int q = 0; q < h->n; ++q)
+        if ((w.qmask >> q) & 1) {
+            const int p = h->qmap[q];
+            phys |= uint64_t(1) << p;
+            lo = std::min(lo, p);
+            hi = std::max(hi, p);
+        }
+    int tb[16];
+    const int T = pass_tile_bits(h->n, h->dtype, phys, tb);
+    if (T < 0) {
+        set_error("pass %zu does not fit the pass tile", index);
+        return SV_EINVAL;
+    }
+    int slot_of[64];
+    for (int b = 0; b < T; ++b)
+        slot_of[tb[b]] = b;
+    const size_t nsub = w.subs.size();
+    const uint64_t S = amp_bytes(h->dtype);
+    const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
+    const uint64_t mats = w.off + ((nsub * sizeof(PassSub) + 255) & ~uint64_t(255));
+    if (!launch) {
+        PassSub *desc = reinterpret_cast<PassSub *>(static_cast<char *>(h->h_arena) + w.off);
+        std::vector<const Block *> mem;
+        for (size_t i = 0; i < nsub; ++i) {
+            mem.clear();
+            for (int m : w.subs[i].members)
+                mem.push_back(&gates[size_t(m)]);
+            const Block b = densify(fuse(mem, w.subs[i].qmask));
+            int slots[4], kk = 0;
+            uint32_t used = 0;
+            for (int j = 0; j < b.k; ++j) {
+                slots[kk] = slot_of[h->qmap[b.targets[j]]];
+                used |= 1u << slots[kk++];
+            }
+            for (int sl = 0; kk < 4 && sl < T; ++sl)
+                if (!((used >> sl) & 1)) {
+                    slots[kk++] = sl;
+                    used |= 1u << sl;
+                }
+            PassSub d{};
+            for (int r = 0; r < 16; ++r)
+                for (int j = 0; j < 4; ++j)
+                    if ((r >> j) & 1)
+                        d.xc[r] |= 1u << slots[j];
+            int sorted[4] = {slots[0], slots[1], slots[2], slots[3]};
+            std::sort(sorted, sorted + 4);
+            for (int j = 0; j < 4; ++j)
+                d.tslot_m[j] = (1u << sorted[j]) - 1u;
+            d.u_off = mats + i * mat16;
+            desc[i] = d;
+            // U (x) I on the padding slots: row/column bits >= b.k must agree
+            Block u4;
+            u4.k = 4;
+            u4.U.assign(256, cd(0.0, 0.0));
+            const int dk = 1 << b.k;
+            for (int r = 0; r < 16; ++r)
+                for (int c = 0; c < 16; ++c)
+                    if ((r >> b.k) == (c >> b.k))
+                        u4.U[size_t(r) * 16 + c] = b.U[size_t(r & (dk - 1)) * dk + (c & (dk - 1))];
+            stage_matrix(h, u4, d.u_off);
+        }
+        return SV_OK;
+    }
+    sv_state::Pending pr{};
+    pr.rec.kind = SV_SWEEP_PASS;
+    pr.rec.k = __builtin_popcountll(w.qmask);
+    pr.rec.c = 0;
+    pr.rec.lowest_target = lo;
+    pr.rec.highest_target = hi;
+    pr.rec.num_gates = w.ngates;
+    pr.rec.bytes = 2.0 * double(h->bytes);
+    pr.rec.flops = double(nsub) * (8.0 * 16.0 - 2.0) * std::ldexp(1.0, h->n);
+    int rc = prof_begin(h, pr);
+    if (rc != SV_OK)
+        return rc;
+    const char *base = static_cast<const char *>(h->d_arena);
+    hipError_t e = launch_pass(h->d_state, h->n, h->dtype, tb, base + w.off, int(nsub), base, h->stream);
+    if (e != hipSuccess) {
+        set_error("pass %zu launch failed: %s", index, hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    rc = prof_end(h, pr);
+    if (rc != SV_OK)
+        return rc;
+    acc.sweeps += 1;
+    if (w.ngates > 1)
+        acc.fused_blocks += 1;
+    acc.algorithmic_bytes += pr.rec.bytes;
+    acc.flops += pr.rec.flops;
+    return SV_OK;
+}
+
+// Run a circuit as LDS passes (SV_PLAN_PASSES), fused, uploaded and launched
+// in chunks of 1, 2, 4, ... passes as in run_groups.
+int run_passes(sv_state *h, const std::vector<Block> &gates, int pass_qubits, int max_fused, int precision, int ngates,
+               sv_run_stats *st)
+{
+    const int T = pass_tile_log(h->dtype);
+    const uint64_t S = amp_bytes(h->dtype);
+    const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
+    const std::vector<Group> pg = group_greedy(gates, pass_qubits);
+    std::vector<PassWork> work(pg.size());
+    uint64_t total = 0;
+    std::vector<Block> mem;
+    for (size_t i = 0; i < pg.size(); ++i) {
+        PassWork &w = work[i];
+        w.qmask = pg[i].qmask;
+        mem.clear();
+        for (int m : pg[i].members) {
+            mem.push_back(gates[size_t(m)]);
+            w.ngates += gates[size_t(m)].ngates;
+        }
+        auto remap = [&](std::vector<Group> g) {
+            for (Group &x : g)
+                for (int &m : x.members)
+                    m = pg[i].members[size_t(m)];
+            return g;
+        };
+        w.subs = remap(group_greedy(mem, 4));
+        w.kernel = h->n >= T && __builtin_popcountll(w.qmask) <= kMaxPassQubits;
+        for (const Group &g : w.subs)
+            if (__builtin_popcountll(g.qmask) > 4)
+                w.kernel = false;
+        w.off = total;
+        if (w.kernel) {
+            w.bytes = ((w.subs.size() * sizeof(PassSub) + 255) & ~uint64_t(255)) + w.subs.size() * mat16;
+        } else {
+            w.subs = remap(group_greedy(mem, max_fused));
+            for (const Group &g : w.subs) {
+                const Block &first = gates[size_t(g.members[0])];
+                const int k = g.members.size() == 1 ? first.k : __builtin_popcountll(g.qmask);
+                const int c = g.members.size() == 1 ? first.c : 0;
+                w.bytes += matrix_bytes(h, (k == 3 && pads_to_four(h->n, h->dtype, c, precision)) ? 4 : k);
+            }
+        }
+        total += w.bytes;
+    }
+    int rc = ensure_arena(h, total);
+    if (rc != SV_OK)
+        return rc;
+    sv_run_stats acc{};
+    acc.gates = ngates;
+    std::vector<const Block *> mp;
+    std::vector<Block> sweeps;
+    std::vector<std::vector<Block>> chunk_sweeps;
+    for (size_t next = 0, size = 1; next < work.size() && rc == SV_OK; next += size, size *= 2) {
+        const size_t end = std::min(work.size(), next + size);
+        chunk_sweeps.assign(end - next, std::vector<Block>());
+        for (size_t i = next; i < end && rc == SV_OK; ++i) {
+            const PassWork &w = work[i];
+            if (w.kernel) {
+                rc = stage_launch_pass(h, gates, w, false, i, acc);
+                continue;
+            }
+            uint64_t off = w.off;
+            for (const Group &g : w.subs) {
+                mp.clear();
+                for (int m : g.members)
+                    mp.push_back(&gates[size_t(m)]);
+                Block b = fuse(mp, g.qmask);
+                if (padded_exec(h, b, precision))
+                    b = pad_to_four(h, b);
+                if (b.k >= 2)
+                    stage_matrix(h, b, off);
+                off += matrix_bytes(h, b.k);
+                chunk_sweeps[i - next].push_back(std::move(b));
+            }
+        }
+        if (rc != SV_OK)
+            break;
+        rc = upload_range(h, work[next].off, end < work.size() ? work[end].off : total);
+        for (size_t i = next; i < end && rc == SV_OK; ++i) {
+            const PassWork &w = work[i];
+            if (w.kernel) {
+                rc = stage_launch_pass(h, gates, w, true, i, acc);
+                continue;
+            }
+            uint64_t off = w.off;
+            for (const Block &b : chunk_sweeps[i - next]) {
+                if (rc != SV_OK)
+                    break;
+                rc = launch_block(h, b, static_cast<const char *>(h->d_arena) + off, precision, i, acc);
+                off += matrix_bytes(h, b.k);
+            }
+        }
+    }
+    if (total > 0) {
+        HIP_TRY(hipEventRecord(h->arena_done, h->stream));
+        h->arena_pending = true;
+    }
+    if (rc == SV_OK && st)
+        *st = acc;
+    return rc;
+}
+
 int parse_pauli(const sv_state *h, const char *term, uint64_t &x, uint64_t &yz, int &ny)
 {
     if (term == nullptr) {
@@ -731,11 +944,12 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
     // gates as one-gate blocks (validated), then grouped by the plan mode
     sv_plan_opts plain = o;
     plain.mode = SV_PLAN_PLAIN;
+    plain.pass_qubits = 0;
     std::vector<Block> gates_b;
     rc = plan_circuit(h->n, h->dtype, gates, ngates, plain, gates_b);
     if (rc != SV_OK)
         return rc;
-    if (o.mode < SV_PLAN_PLAIN || o.mode > SV_PLAN_LEARNED) {
+    if (o.mode < SV_PLAN_PLAIN || o.mode > SV_PLAN_PASSES) {
         set_error("unknown plan mode %d", o.mode);
         return SV_EINVAL;
     }
@@ -743,7 +957,16 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
         set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
         return SV_EINVAL;
     }
+    if (o.mode == SV_PLAN_PASSES ? (o.pass_qubits != 0 && (o.pass_qubits < 4 || o.pass_qubits > kMaxPassQubits))
+                                 : o.pass_qubits != 0) {
+        set_error("pass_qubits %d: 4..%d (0 for %d) with SV_PLAN_PASSES, else 0", o.pass_qubits, kMaxPassQubits,
+                  kMaxPassQubits);
+        return SV_EINVAL;
+    }
     DeviceGuard dg(h->device);
+    if (o.mode == SV_PLAN_PASSES)
+        return run_passes(h, gates_b, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, o.precision, ngates,
+                          stats);
     std::vector<Group> groups;
     if (o.mode == SV_PLAN_PLAIN) {
         groups.reserve(gates_b.size());

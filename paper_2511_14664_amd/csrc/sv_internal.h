@@ -63,6 +63,9 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax);
 // Fuse gates into one block on the qubits of qmask (targets ascending); a
 // single member is returned unchanged.
 Block fuse(const std::vector<const Block *> &members, uint64_t qmask);
+// A controlled block as a dense unitary on targets + controls (controls
+// become the high bits of the index); uncontrolled blocks are returned as is.
+Block densify(const Block &b);
 // The block a group becomes, without its matrix when it spans two or more
 // qubits (targets, controls, width, gate count and diagonality only).
 Block group_shape(const std::vector<Block> &gates, const Group &g);
@@ -119,6 +122,23 @@ uint64_t marginal_scratch_doubles(int n, int m, const int *phys_q);
 hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, int m,
                            double *d_scratch, double *d_out, hipStream_t s);
 uint64_t expect_scratch_doubles(int n);
+// LDS passes (sv_pass.hip): blocks of four tile slots applied in sequence to
+// one tile of the pass's qubits + the lowest free bits.
+constexpr int kMaxPassQubits = 8;
+struct PassSub {
+    uint32_t xc[16];      // tile-local index bits of block row r (bit b of r -> slot of block qubit b)
+    uint32_t tslot_m[4];  // insert masks 2^slot - 1 of the block's four slots, ascending
+    uint64_t u_off;       // byte offset of the 16 x 16 row-major matrix (state precision) from the matrix base
+    uint64_t pad[5];
+};
+static_assert(sizeof(PassSub) == 128, "pass block descriptor layout");
+int pass_tile_log(int dtype);
+// Sorted physical tile bits of a pass (its qubits + the lowest free bits);
+// returns the tile width T, or -1 if the pass does not fit.
+int pass_tile_bits(int n, int dtype, uint64_t phys_qmask, int *tile_bits);
+hipError_t launch_pass(void *st, int n, int dtype, const int *tile_bits, const void *d_subs, int nsub,
+                       const void *d_mats, hipStream_t s);
+
 // Z strings per launch_expect_z call.
 int expect_z_batch();
 hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zmasks, int nt,

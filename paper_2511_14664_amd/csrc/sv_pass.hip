@@ -1,0 +1,210 @@
+// LDS passes: a sequence of fused 4-qubit blocks applied to one tile per HBM
+// round trip.
+//
+// A pass is a set Q of at most 8 qubits and the blocks of the circuit that act
+// inside Q, in circuit order.  Its tile holds the amplitudes spanned by Q and
+// the lowest free index bits (2^12 complex64 or 2^11 complex128 amplitudes,
+// so that contiguous runs stay at least 128 bytes).  Every block is applied
+// to the tile in LDS before the tile goes back to HBM: the state moves once
+// per pass instead of once per block, which is the same product of unitaries
+// in the same order (paper Sec. 2.1: gate application as sweeps over the
+// amplitudes; Sec. 2.2: gate fusion to cut the number of sweeps).
+//
+// Each block is a dense 16 x 16 unitary on four tile slots (smaller blocks
+// are padded with identity on other tile slots by the host).  It runs as the
+// complex GEMM Y = U V over the 2^(T-4) groups of the tile, with the three
+// real products of the matrix-core sweep (Gauss):
+//     P1 = Ur Vr, P2 = Ui Vi, P3 = (Ur + Ui)(Vr + Vi),  Yr = P1 - P2,
+//     Yi = P3 - P1 - P2,
+// on v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64.  The block descriptors
+// are read with scalar loads; the U fragment of the next block is fetched
+// while the current one is multiplied.
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+using namespace dev;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct PassAcc;
+template <>
+struct PassAcc<float> {
+    using T = floatx4;
+};
+template <>
+struct PassAcc<double> {
+    using T = doublex4;
+};
+
+__device__ __forceinline__ floatx4 mma16(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mma16(double a, double b, doublex4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename R, int TA_LOG, bool PAIR>
+__global__ __launch_bounds__(kThreads) void k_pass(R *__restrict__ st, const TileArgs a,
+                                                   const PassSub *__restrict__ subs, int nsub,
+                                                   const char *__restrict__ mats)
+{
+    using C = typename CT<R>::C;
+    using AccT = typename PassAcc<R>::T;
+    constexpr int D = 16, NT = 16, KT = 4, NS = D / KT;
+    constexpr int NGS = (1 << (TA_LOG - 4)) / NT;  // group sets (NMT = 1)
+    constexpr int PER_WAVE = NGS / 4;
+    constexpr bool F64 = std::is_same<R, double>::value;
+    static_assert(NGS % 4 == 0 && PER_WAVE >= 1, "tile shape");
+
+    __shared__ C tile[1 << TA_LOG];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int ai = lane % 16, akk = lane / 16;  // A operand: U[ai][4 s + akk]
+    const int bj = lane % 16, bkk = lane / 16;  // B operand: V[4 s + bkk][group bj]
+    const int q = lane / 16;
+
+    // this lane's fragment of block sb's matrix: U[ai][4 s + akk], s < NS
+    auto load_u = [&](int sb, R *xr, R *xi) {
+        const C *U = reinterpret_cast<const C *>(mats + subs[sb].u_off) + ai * D + akk;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const C u = U[s * KT];
+            xr[s] = u.x;
+            xi[s] = u.y;
+        }
+    };
+    R ur[NS], ui[NS];
+    load_u(0, ur, ui);  // in flight with the tile's loads
+
+    tile_sweep<R, TA_LOG, PAIR>(st, a, tile, [&](C *t) {
+        for (int sb = 0; sb < nsub; ++sb) {
+            R nr[NS], ni[NS];
+            if (sb + 1 < nsub)
+                load_u(sb + 1, nr, ni);
+            const PassSub &d = subs[sb];
+            // slot lookups: xc[r] is linear in the bits of r
+            const uint32_t x1 = d.xc[1], x2 = d.xc[2], x4 = d.xc[4], x8 = d.xc[8];
+            const uint32_t xb_lane = ((bkk & 1) ? x1 : 0u) | ((bkk & 2) ? x2 : 0u);
+            const uint32_t xo_lane = F64 ? (((q & 1) ? x1 : 0u) | ((q & 2) ? x2 : 0u))
+                                         : (((q & 1) ? x4 : 0u) | ((q & 2) ? x8 : 0u));
+            uint32_t xg[PER_WAVE];
+#pragma unroll
+            for (int j = 0; j < PER_WAVE; ++j) {
+                uint32_t g = uint32_t((wave + 4 * j) * NT + bj);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t lo = d.tslot_m[b];
+                    g = (g & lo) | ((g & ~lo) << 1);
+                }
+                xg[j] = g;
+            }
+            AccT p1[PER_WAVE], p2[PER_WAVE], p3[PER_WAVE];
+#pragma unroll
+            for (int j = 0; j < PER_WAVE; ++j) {
+                p1[j] = AccT{};
+                p2[j] = AccT{};
+                p3[j] = AccT{};
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint32_t xs = d.xc[s * KT] | xb_lane;
+                const R us = ur[s] + ui[s];
+#pragma unroll
+                for (int j = 0; j < PER_WAVE; ++j) {
+                    const C x = t[swz(xs | xg[j])];
+                    p1[j] = mma16(ur[s], x.x, p1[j]);
+                    p2[j] = mma16(ui[s], x.y, p2[j]);
+                    p3[j] = mma16(us, x.x + x.y, p3[j]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // accumulator row: 4 (lane / 16) + r (FP32), 4 r + lane / 16 (FP64)
+                const uint32_t xrow = xo_lane | d.xc[F64 ? 4 * r : r];
+#pragma unroll
+                for (int j = 0; j < PER_WAVE; ++j) {
+                    C y;
+                    y.x = p1[j][r] - p2[j][r];
+                    y.y = p3[j][r] - p1[j][r] - p2[j][r];
+                    t[swz(xrow | xg[j])] = y;
+                }
+            }
+            __syncthreads();
+            if (sb + 1 < nsub) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    ur[s] = nr[s];
+                    ui[s] = ni[s];
+                }
+            }
+        }
+    });
+}
+
+template <typename R, int TA_LOG>
+hipError_t launch_pass_t(void *st, const TileArgs &a, const void *subs, int nsub, const void *mats, hipStream_t s)
+{
+    const dim3 grid = tile_grid(a.ntiles);
+    const PassSub *ps = static_cast<const PassSub *>(subs);
+    const char *m = static_cast<const char *>(mats);
+    if (std::is_same<R, float>::value && a.dep[0] == 1)
+        hipLaunchKernelGGL((k_pass<R, TA_LOG, std::is_same<R, float>::value>), grid, dim3(kThreads), 0, s, (R *)st, a,
+                           ps, nsub, m);
+    else
+        hipLaunchKernelGGL((k_pass<R, TA_LOG, false>), grid, dim3(kThreads), 0, s, (R *)st, a, ps, nsub, m);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int pass_tile_log(int dtype)
+{
+    return dtype == SV_C64 ? 12 : 11;
+}
+
+int pass_tile_bits(int n, int dtype, uint64_t phys_qmask, int *tile_bits)
+{
+    const int T = pass_tile_log(dtype);
+    const int q = __builtin_popcountll(phys_qmask);
+    if (n < T || n > 63 || q > kMaxPassQubits || (phys_qmask >> n) != 0)
+        return -1;
+    int got = 0;
+    for (int p = 0; p < n; ++p)
+        if ((phys_qmask >> p) & 1)
+            tile_bits[got++] = p;
+    for (int p = 0; p < n && got < T; ++p)
+        if (!((phys_qmask >> p) & 1))
+            tile_bits[got++] = p;
+    if (got != T)
+        return -1;
+    std::sort(tile_bits, tile_bits + T);
+    return T;
+}
+
+hipError_t launch_pass(void *st, int n, int dtype, const int *tile_bits, const void *d_subs, int nsub,
+                       const void *d_mats, hipStream_t s)
+{
+    const int T = pass_tile_log(dtype);
+    if (nsub < 1 || n < T)
+        return hipErrorInvalidValue;
+    TileArgs a{};
+    std::vector<int> bits(tile_bits, tile_bits + T);
+    for (int b = 0; b < T; ++b)
+        a.dep[b] = uint64_t(1) << bits[b];
+    a.outer = make_insert_masks(bits);
+    a.ntiles = uint64_t(1) << (n - T);
+    if (dtype == SV_C64)
+        return launch_pass_t<float, 12>(st, a, d_subs, nsub, d_mats, s);
+    return launch_pass_t<double, 11>(st, a, d_subs, nsub, d_mats, s);
+}
+
+}  // namespace sv

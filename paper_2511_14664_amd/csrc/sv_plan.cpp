@@ -297,6 +297,33 @@ Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
     return out;
 }
 
+Block densify(const Block &b)
+{
+    if (b.c == 0)
+        return b;
+    Block o;
+    o.k = b.k + b.c;
+    for (int j = 0; j < b.k; ++j)
+        o.targets[j] = b.targets[j];
+    for (int j = 0; j < b.c; ++j)
+        o.targets[b.k + j] = b.controls[j];
+    const int d = 1 << o.k, dk = 1 << b.k;
+    const int all = ((1 << b.c) - 1) << b.k;  // control bits of the new index
+    o.U.assign(size_t(d) * d, cd(0.0, 0.0));
+    for (int r = 0; r < d; ++r) {
+        if ((r & all) != all) {
+            o.U[size_t(r) * d + r] = 1.0;
+            continue;
+        }
+        for (int c = 0; c < d; ++c)
+            if ((c & all) == all)
+                o.U[size_t(r) * d + c] = b.U[size_t(r & (dk - 1)) * dk + (c & (dk - 1))];
+    }
+    o.ngates = b.ngates;
+    o.diag = b.diag;
+    return o;
+}
+
 Block group_shape(const std::vector<Block> &gates, const Group &g)
 {
     if (g.members.size() == 1)
@@ -461,8 +488,16 @@ int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_pl
         set_error("bad gate list");
         return SV_EINVAL;
     }
+    if (o.mode == SV_PLAN_PASSES) {
+        set_error("pass plans (SV_PLAN_PASSES) run through sv_apply_circuit only");
+        return SV_EINVAL;
+    }
     if (o.mode < SV_PLAN_PLAIN || o.mode > SV_PLAN_LEARNED) {
         set_error("unknown plan mode %d", o.mode);
+        return SV_EINVAL;
+    }
+    if (o.pass_qubits != 0) {
+        set_error("pass_qubits must be 0 outside SV_PLAN_PASSES");
         return SV_EINVAL;
     }
     if (o.mode != SV_PLAN_PLAIN && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {

@@ -151,6 +151,37 @@ __global__ __launch_bounds__(kThreads) void k_sum_rows(const double *__restrict_
     out[x] = acc;
 }
 
+// Wide rows: one workgroup per row, strided partial sums in a fixed order,
+// then the fixed block tree.
+__global__ __launch_bounds__(kThreads) void k_sum_rows_wide(const double *__restrict__ part, double *__restrict__ out,
+                                                            uint32_t cols)
+{
+    __shared__ double sh[4];
+    const double *row = part + uint64_t(blockIdx.x) * cols;
+    double acc = 0.0;
+    for (uint32_t c = threadIdx.x; c < cols; c += kThreads)
+        acc += row[c];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = acc;
+}
+
+}  // namespace
+
+// out[x] = sum over c of part[x * cols + c], x < rows, in a fixed order.
+static hipError_t launch_sum_rows(const double *part, double *out, uint64_t rows, uint32_t cols, hipStream_t s)
+{
+    if (cols >= kThreads && rows <= (uint64_t(1) << 20)) {
+        hipLaunchKernelGGL(k_sum_rows_wide, dim3(uint32_t(rows)), dim3(kThreads), 0, s, part, out, cols);
+    } else {
+        const uint64_t g = (rows + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_sum_rows, dim3(uint32_t(g)), dim3(kThreads), 0, s, part, out, rows, cols);
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
 // ---------------------------------------------------------------------------
 // Z-string expectations: sum_i |a_i|^2 (-1)^popcount(i & z_t), up to kMaxZ
 // strings per pass.  part[t * gridDim + block].
@@ -708,8 +739,7 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
             e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
-            const uint64_t g = (uint64_t(a2.nbins) + kThreads - 1) / kThreads;
-            hipLaunchKernelGGL(k_sum_rows, dim3(g), dim3(kThreads), 0, s, part, d_out, uint64_t(a2.nbins), a2.chunks);
+            return launch_sum_rows(part, d_out, uint64_t(a2.nbins), a2.chunks, s);
         } else {
             const uint64_t g = std::min<uint64_t>((uint64_t(a2.nbins) + kThreads - 1) / kThreads, 1u << 20);
             hipLaunchKernelGGL(k_marg_doubles, dim3(g), dim3(kThreads), 0, s, red, d_out, a2);
@@ -735,9 +765,7 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        const uint64_t g = (uint64_t(a.nbins) + kThreads - 1) / kThreads;
-        hipLaunchKernelGGL(k_sum_rows, dim3(g), dim3(kThreads), 0, s, d_scratch, d_out, uint64_t(a.nbins),
-                           p.chunks);
+        return launch_sum_rows(d_scratch, d_out, uint64_t(a.nbins), p.chunks, s);
     } else {
         const uint64_t g = std::min<uint64_t>((uint64_t(a.nbins) + kThreads - 1) / kThreads, 1u << 20);
         if (dtype == SV_C64)
@@ -800,8 +828,7 @@ hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zma
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kThreads), 0, s, d_scratch, d_out, uint64_t(nt), grid);
-    return hipGetLastError();
+    return launch_sum_rows(d_scratch, d_out, uint64_t(nt), grid, s);
 }
 
 hipError_t launch_expect_xy(const void *st, int n, int dtype, uint64_t xmask, uint64_t yzmask, double *d_scratch,
@@ -823,8 +850,7 @@ hipError_t launch_expect_xy(const void *st, int n, int dtype, uint64_t xmask, ui
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kThreads), 0, s, d_scratch, d_out2, uint64_t(2), grid);
-    return hipGetLastError();
+    return launch_sum_rows(d_scratch, d_out2, uint64_t(2), grid, s);
 }
 
 int sample_log_block(int n)

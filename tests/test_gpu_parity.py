@@ -427,3 +427,72 @@ def test_bf16x3_single_blocks_every_placement():
                     e = maxerr(s.host(), want)
                     # one block: relative error ~2^-16 of amplitudes of size ~2^-7
                     assert e <= 1e-6, (k, tg, ctl, e)
+
+
+# ---------------------------------------------------------------------------
+# LDS passes (SV_PLAN_PASSES)
+# ---------------------------------------------------------------------------
+def pass_circuit(n, seed):
+    """Layered circuit plus controlled one-qubit gates, 2..4-target matrix
+    gates, a controlled matrix gate and (n >= 6) a 5-target matrix gate, which
+    no pass kernel takes (its pass runs as ordinary sweeps)."""
+    rng = np.random.default_rng(seed)
+    gates = list(W.layered_u3_pairing(n, 6, W.circuit_seed(7, seed), "cx_or_cz"))
+    for _ in range(6):
+        q = [int(x) for x in rng.permutation(n)[:3]]
+        gates.append(Gate("u3", (q[0],), tuple(q[1:1 + int(rng.integers(1, 3))]), tuple(rng.uniform(0, 6, 3))))
+    for k in (2, 3, 4):
+        q = [int(x) for x in rng.permutation(n)[:k]]
+        gates.append(Gate("matrix", tuple(q), (), (), W.haar_unitary(rng, 1 << k)))
+    q = [int(x) for x in rng.permutation(n)[:3]]
+    gates.append(Gate("matrix", tuple(q[:2]), (q[2],), (), W.haar_unitary(rng, 4)))
+    if n >= 6:
+        q = [int(x) for x in rng.permutation(n)[:5]]
+        gates.append(Gate("matrix", tuple(q), (), (), W.haar_unitary(rng, 32)))
+    gates += list(W.layered_u3_pairing(n, 4, W.circuit_seed(8, seed), "cx"))
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [9, 11, 12, 14, 20])
+def test_pass_plan_matches_oracle(dtype, n):
+    gates = pass_circuit(n, n)
+    want = oracle.run(gates, n)
+    for pq in (0, 4, 6, 8):
+        say(f"passes n={n} {DNAME[dtype]} pass_qubits={pq}")
+        with State(n, dtype) as s:
+            st = B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, pq))
+            assert maxerr(s.host(), want) <= TOL[dtype]
+            assert st["gates"] == len(gates) and 1 <= st["sweeps"] < len(gates)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pass_plan_after_relayout_and_profile_records(dtype):
+    n = 16
+    a = W.layered_u3_pairing(n, 5, W.circuit_seed(9, 1), "cx_or_cz")
+    b = pass_circuit(n, 3)
+    want = oracle.run(list(a) + list(b), n)
+    with State(n, dtype) as s:
+        B.sv_apply_circuit(s.h, a, B.make_opts(B.SV_PLAN_PASSES))
+        B.sv_swap_bits(s.h, 0, n - 6, 6)
+        B.sv_swap_bits(s.h, 2, 9, 3)
+        B.sv_profile_read(s.h)
+        B.sv_profile_enable(s.h, True)
+        st = B.sv_apply_circuit(s.h, b, B.make_opts(B.SV_PLAN_PASSES))
+        recs = B.sv_profile_read(s.h)
+        assert maxerr(s.host(), want) <= TOL[dtype]
+        kinds = {r["kind_name"] for r in recs}
+        assert "pass" in kinds and len(recs) == st["sweeps"]
+        assert sum(r["num_gates"] for r in recs) == len(b)
+        assert all(r["k"] <= 8 and r["ms"] > 0 for r in recs if r["kind_name"] == "pass")
+
+
+def test_pass_plan_rejects_bad_options():
+    with State(12, B.SV_C64) as s:
+        for opts in (B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 3),
+                     B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 9),
+                     B.make_opts(B.SV_PLAN_GREEDY, 5, B.SV_PREC_NATIVE, 8)):
+            with pytest.raises(B.SvError):
+                B.sv_apply_circuit(s.h, [Gate("h", (0,))], opts)
+    with pytest.raises(B.SvError):
+        B.sv_plan_create(12, B.SV_C64, [Gate("h", (0,))], B.make_opts(B.SV_PLAN_PASSES))
