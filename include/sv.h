@@ -100,9 +100,9 @@ typedef enum sv_plan_mode {
     SV_PLAN_PASSES = 3    /* greedy dependency-aware grouping into passes of <= pass_qubits
                              qubits; a pass moves the state through LDS once and applies
                              its gates there as a sequence of fused 4-qubit blocks on the
-                             matrix cores (gates on more than 4 qubits, and states below
-                             the pass tile, run as greedy <= max_fused-qubit sweeps).
-                             sv_apply_circuit only. */
+                             matrix cores in the state's own precision (gates on more
+                             than 4 qubits, and states below the pass tile, run as greedy
+                             <= max_fused-qubit sweeps).  sv_apply_circuit only. */
 } sv_plan_mode;
 
 typedef enum sv_precision {
