@@ -282,7 +282,7 @@ def counter_traffic(dom_key, n, dtype, args):
 def train_cost_model(B, W):
     """Cost model trained on sweep timings the library records on the
     12-qubit complex128 and 28-qubit complex64/complex128 layered workloads
-    (greedy widths 1..6 and plain); untimed set-up."""
+    (greedy widths 1..6, plain and LDS passes); untimed set-up."""
     import numpy as np
 
     Xs, ys = [], []
@@ -297,6 +297,8 @@ def train_cost_model(B, W):
             B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_GREEDY, k))
         B.sv_reset(h)
         B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PLAIN))
+        B.sv_reset(h)
+        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PASSES))
         recs, cnt = B.sv_profile_read_raw(h)
         Xs.append(B.sv_sweep_features(n, dt, recs, cnt))
         ys.append(B.sv_sweep_targets(recs, cnt))
@@ -344,7 +346,9 @@ def bench_su4(args):
         B.sv_destroy(h)
     B.sv_costmodel_destroy(model)
     out = {"workload": f"30-qubit U3 + SU(4) circuit, depth 40, {len(gates)} gates, c64, {args.precision}",
-           "greedy_k": args.max_fused, "learned_k": k, "predicted_ms_by_width": [round(float(x), 1) for x in pred],
+           "greedy_k": args.max_fused, "learned_choice": k if k else "passes",
+           "predicted_ms_by_plan": {**{f"greedy_k{w}": round(float(pred[w - 1]), 1) for w in range(1, 7)},
+                                    "passes": round(float(pred[6]), 1)},
            "greedy_ms": res["greedy"]["ms_per_circuit"], "greedy_sweeps": res["greedy"]["sweeps"],
            "learned_ms": res["learned"]["ms_per_circuit"], "learned_sweeps": res["learned"]["sweeps"],
            "gain": round(res["greedy"]["ms_per_circuit"] / res["learned"]["ms_per_circuit"], 3),

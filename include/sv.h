@@ -95,8 +95,9 @@ typedef struct sv_gate {
 typedef enum sv_plan_mode {
     SV_PLAN_PLAIN = 0,    /* one sweep per gate */
     SV_PLAN_GREEDY = 1,   /* greedy dependency-aware fusion into <= max_fused-qubit blocks */
-    SV_PLAN_LEARNED = 2,  /* candidate fusion plans ranked by the attached cost model;
-                             falls back to SV_PLAN_GREEDY without a usable model */
+    SV_PLAN_LEARNED = 2,  /* candidate plans (greedy widths 1..max_fused and the pass plan)
+                             ranked by the attached cost model; falls back to
+                             SV_PLAN_GREEDY without a usable model */
     SV_PLAN_PASSES = 3    /* greedy dependency-aware grouping into passes of <= pass_qubits
                              qubits; a pass moves the state through LDS once and applies
                              its gates there as a sequence of fused 4-qubit blocks on the
@@ -337,10 +338,12 @@ int sv_sweep_targets(const sv_sweep_record *recs, int count, float *out);
 /* Attach a model to a state (NULL detaches); SV_PLAN_LEARNED uses it. */
 int sv_set_costmodel(sv_handle h, sv_costmodel_handle m);
 
-/* Rank the candidate plans (greedy with widest block 1..max_fused) of a gate
- * list by predicted run time.  predicted_ms[k-1] receives the prediction for
- * width k (max_fused entries); *chosen the width with the smallest one, or
- * max_fused if a prediction is not finite. */
+/* Rank the candidate plans of a gate list by predicted run time: greedy with
+ * widest block 1..max_fused, and the LDS pass plan (SV_PLAN_PASSES with 8-qubit
+ * passes).  predicted_ms (max_fused + 1 entries) receives the prediction for
+ * width k at [k-1] and for the pass plan at [max_fused]; *chosen is the width
+ * with the smallest prediction, 0 for the pass plan, or max_fused if a
+ * prediction is not finite. */
 int sv_costmodel_rank(sv_costmodel_handle m, int n, int dtype, const sv_gate *gates, int ngates, int max_fused,
                       int *chosen, float *predicted_ms);
 

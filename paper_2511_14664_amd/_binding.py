@@ -531,9 +531,11 @@ def sv_set_costmodel(h: int, m: Optional[int]):
 
 
 def sv_costmodel_rank(m: int, n: int, dtype: int, gates, max_fused: int = 6):
+    """(chosen, predicted ms): chosen is the greedy width 1..max_fused or 0 for
+    the pass plan; predictions for widths 1..max_fused, then the pass plan."""
     circ = _as_circuit(gates)
     chosen = ctypes.c_int()
-    pred = np.zeros(max_fused, dtype=np.float32)
+    pred = np.zeros(max_fused + 1, dtype=np.float32)
     _check(_lib.sv_costmodel_rank(ctypes.c_void_p(m), n, dtype, circ.array, circ.n_gates, max_fused,
                                   ctypes.byref(chosen), pred.ctypes.data), "sv_costmodel_rank")
     return chosen.value, pred

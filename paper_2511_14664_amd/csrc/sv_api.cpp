@@ -576,37 +576,21 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
 int run_passes(sv_state *h, const std::vector<Block> &gates, int pass_qubits, int max_fused, int precision, int ngates,
                sv_run_stats *st)
 {
-    const int T = pass_tile_log(h->dtype);
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
-    const std::vector<Group> pg = group_greedy(gates, pass_qubits);
+    const std::vector<PassGroup> pg = plan_passes(gates, pass_qubits, max_fused, h->n >= pass_tile_log(h->dtype));
     std::vector<PassWork> work(pg.size());
     uint64_t total = 0;
-    std::vector<Block> mem;
     for (size_t i = 0; i < pg.size(); ++i) {
         PassWork &w = work[i];
+        w.kernel = pg[i].kernel;
         w.qmask = pg[i].qmask;
-        mem.clear();
-        for (int m : pg[i].members) {
-            mem.push_back(gates[size_t(m)]);
-            w.ngates += gates[size_t(m)].ngates;
-        }
-        auto remap = [&](std::vector<Group> g) {
-            for (Group &x : g)
-                for (int &m : x.members)
-                    m = pg[i].members[size_t(m)];
-            return g;
-        };
-        w.subs = remap(group_greedy(mem, 4));
-        w.kernel = h->n >= T && __builtin_popcountll(w.qmask) <= kMaxPassQubits;
-        for (const Group &g : w.subs)
-            if (__builtin_popcountll(g.qmask) > 4)
-                w.kernel = false;
+        w.subs = pg[i].subs;
+        w.ngates = pg[i].ngates;
         w.off = total;
         if (w.kernel) {
             w.bytes = ((w.subs.size() * sizeof(PassSub) + 255) & ~uint64_t(255)) + w.subs.size() * mat16;
         } else {
-            w.subs = remap(group_greedy(mem, max_fused));
             for (const Group &g : w.subs) {
                 const Block &first = gates[size_t(g.members[0])];
                 const int k = g.members.size() == 1 ? first.k : __builtin_popcountll(g.qmask);
@@ -978,6 +962,8 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
             rc = rank_plans(h->model, h->n, h->dtype, gates_b, o.max_fused, o.precision, k, nullptr);
             if (rc != SV_OK)
                 return rc;
+            if (k == 0)  // the pass plan ranks first
+                return run_passes(h, gates_b, kMaxPassQubits, o.max_fused, o.precision, ngates, stats);
         }
         groups = group_greedy(gates_b, k);
     }

@@ -360,31 +360,50 @@ int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gate
     if (!m)
         return SV_OK;
     std::vector<float> feats;
-    std::vector<int> owner;
+    std::vector<int> owner;  // candidate: width 1..max_fused, 0 = the pass plan
     std::vector<double> gbytes;
-    for (int k = 1; k <= max_fused; ++k) {
-        for (const Group &g : group_greedy(gates, k)) {
-            // the sweep this group becomes: its shape, padded to four targets
-            // where execution pads (the pad is the lowest free qubit >= 6)
-            Block b = group_shape(gates, g);
-            if (b.k == 3 && pads_to_four(n, dtype, b.c, precision)) {
-                uint64_t used = qubit_mask(b);
-                int pick = -1;
-                for (int q = 0; q < n && pick < 0; ++q)
-                    if (q >= 6 && !((used >> q) & 1))
-                        pick = q;
-                for (int q = 0; q < n && pick < 0; ++q)
-                    if (!((used >> q) & 1))
-                        pick = q;
-                b.targets[b.k++] = pick;
-            }
-            float f[F];
-            const sv_sweep_record r = block_record(n, dtype, b, precision);
-            sweep_features(n, dtype, r, f);
-            feats.insert(feats.end(), f, f + F);
-            owner.push_back(k);
-            gbytes.push_back(r.bytes * 1e-9);
+    auto add = [&](const sv_sweep_record &r, int cand) {
+        float f[F];
+        sweep_features(n, dtype, r, f);
+        feats.insert(feats.end(), f, f + F);
+        owner.push_back(cand);
+        gbytes.push_back(r.bytes * 1e-9);
+    };
+    // the sweep a group becomes: its shape, padded to four targets where
+    // execution pads (the pad is the lowest free qubit >= 6)
+    auto shape_record = [&](const Group &g) {
+        Block b = group_shape(gates, g);
+        if (b.k == 3 && pads_to_four(n, dtype, b.c, precision)) {
+            uint64_t used = qubit_mask(b);
+            int pick = -1;
+            for (int q = 0; q < n && pick < 0; ++q)
+                if (q >= 6 && !((used >> q) & 1))
+                    pick = q;
+            for (int q = 0; q < n && pick < 0; ++q)
+                if (!((used >> q) & 1))
+                    pick = q;
+            b.targets[b.k++] = pick;
         }
+        return block_record(n, dtype, b, precision);
+    };
+    for (int k = 1; k <= max_fused; ++k)
+        for (const Group &g : group_greedy(gates, k))
+            add(shape_record(g), k);
+    const bool tile_fits = n >= pass_tile_log(dtype);
+    for (const PassGroup &w : plan_passes(gates, kMaxPassQubits, max_fused, tile_fits)) {
+        if (!w.kernel) {
+            for (const Group &g : w.subs)
+                add(shape_record(g), 0);
+            continue;
+        }
+        sv_sweep_record r{};
+        r.kind = SV_SWEEP_PASS;
+        r.k = __builtin_popcountll(w.qmask);
+        r.lowest_target = __builtin_ctzll(w.qmask);
+        r.highest_target = 63 - __builtin_clzll(w.qmask);
+        r.num_gates = w.ngates;
+        r.bytes = 2.0 * (dtype == SV_C64 ? 8.0 : 16.0) * std::ldexp(1.0, n);
+        add(r, 0);
     }
     const int rows = int(owner.size());
     if (rows == 0)
@@ -397,15 +416,17 @@ int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gate
     for (int i = 0; i < rows; ++i)
         tot[owner[i]] += std::exp(double(pred[i])) * gbytes[i];
     double best = 0.0;
-    bool finite = true;
-    for (int k = 1; k <= max_fused; ++k) {
+    bool finite = true, any = false;
+    for (int cand = 1; cand <= max_fused + 1; ++cand) {
+        const int c = cand == max_fused + 1 ? 0 : cand;  // widths first, then the pass plan
         if (pred_ms)
-            pred_ms[k - 1] = float(tot[k]);
-        if (!std::isfinite(tot[k]))
+            pred_ms[cand - 1] = float(tot[c]);
+        if (!std::isfinite(tot[c]))
             finite = false;
-        if (k == 1 || tot[k] < best) {
-            best = tot[k];
-            chosen = k;
+        if (!any || tot[c] < best) {
+            best = tot[c];
+            chosen = c;
+            any = true;
         }
     }
     if (!finite)

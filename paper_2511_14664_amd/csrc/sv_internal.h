@@ -63,6 +63,18 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax);
 // Fuse gates into one block on the qubits of qmask (targets ascending); a
 // single member is returned unchanged.
 Block fuse(const std::vector<const Block *> &members, uint64_t qmask);
+// One pass of an SV_PLAN_PASSES plan: the greedy groups of the circuit with a
+// pass_qubits budget, each sub-grouped into <= 4-qubit blocks for the pass
+// kernel (kernel = true) or, when a gate is wider or the state is below the
+// pass tile (tile_fits = false), into <= max_fused-qubit sweeps.  Sub-group
+// members index the circuit's gate list.
+struct PassGroup {
+    bool kernel = false;
+    uint64_t qmask = 0;
+    std::vector<Group> subs;
+    int ngates = 0;
+};
+std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, bool tile_fits);
 // A controlled block as a dense unitary on targets + controls (controls
 // become the high bits of the index); uncontrolled blocks are returned as is.
 Block densify(const Block &b);

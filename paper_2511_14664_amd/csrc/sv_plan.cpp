@@ -468,6 +468,36 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
     return out;
 }
 
+std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, bool tile_fits)
+{
+    const std::vector<Group> pg = group_greedy(gates, pass_qubits);
+    std::vector<PassGroup> out(pg.size());
+    std::vector<Block> mem;
+    for (size_t i = 0; i < pg.size(); ++i) {
+        PassGroup &w = out[i];
+        w.qmask = pg[i].qmask;
+        mem.clear();
+        for (int m : pg[i].members) {
+            mem.push_back(gates[size_t(m)]);
+            w.ngates += gates[size_t(m)].ngates;
+        }
+        auto remap = [&](std::vector<Group> g) {
+            for (Group &x : g)
+                for (int &m : x.members)
+                    m = pg[i].members[size_t(m)];
+            return g;
+        };
+        w.subs = remap(group_greedy(mem, 4));
+        w.kernel = tile_fits && __builtin_popcountll(w.qmask) <= kMaxPassQubits;
+        for (const Group &g : w.subs)
+            if (__builtin_popcountll(g.qmask) > 4)
+                w.kernel = false;
+        if (!w.kernel)
+            w.subs = remap(group_greedy(mem, max_fused));
+    }
+    return out;
+}
+
 std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)
 {
     std::vector<Block> out;

@@ -93,9 +93,10 @@ def test_training_reduces_loss_and_rejects_bad_data():
         B.sv_costmodel_destroy(m)
 
 
-def collect(n, dtype, gates, widths=(1, 2, 3, 4, 5, 6), plain=True):
+def collect(n, dtype, gates, widths=(1, 2, 3, 4, 5, 6), plain=True, passes=True):
     """Sweep timings the library records itself (HIP events), as features and
-    ln(ms per GB of algorithmic traffic)."""
+    ln(ms per GB of algorithmic traffic): greedy plans of the given widths, the
+    plain plan and the LDS pass plan."""
     h = B.sv_create(n, dtype)
     circ = B.Circuit(gates)
     try:
@@ -108,6 +109,9 @@ def collect(n, dtype, gates, widths=(1, 2, 3, 4, 5, 6), plain=True):
         if plain:
             B.sv_reset(h)
             B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PLAIN))
+        if passes:
+            B.sv_reset(h)
+            B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PASSES))
         recs, cnt = B.sv_profile_read_raw(h)
         X = B.sv_sweep_features(n, dtype, recs, cnt)
         y = B.sv_sweep_targets(recs, cnt)
@@ -157,15 +161,17 @@ def test_learned_plan_is_correct_and_falls_back_without_model():
             finally:
                 B.sv_destroy(h)
         k, pred = B.sv_costmodel_rank(m, n, B.SV_C64, gates, 5)
-        assert 1 <= k <= 5 and np.all(np.isfinite(pred)) and pred[k - 1] == np.min(pred)
+        assert 0 <= k <= 5 and len(pred) == 6 and np.all(np.isfinite(pred))
+        assert pred[k - 1 if k else 5] == np.min(pred)
     finally:
         B.sv_costmodel_destroy(m)
 
 
 def test_learned_planner_vs_greedy_on_30q_su4():
-    """Train on timings of the 12-qubit and 28-qubit layered workloads, then
-    plan the 30-qubit U3 + SU(4) circuit (depth 40, complex64).  Reports the
-    wall time of both plans and the model's error on held-out sweeps."""
+    """Train on timings of the 12-qubit and 28-qubit layered workloads (greedy
+    widths 1..6, plain, passes), then plan the 30-qubit U3 + SU(4) circuit
+    (depth 40, complex64).  Reports the wall time of the greedy and learned
+    plans and the model's error on held-out sweeps."""
     Xs, ys = [], []
     for n, dtype, ent in ((12, B.SV_C128, "cx"), (28, B.SV_C64, "cx_or_cz"), (28, B.SV_C128, "cx_or_cz")):
         X, y = collect(n, dtype, W.layered_u3_pairing(n, 20, W.circuit_seed(1 if n == 12 else 2, 1), ent))
@@ -184,7 +190,7 @@ def test_learned_planner_vs_greedy_on_30q_su4():
         k, pred = B.sv_costmodel_rank(m, n, B.SV_C64, circ, 6)
         tg, sg, ag = time_circuit(n, B.SV_C64, circ, B.make_opts(B.SV_PLAN_GREEDY, 5))
         tl, sl, al = time_circuit(n, B.SV_C64, circ, B.make_opts(B.SV_PLAN_LEARNED, 6), model=m)
-        say(f"30q SU(4): predicted ms by width {np.round(pred, 1)}, chose {k}; greedy(5) {tg * 1e3:.1f} ms "
+        say(f"30q SU(4): predicted ms by width 1..6, passes {np.round(pred, 1)}, chose {k or 'passes'}; greedy(5) {tg * 1e3:.1f} ms "
             f"({sg['sweeps']} sweeps), learned {tl * 1e3:.1f} ms ({sl['sweeps']} sweeps), gain {tg / tl:.3f}x")
         assert np.max(np.abs(ag - al)) <= 4e-5  # equal accuracy: same amplitudes within the complex64 bound
         assert tl <= 1.25 * tg
@@ -194,12 +200,13 @@ def test_learned_planner_vs_greedy_on_30q_su4():
         Xe, ye = collect(n, B.SV_C64, gates, widths=(3, 5), plain=False)
         pe = B.sv_costmodel_predict(m, Xe)
         mae = float(np.mean(np.abs(pe - ye)))
-        widths = [3, 4, 5, 6]
-        meas = [time_circuit(n, B.SV_C64, circ, B.make_opts(B.SV_PLAN_GREEDY, w), reps=1)[0] for w in widths]
-        pr = np.argsort(np.argsort([pred[w - 1] for w in widths]))
+        # plans: greedy widths 3..6 and the pass plan (prediction index 6)
+        cands = [(w, B.make_opts(B.SV_PLAN_GREEDY, w)) for w in (3, 4, 5, 6)] + [(0, B.make_opts(B.SV_PLAN_PASSES))]
+        meas = [time_circuit(n, B.SV_C64, circ, o, reps=1)[0] for _, o in cands]
+        pr = np.argsort(np.argsort([pred[w - 1] if w else pred[6] for w, _ in cands]))
         mr = np.argsort(np.argsort(meas))
         rho = float(np.corrcoef(pr, mr)[0, 1])
-        say(f"held-out: mean |ln pred - ln meas| (ms/GB) = {mae:.3f}; plan widths {widths}: measured ms "
+        say(f"held-out: mean |ln pred - ln meas| (ms/GB) = {mae:.3f}; plans [3, 4, 5, 6, passes]: measured ms "
             f"{np.round(np.array(meas) * 1e3, 1)}, Spearman(pred, meas) = {rho:.2f}")
         assert mae < 0.5
         assert rho >= 0.7
