@@ -51,7 +51,7 @@ __device__ __forceinline__ doublex4 mma16(double a, double b, doublex4 c)
 }
 
 template <typename R, int TA_LOG, bool PAIR>
-__global__ __launch_bounds__(kThreads) void k_pass(R *__restrict__ st, const TileArgs a,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && PAIR ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
                                                    const PassSub *__restrict__ subs, int nsub,
                                                    const char *__restrict__ mats)
 {
@@ -90,22 +90,34 @@ __global__ __launch_bounds__(kThreads) void k_pass(R *__restrict__ st, const Til
             if (sb + 1 < nsub)
                 load_u(sb + 1, nr, ni);
             const PassSub &d = subs[sb];
-            // slot lookups: xc[r] is linear in the bits of r
+            // LDS addresses.  The slot deposit of a group index and the XOR
+            // swizzle are both linear over XOR, and the index splits into
+            // disjoint lane bits (row bits from bkk or the accumulator row,
+            // group bits 0..3 from bj) and wave-uniform bits (row bits from
+            // the k-step or register, group bits from wave + 4 j): the lane
+            // parts are computed once per block, the uniform parts on the
+            // scalar unit, and each access costs one XOR.
             const uint32_t x1 = d.xc[1], x2 = d.xc[2], x4 = d.xc[4], x8 = d.xc[8];
             const uint32_t xb_lane = ((bkk & 1) ? x1 : 0u) | ((bkk & 2) ? x2 : 0u);
             const uint32_t xo_lane = F64 ? (((q & 1) ? x1 : 0u) | ((q & 2) ? x2 : 0u))
                                          : (((q & 1) ? x4 : 0u) | ((q & 2) ? x8 : 0u));
-            uint32_t xg[PER_WAVE];
-#pragma unroll
-            for (int j = 0; j < PER_WAVE; ++j) {
-                uint32_t g = uint32_t((wave + 4 * j) * NT + bj);
+            auto deposit = [&](uint32_t g) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const uint32_t lo = d.tslot_m[b];
                     g = (g & lo) | ((g & ~lo) << 1);
                 }
-                xg[j] = g;
-            }
+                return g;
+            };
+            // byte offsets into the tile (the XOR parts scale with it)
+            constexpr int SH = F64 ? 4 : 3;
+            const uint32_t gl = deposit(uint32_t(bj));
+            const uint32_t in_lane = swz(xb_lane | gl) << SH, out_lane = swz(xo_lane | gl) << SH;
+            uint32_t hj[PER_WAVE];
+#pragma unroll
+            for (int j = 0; j < PER_WAVE; ++j)
+                hj[j] = swz(deposit(uint32_t(wave + 4 * j) * NT)) << SH;
+            char *tb = reinterpret_cast<char *>(t);
             AccT p1[PER_WAVE], p2[PER_WAVE], p3[PER_WAVE];
 #pragma unroll
             for (int j = 0; j < PER_WAVE; ++j) {
@@ -115,27 +127,29 @@ __global__ __launch_bounds__(kThreads) void k_pass(R *__restrict__ st, const Til
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const uint32_t xs = d.xc[s * KT] | xb_lane;
+                const uint32_t ss = swz(d.xc[s * KT]) << SH;
                 const R us = ur[s] + ui[s];
 #pragma unroll
                 for (int j = 0; j < PER_WAVE; ++j) {
-                    const C x = t[swz(xs | xg[j])];
+                    const C x = *reinterpret_cast<const C *>(tb + (in_lane ^ (ss ^ hj[j])));
                     p1[j] = mma16(ur[s], x.x, p1[j]);
                     p2[j] = mma16(ui[s], x.y, p2[j]);
                     p3[j] = mma16(us, x.x + x.y, p3[j]);
                 }
             }
-            __syncthreads();
+            // Each item writes back exactly the 16 groups x 16 rows it read,
+            // so no other wave touches these locations within this block:
+            // only the next block (other slots) needs the barrier below.
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 // accumulator row: 4 (lane / 16) + r (FP32), 4 r + lane / 16 (FP64)
-                const uint32_t xrow = xo_lane | d.xc[F64 ? 4 * r : r];
+                const uint32_t rr = swz(d.xc[F64 ? 4 * r : r]) << SH;
 #pragma unroll
                 for (int j = 0; j < PER_WAVE; ++j) {
                     C y;
                     y.x = p1[j][r] - p2[j][r];
                     y.y = p3[j][r] - p1[j][r] - p2[j][r];
-                    t[swz(xrow | xg[j])] = y;
+                    *reinterpret_cast<C *>(tb + (out_lane ^ (rr ^ hj[j]))) = y;
                 }
             }
             __syncthreads();

@@ -38,14 +38,15 @@ def run_ops(h, ops, mode=B.SV_PLAN_GREEDY, kmax=5):
             seg.append(op)
 
 
+@pytest.mark.parametrize("mode", [B.SV_PLAN_GREEDY, B.SV_PLAN_PASSES], ids=["greedy", "passes"])
 @pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64], ids=["c128", "c64"])
-def test_share_twin_20q_matches_reference(dtype):
+def test_share_twin_20q_matches_reference(dtype, mode):
     n = 20
     ops = W.share_layers(n, 10, W.circuit_seed(3, 1))
     want = oracle.run(ops, n)
     h = B.sv_create(n, dtype)
     try:
-        run_ops(h, ops)
+        run_ops(h, ops, mode)
         got = B.sv_copy_to_host(h, n, dtype).astype(np.complex128)
         assert float(np.max(np.abs(got - want))) <= TOL[dtype]
         assert B.sv_qubit_map(h, n) != list(range(n))  # 5 exchanges: odd, so relaid out
@@ -79,22 +80,24 @@ def test_full_share_256gib(n, dtype):
         assert np.array_equal(B.sv_copy_to_host(h, n, dtype, 0, w).view(np.uint8), lo0.view(np.uint8))
         assert np.array_equal(B.sv_copy_to_host(h, n, dtype, (1 << n) - w, w).view(np.uint8), hi0.view(np.uint8))
 
-        # two layers of the share workload (one exchange) and their mirror
-        B.sv_reset(h)
+        # two layers of the share workload (one exchange) and their mirror, as
+        # greedy sweeps and as LDS passes (2^23 pass tiles: a 2-D grid)
         ops = W.share_layers(n, 2, W.circuit_seed(3, 1))
-        say(f"{n}q: {W.gate_count(ops)} gates + exchanges, then the mirror")
-        run_ops(h, ops)
-        norm = B.sv_probabilities(h, [])[0]
-        assert abs(norm - 1) <= (1e-12 if dtype == B.SV_C128 else 1e-5)
-        run_ops(h, W.inverse(ops))
-        assert B.sv_qubit_map(h, n) == list(range(n))
-        a0 = complex(B.sv_copy_to_host(h, n, dtype, 0, 1)[0])
-        tol = 10 * TOL[dtype]
-        assert abs(a0 - 1) <= tol, a0
-        p = B.sv_probabilities(h, [0, n - 1, n // 2])
-        assert abs(p[0] - 1) <= tol and np.all(p[1:] <= tol)
-        s = B.sv_sample(h, W.uniforms(7, 1000))
-        assert np.all(s == 0)
+        for mode in (B.SV_PLAN_GREEDY, B.SV_PLAN_PASSES):
+            B.sv_reset(h)
+            say(f"{n}q: {W.gate_count(ops)} gates + exchanges, then the mirror (plan mode {mode})")
+            run_ops(h, ops, mode)
+            norm = B.sv_probabilities(h, [])[0]
+            assert abs(norm - 1) <= (1e-12 if dtype == B.SV_C128 else 1e-5)
+            run_ops(h, W.inverse(ops), mode)
+            assert B.sv_qubit_map(h, n) == list(range(n))
+            a0 = complex(B.sv_copy_to_host(h, n, dtype, 0, 1)[0])
+            tol = 10 * TOL[dtype]
+            assert abs(a0 - 1) <= tol, a0
+            p = B.sv_probabilities(h, [0, n - 1, n // 2])
+            assert abs(p[0] - 1) <= tol and np.all(p[1:] <= tol)
+            s = B.sv_sample(h, W.uniforms(7, 1000))
+            assert np.all(s == 0)
     finally:
         B.sv_destroy(h)
         torch.cuda.empty_cache()
