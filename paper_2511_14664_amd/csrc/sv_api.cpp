@@ -487,7 +487,8 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
             hi = std::max(hi, p);
         }
     int tb[16];
-    const int T = pass_tile_bits(h->n, h->dtype, phys, tb);
+    const size_t nsub = w.subs.size();
+    const int T = pass_tile_bits(h->n, pass_tile_log_for(h->n, h->dtype, int(nsub)), phys, tb);
     if (T < 0) {
         set_error("pass %zu does not fit the pass tile", index);
         return SV_EINVAL;
@@ -495,7 +496,6 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     int slot_of[64];
     for (int b = 0; b < T; ++b)
         slot_of[tb[b]] = b;
-    const size_t nsub = w.subs.size();
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
     const uint64_t mats = w.off + ((nsub * sizeof(PassSub) + 255) & ~uint64_t(255));
@@ -555,7 +555,7 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     if (rc != SV_OK)
         return rc;
     const char *base = static_cast<const char *>(h->d_arena);
-    hipError_t e = launch_pass(h->d_state, h->n, h->dtype, tb, base + w.off, int(nsub), base, h->stream);
+    hipError_t e = launch_pass(h->d_state, h->n, h->dtype, T, tb, base + w.off, int(nsub), base, h->stream);
     if (e != hipSuccess) {
         set_error("pass %zu launch failed: %s", index, hipGetErrorString(e));
         return SV_EDEVICE;

@@ -214,32 +214,34 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v)
 // blockIdx.x, see tile_grid) so that no workgroup loops: a loop would let the
 // compiler hoist the per-tile constants into registers.  PAIR (complex64
 // with physical bit 0 inside the tile) moves amplitude pairs as 16-byte
-// accesses.
+// accesses.  NTH is the workgroup size (256 or 512 threads).
 //
-// compute(tile) must read the tile, __syncthreads(), write its results back
-// into the same LDS slots and __syncthreads() again.
+// compute(tile) starts after a barrier that follows the tile's LDS writes; it
+// must leave its results in the same LDS slots and end with __syncthreads().
 // ---------------------------------------------------------------------------
-template <typename R, int TA_LOG, bool PAIR, typename F>
+template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, typename F>
 __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a, typename CT<R>::C *tile,
                                            F &&compute)
 {
     using C = typename CT<R>::C;
     constexpr int TA = 1 << TA_LOG;
-    constexpr int OPT = TA / kThreads;
+    constexpr int OPT = TA / NTH;
+    constexpr int TB = NTH == 512 ? 9 : 8;  // thread index bits
+    static_assert(NTH == 256 || NTH == 512, "256 or 512 threads");
     static_assert(OPT >= 2 && OPT % 2 == 0, "tile smaller than two elements per thread");
     static_assert(!PAIR || std::is_same<R, float>::value, "16-byte pairs are complex64 only");
     constexpr int LO = PAIR ? 1 : 0;  // tile bits below the thread bits
     const int tid = threadIdx.x;
     uint64_t off_lo = 0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < TB; ++b)
         if ((tid >> b) & 1)
             off_lo |= a.dep[b + LO];
     auto offset = [&](int s) -> uint64_t {
         uint64_t off = off_lo;
 #pragma unroll
-        for (int b = 8 + LO; b < TA_LOG; ++b)
-            if ((s >> (b - 8 - LO)) & 1)
+        for (int b = TB + LO; b < TA_LOG; ++b)
+            if ((s >> (b - TB - LO)) & 1)
                 off |= a.dep[b];
         return off;
     };
@@ -256,7 +258,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
                 q[s] = ld_nt(&v4[(base + offset(s)) >> 1]);
 #pragma unroll
             for (int s = 0; s < OPT / 2; ++s) {
-                const uint32_t x = 2u * uint32_t(s * kThreads + tid);
+                const uint32_t x = 2u * uint32_t(s * NTH + tid);
                 tile[swz(x)] = make_float2(q[s].x, q[s].y);
                 tile[swz(x + 1)] = make_float2(q[s].z, q[s].w);
             }
@@ -274,7 +276,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
                 C q;
                 q.x = qr[s];
                 q.y = qi[s];
-                tile[swz(uint32_t(s * kThreads + tid))] = q;
+                tile[swz(uint32_t(s * NTH + tid))] = q;
             }
         }
         __syncthreads();
@@ -283,7 +285,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
             float4 *v4 = reinterpret_cast<float4 *>(st);
 #pragma unroll
             for (int s = 0; s < OPT / 2; ++s) {
-                const uint32_t x = 2u * uint32_t(s * kThreads + tid);
+                const uint32_t x = 2u * uint32_t(s * NTH + tid);
                 const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
                 st_nt(&v4[(base + offset(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
             }
@@ -291,7 +293,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
             C *v = reinterpret_cast<C *>(st);
 #pragma unroll
             for (int s = 0; s < OPT; ++s)
-                st_nt(&v[base + offset(s)], tile[swz(uint32_t(s * kThreads + tid))]);
+                st_nt(&v[base + offset(s)], tile[swz(uint32_t(s * NTH + tid))]);
         }
     }
 }

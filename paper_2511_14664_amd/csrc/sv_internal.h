@@ -144,11 +144,14 @@ struct PassSub {
     uint64_t pad[5];
 };
 static_assert(sizeof(PassSub) == 128, "pass block descriptor layout");
+// Smallest pass tile width (log2 amplitudes) and the width used for a pass of
+// nsub blocks on an n-qubit state (the smallest or one more).
 int pass_tile_log(int dtype);
-// Sorted physical tile bits of a pass (its qubits + the lowest free bits);
-// returns the tile width T, or -1 if the pass does not fit.
-int pass_tile_bits(int n, int dtype, uint64_t phys_qmask, int *tile_bits);
-hipError_t launch_pass(void *st, int n, int dtype, const int *tile_bits, const void *d_subs, int nsub,
+int pass_tile_log_for(int n, int dtype, int nsub);
+// Sorted physical tile bits of a T-bit pass tile (the pass qubits + the
+// lowest free bits); returns T, or -1 if the pass does not fit.
+int pass_tile_bits(int n, int T, uint64_t phys_qmask, int *tile_bits);
+hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
                        const void *d_mats, hipStream_t s);
 
 // Z strings per launch_expect_z call.

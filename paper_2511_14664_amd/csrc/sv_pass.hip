@@ -3,8 +3,10 @@
 //
 // A pass is a set Q of at most 8 qubits and the blocks of the circuit that act
 // inside Q, in circuit order.  Its tile holds the amplitudes spanned by Q and
-// the lowest free index bits (2^12 complex64 or 2^11 complex128 amplitudes,
-// so that contiguous runs stay at least 128 bytes).  Every block is applied
+// the lowest free index bits (2^12 complex64 or 2^11 complex128 amplitudes on
+// 256 threads, so that contiguous runs stay at least 128 bytes; twice that on
+// 512 threads for passes of at most two (complex64) or three (complex128)
+// blocks, which are bound by HBM).  Every block is applied
 // to the tile in LDS before the tile goes back to HBM: the state moves once
 // per pass instead of once per block, which is the same product of unitaries
 // in the same order (paper Sec. 2.1: gate application as sweeps over the
@@ -50,8 +52,8 @@ __device__ __forceinline__ doublex4 mma16(double a, double b, doublex4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <typename R, int TA_LOG, bool PAIR>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && PAIR ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
+template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThreads && std::is_same<R, float>::value && PAIR ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
                                                    const PassSub *__restrict__ subs, int nsub,
                                                    const char *__restrict__ mats)
 {
@@ -59,9 +61,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::i
     using AccT = typename PassAcc<R>::T;
     constexpr int D = 16, NT = 16, KT = 4, NS = D / KT;
     constexpr int NGS = (1 << (TA_LOG - 4)) / NT;  // group sets (NMT = 1)
-    constexpr int PER_WAVE = NGS / 4;
+    constexpr int NW = NTH / 64;  // waves
+    constexpr int PER_WAVE = NGS / NW;
     constexpr bool F64 = std::is_same<R, double>::value;
-    static_assert(NGS % 4 == 0 && PER_WAVE >= 1, "tile shape");
+    static_assert(NGS % NW == 0 && PER_WAVE >= 1, "tile shape");
 
     __shared__ C tile[1 << TA_LOG];
     const int tid = threadIdx.x;
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::i
     R ur[NS], ui[NS];
     load_u(0, ur, ui);  // in flight with the tile's loads
 
-    tile_sweep<R, TA_LOG, PAIR>(st, a, tile, [&](C *t) {
+    tile_sweep<R, TA_LOG, PAIR, NTH>(st, a, tile, [&](C *t) {
         for (int sb = 0; sb < nsub; ++sb) {
             R nr[NS], ni[NS];
             if (sb + 1 < nsub)
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::i
             // swizzle are both linear over XOR, and the index splits into
             // disjoint lane bits (row bits from bkk or the accumulator row,
             // group bits 0..3 from bj) and wave-uniform bits (row bits from
-            // the k-step or register, group bits from wave + 4 j): the lane
+            // the k-step or register, group bits from wave + NW j): the lane
             // parts are computed once per block, the uniform parts on the
             // scalar unit, and each access costs one XOR.
             const uint32_t x1 = d.xc[1], x2 = d.xc[2], x4 = d.xc[4], x8 = d.xc[8];
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::i
             uint32_t hj[PER_WAVE];
 #pragma unroll
             for (int j = 0; j < PER_WAVE; ++j)
-                hj[j] = swz(deposit(uint32_t(wave + 4 * j) * NT)) << SH;
+                hj[j] = swz(deposit(uint32_t(wave + NW * j) * NT)) << SH;
             char *tb = reinterpret_cast<char *>(t);
             AccT p1[PER_WAVE], p2[PER_WAVE], p3[PER_WAVE];
 #pragma unroll
@@ -164,17 +167,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(std::i
     });
 }
 
-template <typename R, int TA_LOG>
+template <typename R, int TA_LOG, int NTH>
 hipError_t launch_pass_t(void *st, const TileArgs &a, const void *subs, int nsub, const void *mats, hipStream_t s)
 {
-    const dim3 grid = tile_grid(a.ntiles);
-    const PassSub *ps = static_cast<const PassSub *>(subs);
-    const char *m = static_cast<const char *>(mats);
-    if (std::is_same<R, float>::value && a.dep[0] == 1)
-        hipLaunchKernelGGL((k_pass<R, TA_LOG, std::is_same<R, float>::value>), grid, dim3(kThreads), 0, s, (R *)st, a,
-                           ps, nsub, m);
-    else
-        hipLaunchKernelGGL((k_pass<R, TA_LOG, false>), grid, dim3(kThreads), 0, s, (R *)st, a, ps, nsub, m);
+    constexpr bool F32 = std::is_same<R, float>::value;
+    // a pass tile always holds physical bit 0 (a pass qubit or the lowest
+    // free bit), so complex64 moves 16-byte amplitude pairs
+    if (F32 && a.dep[0] != 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_pass<R, TA_LOG, F32, NTH>), tile_grid(a.ntiles), dim3(NTH), 0, s, (R *)st, a,
+                       static_cast<const PassSub *>(subs), nsub, static_cast<const char *>(mats));
     return hipGetLastError();
 }
 
@@ -185,11 +187,22 @@ int pass_tile_log(int dtype)
     return dtype == SV_C64 ? 12 : 11;
 }
 
-int pass_tile_bits(int n, int dtype, uint64_t phys_qmask, int *tile_bits)
+int pass_tile_log_for(int n, int dtype, int nsub)
 {
+    // Passes with few blocks are bound by HBM, and twice the tile (512
+    // threads, 64 KiB of LDS) doubles the contiguous runs of a pass whose
+    // qubits are all high (128 -> 256 bytes); with more blocks the matrix
+    // cores bind and the smaller tile, with more workgroups per CU, overlaps
+    // better.  Small states keep the small tile (enough tiles to spread).
     const int T = pass_tile_log(dtype);
+    const int few = dtype == SV_C64 ? 2 : 3;
+    return (nsub <= few && n >= T + 1 + 6) ? T + 1 : T;
+}
+
+int pass_tile_bits(int n, int T, uint64_t phys_qmask, int *tile_bits)
+{
     const int q = __builtin_popcountll(phys_qmask);
-    if (n < T || n > 63 || q > kMaxPassQubits || (phys_qmask >> n) != 0)
+    if (T < 1 || T > 16 || n < T || n > 63 || q > kMaxPassQubits || (phys_qmask >> n) != 0)
         return -1;
     int got = 0;
     for (int p = 0; p < n; ++p)
@@ -204,11 +217,11 @@ int pass_tile_bits(int n, int dtype, uint64_t phys_qmask, int *tile_bits)
     return T;
 }
 
-hipError_t launch_pass(void *st, int n, int dtype, const int *tile_bits, const void *d_subs, int nsub,
+hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
                        const void *d_mats, hipStream_t s)
 {
-    const int T = pass_tile_log(dtype);
-    if (nsub < 1 || n < T)
+    const int T0 = pass_tile_log(dtype);
+    if (nsub < 1 || (T != T0 && T != T0 + 1) || n < T)
         return hipErrorInvalidValue;
     TileArgs a{};
     std::vector<int> bits(tile_bits, tile_bits + T);
@@ -217,8 +230,10 @@ hipError_t launch_pass(void *st, int n, int dtype, const int *tile_bits, const v
     a.outer = make_insert_masks(bits);
     a.ntiles = uint64_t(1) << (n - T);
     if (dtype == SV_C64)
-        return launch_pass_t<float, 12>(st, a, d_subs, nsub, d_mats, s);
-    return launch_pass_t<double, 11>(st, a, d_subs, nsub, d_mats, s);
+        return T == 12 ? launch_pass_t<float, 12, kThreads>(st, a, d_subs, nsub, d_mats, s)
+                       : launch_pass_t<float, 13, 512>(st, a, d_subs, nsub, d_mats, s);
+    return T == 11 ? launch_pass_t<double, 11, kThreads>(st, a, d_subs, nsub, d_mats, s)
+                   : launch_pass_t<double, 12, 512>(st, a, d_subs, nsub, d_mats, s);
 }
 
 }  // namespace sv
