@@ -30,12 +30,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["layered", "share", "batch", "su4"], default="layered",
+    ap.add_argument("--workload", choices=["layered", "share", "batch", "su4", "rcs", "qpe"], default="layered",
                     help="layered: 28-qubit random layered circuit (the headline line); share: 34q complex128 / "
                          "35q complex64 share with 6-bit exchanges every 2 layers; batch: 512 HEA circuits "
                          "of 10..22 qubits in one graph launch vs one launch per gate; su4: 30-qubit U3 + "
-                         "SU(4) circuit, depth 40, greedy vs learned fusion plan")
-    ap.add_argument("--qubits", type=int, default=28)
+                         "SU(4) circuit, depth 40, greedy vs learned fusion plan; rcs / qpe: the paper's "
+                         "random-circuit and phase-estimation workloads (33 qubits complex64, 1000 shots), "
+                         "time to solution")
+    ap.add_argument("--qubits", type=int, default=None, help="28 (layered) or 33 (rcs, qpe)")
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--mode", choices=["plain", "greedy", "learned", "passes"], default="passes")
     ap.add_argument("--pass-qubits", type=int, default=8, help="qubits per LDS pass (--mode passes)")
@@ -78,7 +80,9 @@ def main():
         return bench_share(args)
     if args.workload == "su4":
         return bench_su4(args)
-    n = args.qubits
+    if args.workload in ("rcs", "qpe"):
+        return bench_paper33(args)
+    n = args.qubits or 28
     dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
     S = 8 if dtype == B.SV_C64 else 16
     gates = W.layered_u3_pairing(n, 20, W.circuit_seed(2, 1), "cx_or_cz")
@@ -353,6 +357,80 @@ def bench_su4(args):
            "learned_ms": res["learned"]["ms_per_circuit"], "learned_sweeps": res["learned"]["sweeps"],
            "gain": round(res["greedy"]["ms_per_circuit"] / res["learned"]["ms_per_circuit"], 3),
            "max_abs_diff_first_4096_amps": float(np.max(np.abs(res["greedy"]["amp"] - res["learned"]["amp"])))}
+    print(json.dumps(out), flush=True)
+
+
+def bench_paper33(args):
+    """The paper's single-GPU workloads (Sec. 2.2), synthesised, at 33 qubits
+    complex64: random circuit sampling (30n gates: CZ with probability 0.25,
+    else H/RX/RY/RZ) or textbook phase estimation of an exactly representable
+    phase on n - 1 counting qubits.  Time to solution per circuit = reset, the
+    circuit and 1000 shots, synchronised, for the pass plan and the greedy
+    plan.  Phase estimation is checked in the same run: every shot must return
+    the phase register value m."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2511_14664_amd import _binding as B
+
+    n = args.qubits or 33
+    if args.workload == "rcs":
+        gates = W.rcs_circuit(n, W.circuit_seed(6, 1))
+        want = None
+        paper = {"A100_s": 5.907, "gates": 30 * 33}
+    else:
+        k = n - 1
+        m = 0x5A5A5A5A5A5A5A5A & ((1 << k) - 1)
+        gates = W.qpe_circuit(k, m)
+        want = m | (1 << k)
+        paper = {"A100_s": 3.804, "GB200_s": 0.843, "gates": 625}
+    circ = B.Circuit(gates)
+    uni = W.uniforms(7, 1000)
+    torch.cuda.empty_cache()
+    h = B.sv_create(n, B.SV_C64)
+    res = {}
+    plans = (("passes", B.make_opts(B.SV_PLAN_PASSES, args.max_fused, B.SV_PREC_NATIVE, args.pass_qubits)),
+             ("greedy", B.make_opts(B.SV_PLAN_GREEDY, args.max_fused)))
+    for name, opts in plans:
+        def run():
+            B.sv_reset(h)
+            st = B.sv_apply_circuit(h, circ, opts)
+            return st, B.sv_sample(h, uni)
+        log(f"{args.workload}: {n} qubits c64, {len(gates)} gates, plan {name}")
+        for _ in range(max(args.warmup, 1)):
+            run()
+        B.sv_profile_read(h)
+        B.sv_profile_enable(h, True)
+        ts, ok = [], True
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, shots = run()
+            ts.append(time.perf_counter() - t0)
+            if want is not None:
+                ok = ok and bool(np.all(shots == want))
+        B.sv_profile_enable(h, False)
+        recs = B.sv_profile_read(h, 1 << 18)
+        kern_ms = sum(r["ms"] for r in recs) / args.steps
+        kern_bytes = sum(r["bytes"] for r in recs) / args.steps
+        res[name] = {"s_per_circuit": round(float(np.median(ts)), 4), "s_min": round(float(np.min(ts)), 4),
+                     "sweeps": st["sweeps"], "kernel_ms": round(kern_ms, 2),
+                     "achieved_GB/s": round(kern_bytes / (kern_ms * 1e6), 1) if kern_ms > 0 else None,
+                     "gate_apps_per_s": round(len(gates) / float(np.median(ts)), 1)}
+        if want is not None:
+            res[name]["all_shots_equal_m"] = ok
+        log(f"  {res[name]}")
+    B.sv_destroy(h)
+    best = min(res, key=lambda x: res[x]["s_per_circuit"])
+    label = ("random circuit sampling (30n gates, CZ p=0.25 else H/RX/RY/RZ)" if args.workload == "rcs" else
+             f"phase estimation, {n - 1} counting qubits, exact phase")
+    out = {"metric": "time to solution per circuit incl. 1000 shots", "value": res[best]["s_per_circuit"],
+           "unit": "s", "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"{n}-qubit {label}, c64, {len(gates)} gates, 1000 shots", "qubits": n,
+                      "plan": best},
+           "plans": res, "paper_context_other_hardware": paper}
     print(json.dumps(out), flush=True)
 
 
