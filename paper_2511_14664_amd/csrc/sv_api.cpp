@@ -462,16 +462,81 @@ int run_groups(sv_state *h, const std::vector<Block> &gates, const std::vector<G
 }
 
 // One pass of an SV_PLAN_PASSES plan: its gates grouped into sub-blocks of at
-// most four qubits (pass kernel) or, when some gate is wider or the state is
-// below the pass tile, into ordinary <= max_fused sweeps.
+// most four qubits (pass kernel; phase gates reaching outside the tile ride on
+// them as per-tile phases) or, when some gate is wider or the state is below
+// the pass tile, into ordinary <= max_fused sweeps.
 struct PassWork {
     bool kernel = false;
-    uint64_t qmask = 0;      // logical qubits of the pass
+    uint64_t qmask = 0;      // logical tile qubits of the pass
+    uint64_t omask = 0;      // logical qubits only phase gates touch (outside the tile)
     std::vector<Group> subs; // members index the circuit's gate list
+    std::vector<std::vector<int>> front, back;
+    std::vector<uint64_t> vq;  // per block: outer qubits whose values select its matrix variant
     uint64_t off = 0;        // arena range of the pass: [off, off + bytes)
     uint64_t bytes = 0;
+    uint64_t nterm_max = 0;  // bound on the pass's phase terms
     int ngates = 0;
 };
+
+// Monomials of a phase gate's angle: a diagonal gate on qubits Q (targets,
+// then controls) multiplies basis state x by exp(i f(x)), f(x) = arg U[x_t]
+// when every control bit is 1, else 0.  Written as a sum over subsets S of Q,
+// f(x) = sum_S alpha_S prod_{q in S} x_q, alpha_S = sum_{T subset of S}
+// (-1)^{|S \ T|} f(T) (Moebius inversion over the subset lattice).
+static void phase_monomials(const Block &g, int qubits[kMaxPhaseQubits], int &nq, std::vector<double> &alpha)
+{
+    nq = 0;
+    for (int j = 0; j < g.k; ++j)
+        qubits[nq++] = g.targets[j];
+    for (int j = 0; j < g.c; ++j)
+        qubits[nq++] = g.controls[j];
+    const int N = 1 << nq, dk = 1 << g.k, cm = ((1 << g.c) - 1) << g.k;
+    alpha.assign(size_t(N), 0.0);
+    for (int x = 0; x < N; ++x)
+        if ((x & cm) == cm) {
+            const cd u = g.U[size_t(x & (dk - 1)) * dk + (x & (dk - 1))];
+            alpha[size_t(x)] = std::atan2(u.imag(), u.real());
+        }
+    for (int b = 0; b < nq; ++b)
+        for (int x = 0; x < N; ++x)
+            if ((x >> b) & 1)
+                alpha[size_t(x)] -= alpha[size_t(x ^ (1 << b))];
+}
+
+// A phase gate with its qubits outside the tile fixed: `ones` holds the
+// logical qubits (among those outside tmask) whose index bit is 1.  Returns
+// the diagonal block on its in-tile qubits; with none left, k = 0 and U[0]
+// is the scalar phase.
+static Block restrict_phase(const Block &g, uint64_t tmask, uint64_t ones)
+{
+    int qs[kMaxPhaseQubits + 1], nq = 0;
+    for (int j = 0; j < g.k; ++j)
+        qs[nq++] = g.targets[j];
+    for (int j = 0; j < g.c; ++j)
+        qs[nq++] = g.controls[j];
+    Block o;
+    int pos[kMaxPhaseQubits + 1];
+    for (int j = 0; j < nq; ++j)
+        if ((tmask >> qs[j]) & 1) {
+            pos[j] = o.k;
+            o.targets[o.k++] = qs[j];
+        } else {
+            pos[j] = -1;
+        }
+    const int d = 1 << o.k, dk = 1 << g.k, cm = ((1 << g.c) - 1) << g.k;
+    o.U.assign(size_t(d) * d, cd(0.0, 0.0));
+    for (int y = 0; y < d; ++y) {
+        int x = 0;  // the gate's own index: targets, then controls
+        for (int j = 0; j < nq; ++j) {
+            const int bit = pos[j] >= 0 ? ((y >> pos[j]) & 1) : int((ones >> qs[j]) & 1);
+            x |= bit << j;
+        }
+        o.U[size_t(y) * d + y] = (x & cm) == cm ? g.U[size_t(x & (dk - 1)) * dk + (x & (dk - 1))] : cd(1.0, 0.0);
+    }
+    o.diag = true;
+    o.ngates = g.ngates;
+    return o;
+}
 
 // Stage a kernel pass (descriptors, then the 16 x 16 matrices) and launch it.
 int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWork &w, bool launch, size_t index,
@@ -486,9 +551,15 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
             lo = std::min(lo, p);
             hi = std::max(hi, p);
         }
+    uint64_t avoid = 0;  // outer qubits of the pass's phase gates stay outside the tile
+    for (int q = 0; q < h->n; ++q)
+        if ((w.omask >> q) & 1)
+            avoid |= uint64_t(1) << h->qmap[q];
     int tb[16];
     const size_t nsub = w.subs.size();
-    const int T = pass_tile_bits(h->n, pass_tile_log_for(h->n, h->dtype, int(nsub)), phys, tb);
+    int T = pass_tile_bits(h->n, pass_tile_log_for(h->n, h->dtype, int(nsub)), phys, avoid, tb);
+    if (T < 0)
+        T = pass_tile_bits(h->n, pass_tile_log(h->dtype), phys, avoid, tb);
     if (T < 0) {
         set_error("pass %zu does not fit the pass tile", index);
         return SV_EINVAL;
@@ -498,20 +569,82 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
         slot_of[tb[b]] = b;
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
-    const uint64_t mats = w.off + ((nsub * sizeof(PassSub) + 255) & ~uint64_t(255));
+    const uint64_t terms = w.off + ((nsub * sizeof(PassSub) + 255) & ~uint64_t(255));
+    const uint64_t mats = terms + ((w.nterm_max * sizeof(PassTerm) + 255) & ~uint64_t(255));
     if (!launch) {
         PassSub *desc = reinterpret_cast<PassSub *>(static_cast<char *>(h->h_arena) + w.off);
+        PassTerm *tt = reinterpret_cast<PassTerm *>(static_cast<char *>(h->h_arena) + terms);
+        uint64_t nt = 0;
         std::vector<const Block *> mem;
+        std::vector<double> alpha;
+        uint64_t moff = mats;
+        std::vector<Block> restricted;
         for (size_t i = 0; i < nsub; ++i) {
-            mem.clear();
-            for (int m : w.subs[i].members)
-                mem.push_back(&gates[size_t(m)]);
-            const Block b = densify(fuse(mem, w.subs[i].qmask));
+            const uint64_t vq = w.vq[i];
+            const int nv = __builtin_popcountll(vq);
+            int vql[kMaxVariantBits];
+            for (int q = 0, j = 0; q < h->n; ++q)
+                if ((vq >> q) & 1)
+                    vql[j++] = q;
+            // variant 0 (all variant qubits 0) fixes the slot layout
+            auto build = [&](uint32_t var) {
+                uint64_t ones = 0;
+                for (int j = 0; j < nv; ++j)
+                    if ((var >> j) & 1)
+                        ones |= uint64_t(1) << vql[j];
+                mem.clear();
+                restricted.clear();
+                restricted.reserve(w.subs[i].members.size());
+                cd scalar(1.0, 0.0);
+                for (int m : w.subs[i].members) {
+                    const Block &g = gates[size_t(m)];
+                    if ((qubit_mask(g) & ~w.qmask) == 0) {
+                        mem.push_back(&g);
+                        continue;
+                    }
+                    // a phase gate reaching outside the tile (variant blocks only)
+                    restricted.push_back(restrict_phase(g, w.qmask, ones));
+                    if (restricted.back().k == 0) {
+                        scalar *= restricted.back().U[0];
+                        restricted.pop_back();
+                    } else {
+                        mem.push_back(&restricted.back());
+                    }
+                }
+                Block b;
+                if (mem.empty() || nv > 0) {
+                    b = fuse(mem, w.subs[i].qmask, true);
+                } else {
+                    b = densify(fuse(mem, w.subs[i].qmask));
+                }
+                for (cd &u : b.U)
+                    u *= scalar;
+                return b;
+            };
+            Block b = build(0);
+            // slots: the block's qubits, then the in-tile qubits of its phase
+            // gates, then the lowest free tile slots (identity on all of these)
             int slots[4], kk = 0;
             uint32_t used = 0;
+            int lq_of_slot[4] = {-1, -1, -1, -1};
             for (int j = 0; j < b.k; ++j) {
+                lq_of_slot[kk] = b.targets[j];
                 slots[kk] = slot_of[h->qmap[b.targets[j]]];
                 used |= 1u << slots[kk++];
+            }
+            for (int q = 0; q < h->n; ++q) {
+                if (!((w.subs[i].qmask >> q) & 1))
+                    continue;
+                const int sl = slot_of[h->qmap[q]];
+                if ((used >> sl) & 1)
+                    continue;
+                if (kk == 4) {
+                    set_error("pass %zu: block %zu spans more than four tile slots", index, i);
+                    return SV_EINVAL;
+                }
+                lq_of_slot[kk] = q;
+                slots[kk++] = sl;
+                used |= 1u << sl;
             }
             for (int sl = 0; kk < 4 && sl < T; ++sl)
                 if (!((used >> sl) & 1)) {
@@ -527,18 +660,80 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
             std::sort(sorted, sorted + 4);
             for (int j = 0; j < 4; ++j)
                 d.tslot_m[j] = (1u << sorted[j]) - 1u;
-            d.u_off = mats + i * mat16;
+            d.u_off = moff;
+            d.nvar = uint32_t(nv);
+            for (int j = 0; j < nv; ++j)
+                d.vpos[j] = uint8_t(h->qmap[vql[j]]);
+            moff += (uint64_t(1) << nv) * mat16;
+            // phase terms: (physical outer mask, block-local slot mask, side)
+            d.t_off = terms + nt * sizeof(PassTerm);
+            const uint64_t first = nt;
+            // angle -> fixed-point turns (2^64 per turn); equal monomials merge
+            auto add_term = [&](PassTerm t, double a) {
+                double f = a / (2.0 * M_PI);
+                f -= std::floor(f);
+                t.turn = uint64_t(std::ldexp(f, 64) >= 18446744073709551615.0 ? 0.0 : std::ldexp(f, 64));
+                for (uint64_t e = first; e < nt; ++e)
+                    if (tt[e].omask == t.omask && tt[e].smask == t.smask && tt[e].back == t.back) {
+                        tt[e].turn += t.turn;
+                        return;
+                    }
+                if (nt < w.nterm_max)
+                    tt[nt] = t;
+                ++nt;
+            };
+            for (int side = 0; side < 2; ++side)
+                for (int m : (side ? w.back[i] : w.front[i])) {
+                    int qs[kMaxPhaseQubits], nq = 0;
+                    phase_monomials(gates[size_t(m)], qs, nq, alpha);
+                    for (int x = 1; x < (1 << nq); ++x) {
+                        if (alpha[size_t(x)] == 0.0)
+                            continue;
+                        PassTerm t{};
+                        for (int j = 0; j < nq; ++j) {
+                            if (!((x >> j) & 1))
+                                continue;
+                            const int q = qs[j];
+                            if ((w.omask >> q) & 1) {
+                                t.omask |= uint64_t(1) << h->qmap[q];
+                                continue;
+                            }
+                            int pos = -1;
+                            for (int s2 = 0; s2 < 4; ++s2)
+                                if (lq_of_slot[s2] == q)
+                                    pos = s2;
+                            if (pos < 0) {
+                                set_error("pass %zu: phase gate %d outside block %zu", index, m, i);
+                                return SV_EINVAL;
+                            }
+                            t.smask |= 1u << pos;
+                        }
+                        t.back = (side == 1 && t.smask != 0) ? 1u : 0u;
+                        add_term(t, alpha[size_t(x)]);
+                    }
+                    // the constant monomial (x = 0) multiplies the whole tile
+                    if (alpha[0] != 0.0)
+                        add_term(PassTerm{}, alpha[0]);
+                    if (nt > w.nterm_max) {
+                        set_error("pass %zu: phase term table overflow", index);
+                        return SV_EINVAL;
+                    }
+                }
+            d.nterm = uint32_t(nt - first);
             desc[i] = d;
             // U (x) I on the padding slots: row/column bits >= b.k must agree
-            Block u4;
-            u4.k = 4;
-            u4.U.assign(256, cd(0.0, 0.0));
-            const int dk = 1 << b.k;
-            for (int r = 0; r < 16; ++r)
-                for (int c = 0; c < 16; ++c)
-                    if ((r >> b.k) == (c >> b.k))
-                        u4.U[size_t(r) * 16 + c] = b.U[size_t(r & (dk - 1)) * dk + (c & (dk - 1))];
-            stage_matrix(h, u4, d.u_off);
+            for (uint32_t var = 0; var < (1u << nv); ++var) {
+                const Block bv = var == 0 ? b : build(var);
+                Block u4;
+                u4.k = 4;
+                u4.U.assign(256, cd(0.0, 0.0));
+                const int dk = 1 << bv.k;
+                for (int r = 0; r < 16; ++r)
+                    for (int c = 0; c < 16; ++c)
+                        if ((r >> bv.k) == (c >> bv.k))
+                            u4.U[size_t(r) * 16 + c] = bv.U[size_t(r & (dk - 1)) * dk + (c & (dk - 1))];
+                stage_matrix(h, u4, d.u_off + var * mat16);
+            }
         }
         return SV_OK;
     }
@@ -555,7 +750,10 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     if (rc != SV_OK)
         return rc;
     const char *base = static_cast<const char *>(h->d_arena);
-    hipError_t e = launch_pass(h->d_state, h->n, h->dtype, T, tb, base + w.off, int(nsub), base, h->stream);
+    bool phases = false;
+    for (size_t i = 0; i < nsub; ++i)
+        phases = phases || !w.front[i].empty() || !w.back[i].empty();
+    hipError_t e = launch_pass(h->d_state, h->n, h->dtype, T, tb, base + w.off, int(nsub), base, phases, h->stream);
     if (e != hipSuccess) {
         set_error("pass %zu launch failed: %s", index, hipGetErrorString(e));
         return SV_EDEVICE;
@@ -578,18 +776,29 @@ int run_passes(sv_state *h, const std::vector<Block> &gates, int pass_qubits, in
 {
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
-    const std::vector<PassGroup> pg = plan_passes(gates, pass_qubits, max_fused, h->n >= pass_tile_log(h->dtype));
+    const std::vector<PassGroup> pg =
+        plan_passes(gates, pass_qubits, max_fused, h->n, pass_tile_log(h->dtype), h->qmap);
     std::vector<PassWork> work(pg.size());
     uint64_t total = 0;
     for (size_t i = 0; i < pg.size(); ++i) {
         PassWork &w = work[i];
         w.kernel = pg[i].kernel;
         w.qmask = pg[i].qmask;
+        w.omask = pg[i].omask;
         w.subs = pg[i].subs;
+        w.front = pg[i].front;
+        w.back = pg[i].back;
+        w.vq = pg[i].vq;
         w.ngates = pg[i].ngates;
         w.off = total;
         if (w.kernel) {
-            w.bytes = ((w.subs.size() * sizeof(PassSub) + 255) & ~uint64_t(255)) + w.subs.size() * mat16;
+            uint64_t nmat = 0;
+            for (size_t j = 0; j < w.subs.size(); ++j) {
+                w.nterm_max += uint64_t(1 << kMaxPhaseQubits) * (w.front[j].size() + w.back[j].size());
+                nmat += uint64_t(1) << __builtin_popcountll(w.vq[j]);
+            }
+            w.bytes = ((w.subs.size() * sizeof(PassSub) + 255) & ~uint64_t(255)) +
+                      ((w.nterm_max * sizeof(PassTerm) + 255) & ~uint64_t(255)) + nmat * mat16;
         } else {
             for (const Group &g : w.subs) {
                 const Block &first = gates[size_t(g.members[0])];

@@ -389,8 +389,7 @@ int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gate
     for (int k = 1; k <= max_fused; ++k)
         for (const Group &g : group_greedy(gates, k))
             add(shape_record(g), k);
-    const bool tile_fits = n >= pass_tile_log(dtype);
-    for (const PassGroup &w : plan_passes(gates, kMaxPassQubits, max_fused, tile_fits)) {
+    for (const PassGroup &w : plan_passes(gates, kMaxPassQubits, max_fused, n, pass_tile_log(dtype), nullptr)) {
         if (!w.kernel) {
             for (const Group &g : w.subs)
                 add(shape_record(g), 0);

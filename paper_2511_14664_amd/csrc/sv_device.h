@@ -214,12 +214,13 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v)
 // blockIdx.x, see tile_grid) so that no workgroup loops: a loop would let the
 // compiler hoist the per-tile constants into registers.  PAIR (complex64
 // with physical bit 0 inside the tile) moves amplitude pairs as 16-byte
-// accesses.  NTH is the workgroup size (256 or 512 threads).
+// accesses.  NTH is the workgroup size (256 or 512 threads); REMAT
+// recomputes the store addresses after compute() instead of keeping them.
 //
 // compute(tile) starts after a barrier that follows the tile's LDS writes; it
 // must leave its results in the same LDS slots and end with __syncthreads().
 // ---------------------------------------------------------------------------
-template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, typename F>
+template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, bool REMAT = false, typename F>
 __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a, typename CT<R>::C *tile,
                                            F &&compute)
 {
@@ -281,19 +282,39 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
         }
         __syncthreads();
         compute(tile);
+        // REMAT: the store addresses are recomputed from a copy of the thread
+        // index the compiler cannot see through (an empty asm), so they are
+        // not held in registers, or spilled, across a register-hungry
+        // compute().
+        int tid2 = tid;
+        if constexpr (REMAT)
+            asm volatile("" : "+v"(tid2));
+        uint64_t off_lo2 = 0;
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+            if ((tid2 >> b) & 1)
+                off_lo2 |= a.dep[b + LO];
+        auto offset2 = [&](int s) -> uint64_t {
+            uint64_t off = off_lo2;
+#pragma unroll
+            for (int b = TB + LO; b < TA_LOG; ++b)
+                if ((s >> (b - TB - LO)) & 1)
+                    off |= a.dep[b];
+            return off;
+        };
         if constexpr (PAIR) {
             float4 *v4 = reinterpret_cast<float4 *>(st);
 #pragma unroll
             for (int s = 0; s < OPT / 2; ++s) {
-                const uint32_t x = 2u * uint32_t(s * NTH + tid);
+                const uint32_t x = 2u * uint32_t(s * NTH + tid2);
                 const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
-                st_nt(&v4[(base + offset(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
+                st_nt(&v4[(base + offset2(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
             }
         } else {
             C *v = reinterpret_cast<C *>(st);
 #pragma unroll
             for (int s = 0; s < OPT; ++s)
-                st_nt(&v[base + offset(s)], tile[swz(uint32_t(s * NTH + tid))]);
+                st_nt(&v[base + offset2(s)], tile[swz(uint32_t(s * NTH + tid2))]);
         }
     }
 }

@@ -61,20 +61,42 @@ struct Group {
 };
 std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax);
 // Fuse gates into one block on the qubits of qmask (targets ascending); a
-// single member is returned unchanged.
-Block fuse(const std::vector<const Block *> &members, uint64_t qmask);
+// single member is returned unchanged unless dense is set.
+Block fuse(const std::vector<const Block *> &members, uint64_t qmask, bool dense = false);
+// Diagonal gates of at most this many qubits (targets + controls) may act on
+// qubits outside a pass tile, as per-tile phases ("phase gates").
+constexpr int kMaxPhaseQubits = 4;
+// Physical index bits below this are tile bits of every pass: a phase gate's
+// qubits there count towards the pass budget.
+constexpr int kPassLowBits = 6;
+// A pass block whose phase gates reach at most this many qubits outside the
+// tile is staged as one fused matrix per value of those index bits.
+constexpr int kMaxVariantBits = 3;
+bool is_phase_gate(const Block &b);
 // One pass of an SV_PLAN_PASSES plan: the greedy groups of the circuit with a
-// pass_qubits budget, each sub-grouped into <= 4-qubit blocks for the pass
-// kernel (kernel = true) or, when a gate is wider or the state is below the
-// pass tile (tile_fits = false), into <= max_fused-qubit sweeps.  Sub-group
-// members index the circuit's gate list.
+// pass_qubits budget on their tile qubits (qmask); phase gates may also touch
+// qubits outside the tile (omask), which are constant within each tile.  A
+// kernel pass is sub-grouped into <= 4-qubit blocks: subs[i].members are the
+// gates fused into block i's matrix, front[i] / back[i] the phase gates with
+// qubits outside the tile applied just before / after it.  Otherwise (a
+// wider gate, or the state below the pass tile) subs are <= max_fused-qubit
+// sweeps over all the pass's gates.  Member indices refer to the circuit's
+// gate list.  A block with variant qubits vq[i] (outer qubits of its phase
+// gates, at most kMaxVariantBits) instead holds every gate in members, phase
+// gates included, and is staged as one matrix per value of those qubits.
 struct PassGroup {
     bool kernel = false;
     uint64_t qmask = 0;
+    uint64_t omask = 0;
     std::vector<Group> subs;
+    std::vector<std::vector<int>> front, back;
+    std::vector<uint64_t> vq;
     int ngates = 0;
 };
-std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, bool tile_fits);
+// phys: logical -> physical qubit map (nullptr: identity); T0: smallest pass
+// tile (log2 amplitudes) of the state's dtype.
+std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
+                                   const int *phys);
 // A controlled block as a dense unitary on targets + controls (controls
 // become the high bits of the index); uncontrolled blocks are returned as is.
 Block densify(const Block &b);
@@ -141,18 +163,36 @@ struct PassSub {
     uint32_t xc[16];      // tile-local index bits of block row r (bit b of r -> slot of block qubit b)
     uint32_t tslot_m[4];  // insert masks 2^slot - 1 of the block's four slots, ascending
     uint64_t u_off;       // byte offset of the 16 x 16 row-major matrix (state precision) from the matrix base
-    uint64_t pad[5];
+    uint64_t t_off;       // byte offset of the block's phase terms (PassTerm) from the matrix base
+    uint32_t nterm;       // number of phase terms (0: the matrix alone)
+    uint32_t nvar;        // matrix variants 2^nvar, selected by the tile's index bits vpos[0..nvar)
+    uint8_t vpos[8];
+    uint64_t pad[2];
 };
 static_assert(sizeof(PassSub) == 128, "pass block descriptor layout");
+// One monomial of a per-tile phase: where the tile's outer index bits cover
+// omask (physical bits), entry (r, c) of the block matrix gains the angle
+// 2 pi turn / 2^64 if the block-local column index c (front) or row index r
+// (back) covers smask.  Angles in fixed-point turns add exactly and wrap
+// modulo 2 pi by themselves.
+struct PassTerm {
+    uint64_t omask;
+    uint32_t smask;
+    uint32_t back;
+    uint64_t turn;
+};
+static_assert(sizeof(PassTerm) == 24, "pass phase term layout");
 // Smallest pass tile width (log2 amplitudes) and the width used for a pass of
 // nsub blocks on an n-qubit state (the smallest or one more).
 int pass_tile_log(int dtype);
 int pass_tile_log_for(int n, int dtype, int nsub);
 // Sorted physical tile bits of a T-bit pass tile (the pass qubits + the
-// lowest free bits); returns T, or -1 if the pass does not fit.
-int pass_tile_bits(int n, int T, uint64_t phys_qmask, int *tile_bits);
+// lowest free bits outside phys_avoid); returns T, or -1 if the pass does not
+// fit.
+int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *tile_bits);
+// phases: some block carries phase terms (selects the kernel that reads them).
 hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
-                       const void *d_mats, hipStream_t s);
+                       const void *d_mats, bool phases, hipStream_t s);
 
 // Z strings per launch_expect_z call.
 int expect_z_batch();

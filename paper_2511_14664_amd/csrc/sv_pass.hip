@@ -21,6 +21,14 @@
 // on v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64.  The block descriptors
 // are read with scalar loads; the U fragment of the next block is fetched
 // while the current one is multiplied.
+//
+// Diagonal gates may also act on qubits outside the tile.  Those index bits
+// are constant within a tile, so on each tile such a gate is a diagonal
+// phase on the block's slots.  A block whose gates reach few outer qubits is
+// stored as one fused matrix per value of those bits and the tile picks its
+// variant; otherwise the phases are folded into the block's matrix as a
+// column phase (applied before the block) or a row phase (after it), from a
+// list of monomials (outer-bit mask, slot mask, angle) per block.
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -52,7 +60,49 @@ __device__ __forceinline__ doublex4 mma16(double a, double b, doublex4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads>
+// sin and cos of 2 pi u / 2^32 (u: fixed-point turns).  The nearest quarter
+// turn k comes from the top bits, the rest x lies in [-pi/4, pi/4) and goes
+// through the Taylor series of sin and cos (truncation error below
+// (pi/4)^11 / 11! = 2e-9 and (pi/4)^12 / 12! = 1e-10); then the quarter-turn
+// rotation.
+__device__ __forceinline__ void turn_sincos(uint32_t u, float &sn, float &cs)
+{
+    const uint32_t k = (u + (1u << 29)) >> 30;
+    const float x = float(int32_t(u - (k << 30))) * float(2.0 * M_PI / 4294967296.0);
+    const float x2 = x * x;
+    const float s = x * (1.0f + x2 * (-1.0f / 6 + x2 * (1.0f / 120 + x2 * (-1.0f / 5040 + x2 * (1.0f / 362880)))));
+    const float c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24 + x2 * (-1.0f / 720 + x2 * (1.0f / 40320 + x2 * (-1.0f / 3628800)))));
+    sn = (k & 1) ? c : s;
+    cs = (k & 1) ? s : c;
+    if (k & 2)
+        sn = -sn;
+    if ((k + 1) & 2)
+        cs = -cs;
+}
+
+// The same for 2 pi u / 2^64 in FP64: Taylor terms through x^17 (sin) and
+// x^18 (cos), truncation error below (pi/4)^19 / 19! = 2e-19.
+__device__ __forceinline__ void turn_sincos(uint64_t u, double &sn, double &cs)
+{
+    const uint64_t k = (u + (uint64_t(1) << 61)) >> 62;
+    const double x = double(int64_t(u - (k << 62))) * (2.0 * M_PI / 18446744073709551616.0);
+    const double x2 = x * x;
+    double s = 1.0, c = 1.0;
+    // Horner from the highest term: sin = x sum (-x2)^j / (2j+1)!, cos = sum (-x2)^j / (2j)!
+    for (int j = 8; j >= 1; --j)
+        s = 1.0 - x2 / double((2 * j) * (2 * j + 1)) * s;
+    for (int j = 9; j >= 1; --j)
+        c = 1.0 - x2 / double((2 * j - 1) * (2 * j)) * c;
+    s *= x;
+    sn = (k & 1) ? c : s;
+    cs = (k & 1) ? s : c;
+    if (k & 2)
+        sn = -sn;
+    if ((k + 1) & 2)
+        cs = -cs;
+}
+
+template <typename R, int TA_LOG, bool PAIR, int NTH, bool PHASES>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThreads && std::is_same<R, float>::value && PAIR ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
                                                    const PassSub *__restrict__ subs, int nsub,
                                                    const char *__restrict__ mats)
@@ -74,9 +124,17 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
     const int bj = lane % 16, bkk = lane / 16;  // B operand: V[4 s + bkk][group bj]
     const int q = lane / 16;
 
-    // this lane's fragment of block sb's matrix: U[ai][4 s + akk], s < NS
+    // this tile's index bits outside the tile (variant selection, phase terms)
+    const uint64_t tbase = insert_zeros(uint64_t(blockIdx.y) * gridDim.x + blockIdx.x, a.outer);
+    // this lane's fragment of block sb's matrix: U[ai][4 s + akk], s < NS;
+    // a block with variants stores one matrix per value of its selecting
+    // index bits, consecutively
     auto load_u = [&](int sb, R *xr, R *xi) {
-        const C *U = reinterpret_cast<const C *>(mats + subs[sb].u_off) + ai * D + akk;
+        const PassSub &d = subs[sb];
+        uint32_t var = 0;
+        for (uint32_t j = 0; j < d.nvar; ++j)
+            var |= uint32_t((tbase >> d.vpos[j]) & 1) << j;
+        const C *U = reinterpret_cast<const C *>(mats + d.u_off) + size_t(var) * (D * D) + ai * D + akk;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const C u = U[s * KT];
@@ -87,7 +145,66 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
     R ur[NS], ui[NS];
     load_u(0, ur, ui);  // in flight with the tile's loads
 
-    tile_sweep<R, TA_LOG, PAIR, NTH>(st, a, tile, [&](C *t) {
+    auto apply_phases = [&](const PassSub &d) {
+        if (PHASES && d.nterm > 0) {
+            // Phase gates reaching outside the tile: on this tile they are
+            // diagonal phases on the block's slots, folded into U as
+            // U[r][c] * exp(i (front(c) + back(r))).  Angles are summed in
+            // fixed-point turns (exact, wrapping mod 2 pi): 32 bits for
+            // complex64, 64 for complex128.
+            using TurnT = typename std::conditional<F64, uint64_t, uint32_t>::type;
+            const PassTerm *tm = reinterpret_cast<const PassTerm *>(mats + d.t_off);
+            TurnT turn[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                turn[s] = 0;
+            // terms in groups of four, loads first (the scalar loads of a
+            // group are in flight together)
+            constexpr uint32_t G = 4;
+            for (uint32_t e0 = 0; e0 < d.nterm; e0 += G) {
+                uint64_t om[G], tq[G];
+                uint32_t sm[G], bk[G];
+#pragma unroll
+                for (uint32_t j = 0; j < G; ++j) {
+                    const uint32_t e = e0 + j < d.nterm ? e0 + j : e0;
+                    om[j] = tm[e].omask;
+                    sm[j] = tm[e].smask;
+                    bk[j] = tm[e].back;
+                    tq[j] = tm[e].turn;
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < G; ++j) {
+                    if (e0 + j >= d.nterm || (tbase & om[j]) != om[j])
+                        continue;
+                    const TurnT tu = TurnT(F64 ? tq[j] : (tq[j] >> 32));
+                    if (bk[j]) {
+                        if ((uint32_t(ai) & sm[j]) == sm[j])
+#pragma unroll
+                            for (int s = 0; s < NS; ++s)
+                                turn[s] += tu;
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < NS; ++s)
+                            if ((uint32_t(s * KT + akk) & sm[j]) == sm[j])
+                                turn[s] += tu;
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                R sn, cs;
+                turn_sincos(turn[s], sn, cs);
+                const R r0 = ur[s], i0 = ui[s];
+                ur[s] = r0 * cs - i0 * sn;
+                ui[s] = r0 * sn + i0 * cs;
+            }
+        }
+    };
+
+    tile_sweep<R, TA_LOG, PAIR, NTH, true>(st, a, tile, [&](C *t) {
+        // phases of block sb + 1 are folded in at the end of iteration sb,
+        // where no accumulator is live
+        apply_phases(subs[0]);
         for (int sb = 0; sb < nsub; ++sb) {
             R nr[NS], ni[NS];
             if (sb + 1 < nsub)
@@ -162,21 +279,29 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
                     ur[s] = nr[s];
                     ui[s] = ni[s];
                 }
+                apply_phases(subs[sb + 1]);
             }
         }
     });
 }
 
 template <typename R, int TA_LOG, int NTH>
-hipError_t launch_pass_t(void *st, const TileArgs &a, const void *subs, int nsub, const void *mats, hipStream_t s)
+hipError_t launch_pass_t(void *st, const TileArgs &a, const void *subs, int nsub, const void *mats, bool phases,
+                         hipStream_t s)
 {
     constexpr bool F32 = std::is_same<R, float>::value;
     // a pass tile always holds physical bit 0 (a pass qubit or the lowest
     // free bit), so complex64 moves 16-byte amplitude pairs
     if (F32 && a.dep[0] != 1)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_pass<R, TA_LOG, F32, NTH>), tile_grid(a.ntiles), dim3(NTH), 0, s, (R *)st, a,
-                       static_cast<const PassSub *>(subs), nsub, static_cast<const char *>(mats));
+    const PassSub *ps = static_cast<const PassSub *>(subs);
+    const char *m = static_cast<const char *>(mats);
+    if (phases)
+        hipLaunchKernelGGL((k_pass<R, TA_LOG, F32, NTH, true>), tile_grid(a.ntiles), dim3(NTH), 0, s, (R *)st, a, ps,
+                           nsub, m);
+    else
+        hipLaunchKernelGGL((k_pass<R, TA_LOG, F32, NTH, false>), tile_grid(a.ntiles), dim3(NTH), 0, s, (R *)st, a, ps,
+                           nsub, m);
     return hipGetLastError();
 }
 
@@ -199,17 +324,18 @@ int pass_tile_log_for(int n, int dtype, int nsub)
     return (nsub <= few && n >= T + 1 + 6) ? T + 1 : T;
 }
 
-int pass_tile_bits(int n, int T, uint64_t phys_qmask, int *tile_bits)
+int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *tile_bits)
 {
     const int q = __builtin_popcountll(phys_qmask);
-    if (T < 1 || T > 16 || n < T || n > 63 || q > kMaxPassQubits || (phys_qmask >> n) != 0)
+    if (T < 1 || T > 16 || n < T || n > 63 || q > kMaxPassQubits || (phys_qmask >> n) != 0 ||
+        (phys_qmask & phys_avoid) != 0)
         return -1;
     int got = 0;
     for (int p = 0; p < n; ++p)
         if ((phys_qmask >> p) & 1)
             tile_bits[got++] = p;
     for (int p = 0; p < n && got < T; ++p)
-        if (!((phys_qmask >> p) & 1))
+        if (!(((phys_qmask | phys_avoid) >> p) & 1))
             tile_bits[got++] = p;
     if (got != T)
         return -1;
@@ -218,7 +344,7 @@ int pass_tile_bits(int n, int T, uint64_t phys_qmask, int *tile_bits)
 }
 
 hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
-                       const void *d_mats, hipStream_t s)
+                       const void *d_mats, bool phases, hipStream_t s)
 {
     const int T0 = pass_tile_log(dtype);
     if (nsub < 1 || (T != T0 && T != T0 + 1) || n < T)
@@ -230,10 +356,10 @@ hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, 
     a.outer = make_insert_masks(bits);
     a.ntiles = uint64_t(1) << (n - T);
     if (dtype == SV_C64)
-        return T == 12 ? launch_pass_t<float, 12, kThreads>(st, a, d_subs, nsub, d_mats, s)
-                       : launch_pass_t<float, 13, 512>(st, a, d_subs, nsub, d_mats, s);
-    return T == 11 ? launch_pass_t<double, 11, kThreads>(st, a, d_subs, nsub, d_mats, s)
-                   : launch_pass_t<double, 12, 512>(st, a, d_subs, nsub, d_mats, s);
+        return T == 12 ? launch_pass_t<float, 12, kThreads>(st, a, d_subs, nsub, d_mats, phases, s)
+                       : launch_pass_t<float, 13, 512>(st, a, d_subs, nsub, d_mats, phases, s);
+    return T == 11 ? launch_pass_t<double, 11, kThreads>(st, a, d_subs, nsub, d_mats, phases, s)
+                   : launch_pass_t<double, 12, 512>(st, a, d_subs, nsub, d_mats, phases, s);
 }
 
 }  // namespace sv

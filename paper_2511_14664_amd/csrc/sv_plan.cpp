@@ -259,9 +259,9 @@ static void left_multiply(double *Mr, double *Mi, int kb, const Block &g, const 
     }
 }
 
-Block fuse(const std::vector<const Block *> &members, uint64_t qmask)
+Block fuse(const std::vector<const Block *> &members, uint64_t qmask, bool dense)
 {
-    if (members.size() == 1)
+    if (members.size() == 1 && !dense)
         return *members[0];
     Block out;
     int pos[64];
@@ -368,8 +368,10 @@ uint64_t qubit_mask(const Block &b)
 // their union stays within kmax qubits and every block between them acts on
 // qubits disjoint from j's (so j commutes back to i); or, symmetrically, i
 // joins j when everything between is disjoint from i.  Repeats until no
-// merge applies.
-static void merge_groups(std::vector<Group> &g, int kmax)
+// merge applies.  dep[] holds each block's qubits for the commutation test,
+// g[].qmask those that count towards kmax; at most omax qubits of dep lie
+// outside qmask.
+static void merge_groups(std::vector<Group> &g, std::vector<uint64_t> &dep, int kmax, int omax)
 {
     auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
     bool changed = true;
@@ -378,57 +380,81 @@ static void merge_groups(std::vector<Group> &g, int kmax)
         for (size_t i = 0; i < g.size() && !changed; ++i) {
             uint64_t between = 0;  // union of qubits of blocks strictly between i and j
             for (size_t j = i + 1; j < g.size(); ++j) {
-                if (popc(g[i].qmask | g[j].qmask) <= kmax) {
-                    if ((between & g[j].qmask) == 0) {
+                if (popc(g[i].qmask | g[j].qmask) <= kmax &&
+                    popc((dep[i] | dep[j]) & ~(g[i].qmask | g[j].qmask)) <= omax) {
+                    if ((between & dep[j]) == 0) {
                         // move j back into i: members of j follow those of i
                         g[i].members.insert(g[i].members.end(), g[j].members.begin(), g[j].members.end());
                         g[i].qmask |= g[j].qmask;
+                        dep[i] |= dep[j];
                         g.erase(g.begin() + long(j));
+                        dep.erase(dep.begin() + long(j));
                         changed = true;
                         break;
                     }
-                    if ((between & g[i].qmask) == 0) {
+                    if ((between & dep[i]) == 0) {
                         // move i forward into j: members of i precede those of j
                         g[j].members.insert(g[j].members.begin(), g[i].members.begin(), g[i].members.end());
                         g[j].qmask |= g[i].qmask;
+                        dep[j] |= dep[i];
                         g.erase(g.begin() + long(i));
+                        dep.erase(dep.begin() + long(i));
                         changed = true;
                         break;
                     }
                 }
-                between |= g[j].qmask;
-                if (popc(between | g[i].qmask) > 64)
+                between |= dep[j];
+                if (popc(between | dep[i]) > 64)
                     break;
             }
         }
     }
 }
 
-std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
+// The greedy packing over items with qubit masks dep (every qubit the item
+// touches: ordering) and budget masks (the qubits that count towards kmax).
+// With dep == budget this is the plain greedy plan.  Pass planning gives a
+// diagonal gate a second, smaller budget mask (qubits outside a pass tile are
+// constant per tile, so there a diagonal gate needs only its in-tile qubits):
+// a gate joins with its full mask when that fits, else with the small one,
+// and a block may hold at most omax qubits outside its budget.
+static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const std::vector<uint64_t> &budm,
+                                       const std::vector<uint64_t> *minm, int kmax, int omax,
+                                       std::vector<uint64_t> *dep_out)
 {
     struct PB {
         std::vector<int> members;
-        uint64_t qmask = 0;
+        uint64_t qmask = 0, dep = 0;
         bool alive = true;
     };
     std::vector<PB> pb;
     int last[64];
     std::fill(last, last + 64, -1);
     auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
-    for (int i = 0; i < int(gates.size()); ++i) {
-        const uint64_t gm = qubit_mask(gates[i]);
+    auto fits = [&](uint64_t bud, uint64_t dep) { return popc(bud) <= kmax && popc(dep & ~bud) <= omax; };
+    for (int i = 0; i < int(depm.size()); ++i) {
+        const uint64_t gm = depm[size_t(i)];
+        uint64_t gb = budm[size_t(i)];
         int cand = -1;
         for (int q = 0; q < 64; ++q)
             if ((gm >> q) & 1)
                 cand = std::max(cand, last[q]);
-        int target;
-        if (popc(gm) <= kmax && cand >= 0 && popc(pb[cand].qmask | gm) <= kmax) {
-            target = cand;
-        } else {
+        int target = -1;
+        if (cand >= 0) {
+            if (fits(pb[cand].qmask | gb, pb[cand].dep | gm)) {
+                target = cand;
+            } else if (minm && fits(pb[cand].qmask | (*minm)[size_t(i)], pb[cand].dep | gm)) {
+                gb = (*minm)[size_t(i)];
+                target = cand;
+            }
+        }
+        if (target < 0) {
+            if (!fits(gb, gm) && minm && fits((*minm)[size_t(i)], gm))
+                gb = (*minm)[size_t(i)];
             pb.push_back(PB());
             target = int(pb.size()) - 1;
         }
-        if (popc(gm) <= kmax) {
+        if (fits(gb, gm)) {
             for (int q = 0; q < 64; ++q) {
                 if (!((gm >> q) & 1))
                     continue;
@@ -437,65 +463,252 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
                     continue;
                 bool movable = true;
                 for (int r = 0; r < 64 && movable; ++r)
-                    if (((pb[b].qmask >> r) & 1) && last[r] != b)
+                    if (((pb[b].dep >> r) & 1) && last[r] != b)
                         movable = false;
-                if (!movable || popc(pb[target].qmask | pb[b].qmask | gm) > kmax)
+                if (!movable || !fits(pb[target].qmask | pb[b].qmask | gb, pb[target].dep | pb[b].dep | gm))
                     continue;
                 std::vector<int> merged = pb[b].members;
                 merged.insert(merged.end(), pb[target].members.begin(), pb[target].members.end());
                 pb[target].members.swap(merged);
                 pb[target].qmask |= pb[b].qmask;
+                pb[target].dep |= pb[b].dep;
                 pb[b].alive = false;
                 pb[b].members.clear();
                 for (int r = 0; r < 64; ++r)
-                    if ((pb[b].qmask >> r) & 1)
+                    if ((pb[b].dep >> r) & 1)
                         last[r] = target;
             }
         }
         pb[target].members.push_back(i);
-        pb[target].qmask |= gm;
+        pb[target].qmask |= gb;
+        pb[target].dep |= gm;
         for (int q = 0; q < 64; ++q)
             if ((gm >> q) & 1)
                 last[q] = target;
     }
     std::vector<Group> out;
+    std::vector<uint64_t> dep;
     for (const PB &b : pb) {
         if (!b.alive || b.members.empty())
             continue;
         out.push_back(Group{b.members, b.qmask});
+        dep.push_back(b.dep);
     }
-    merge_groups(out, kmax);
+    merge_groups(out, dep, kmax, omax);
+    if (dep_out)
+        *dep_out = dep;
     return out;
 }
 
-std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, bool tile_fits)
+std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
 {
-    const std::vector<Group> pg = group_greedy(gates, pass_qubits);
+    std::vector<uint64_t> m(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i)
+        m[i] = qubit_mask(gates[i]);
+    return greedy_masks(m, m, nullptr, kmax, 64, nullptr);
+}
+
+bool is_phase_gate(const Block &b)
+{
+    return b.diag && b.k + b.c <= kMaxPhaseQubits;
+}
+
+// Qubits a gate acts on non-diagonally (the targets of a non-diagonal matrix;
+// controls and diagonal matrices only multiply by phases).
+static uint64_t nondiag_mask(const Block &b)
+{
+    if (b.diag)
+        return 0;
+    uint64_t m = 0;
+    for (int j = 0; j < b.k; ++j)
+        m |= uint64_t(1) << b.targets[j];
+    return m;
+}
+
+// Sub-blocks of one kernel pass.  Gates whose qubits all lie in the pass
+// tile are packed greedily into <= 4-qubit blocks; a diagonal gate with
+// qubits outside the tile takes part through its in-tile qubits only.  If a
+// block's gates reach at most kMaxVariantBits qubits outside the tile, the
+// block keeps all its gates in order and is staged once per value of those
+// qubits.  Otherwise each such gate is attached to its block as a phase
+// applied before the block's matrix (front: it commutes with every member
+// before it) or after it (back: it commutes with every member after it), and
+// the block is split where neither holds.
+static void pass_subblocks(const std::vector<Block> &gates, const std::vector<int> &members, uint64_t tmask,
+                           PassGroup &w)
+{
+    std::vector<uint64_t> depm(members.size()), budm(members.size());
+    std::vector<char> phase(members.size(), 0);
+    for (size_t i = 0; i < members.size(); ++i) {
+        const Block &g = gates[size_t(members[i])];
+        const uint64_t qm = qubit_mask(g);
+        phase[i] = (qm & ~tmask) != 0;  // only phase gates reach outside the tile
+        depm[i] = budm[i] = qm & tmask;
+    }
+    const std::vector<Group> sub = greedy_masks(depm, budm, nullptr, 4, 64, nullptr);
+    w.subs.clear();
+    w.front.clear();
+    w.back.clear();
+    w.vq.clear();
+    for (const Group &sg : sub) {
+        // few outer qubits: one matrix per value of them, gates kept in order
+        uint64_t outer = 0;
+        for (int i : sg.members)
+            outer |= qubit_mask(gates[size_t(members[size_t(i)])]) & ~tmask;
+        if (__builtin_popcountll(outer) <= kMaxVariantBits) {
+            std::vector<int> all;
+            for (int i : sg.members)
+                all.push_back(members[size_t(i)]);
+            w.subs.push_back(Group{all, sg.qmask});
+            w.front.push_back({});
+            w.back.push_back({});
+            w.vq.push_back(outer);
+            continue;
+        }
+        // sg.members index `members`; walk them in order, splitting where a
+        // phase commutes neither to the front nor to the back
+        std::vector<int> reg, fr, bk;
+        uint64_t qm = 0;
+        auto flush = [&]() {
+            if (reg.empty() && fr.empty() && bk.empty())
+                return;
+            w.subs.push_back(Group{reg, qm});
+            w.front.push_back(fr);
+            w.back.push_back(bk);
+            w.vq.push_back(0);
+            reg.clear();
+            fr.clear();
+            bk.clear();
+            qm = 0;
+        };
+        const size_t m = sg.members.size();
+        for (size_t a = 0; a < m; ++a) {
+            const size_t i = size_t(sg.members[a]);
+            const int gi = members[i];
+            if (!phase[i]) {
+                reg.push_back(gi);
+                qm |= depm[i];
+                continue;
+            }
+            const uint64_t in = depm[i];
+            uint64_t before = 0, after = 0;
+            for (int r : reg)
+                before |= nondiag_mask(gates[size_t(r)]);
+            for (size_t b2 = a + 1; b2 < m; ++b2)
+                if (!phase[size_t(sg.members[b2])])
+                    after |= nondiag_mask(gates[size_t(members[size_t(sg.members[b2])])]);
+            if ((before & in) == 0) {
+                fr.push_back(gi);
+            } else if ((after & in) == 0) {
+                bk.push_back(gi);
+            } else {
+                flush();
+                fr.push_back(gi);
+            }
+            qm |= in;
+        }
+        flush();
+    }
+}
+
+// One pass plan.  phases: 0 = phase gates count all their qubits (no outer
+// qubits); 1 = all their qubits when that fits, else only those at low
+// physical positions; 2 = only those at low physical positions.
+static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n,
+                                        int T0, const int *phys, int phases)
+{
+    std::vector<uint64_t> depm(gates.size()), minm(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) {
+        const Block &g = gates[i];
+        depm[i] = minm[i] = qubit_mask(g);
+        if (phases > 0 && is_phase_gate(g)) {
+            uint64_t low = 0;
+            for (int q = 0; q < 64; ++q)
+                if (((depm[i] >> q) & 1) && (phys ? phys[q] : q) < kPassLowBits)
+                    low |= uint64_t(1) << q;
+            minm[i] = low;
+        }
+    }
+    std::vector<uint64_t> pdep;
+    // a pass keeps at least T0 index bits off its outer qubits for the tile
+    const int omax = std::max(0, n - T0);
+    const std::vector<Group> pg = phases == 2 ? greedy_masks(depm, minm, nullptr, pass_qubits, omax, &pdep)
+                                              : greedy_masks(depm, depm, &minm, pass_qubits, omax, &pdep);
     std::vector<PassGroup> out(pg.size());
     std::vector<Block> mem;
     for (size_t i = 0; i < pg.size(); ++i) {
         PassGroup &w = out[i];
         w.qmask = pg[i].qmask;
-        mem.clear();
-        for (int m : pg[i].members) {
-            mem.push_back(gates[size_t(m)]);
+        w.omask = pdep[i] & ~pg[i].qmask;
+        for (int m : pg[i].members)
             w.ngates += gates[size_t(m)].ngates;
+        const int q = __builtin_popcountll(w.qmask), o = __builtin_popcountll(w.omask);
+        w.kernel = n >= T0 && q >= 1 && q <= kMaxPassQubits && n - o >= T0;
+        if (w.kernel) {
+            pass_subblocks(gates, pg[i].members, w.qmask, w);
+            for (const Group &g : w.subs)
+                if (__builtin_popcountll(g.qmask) > 4)
+                    w.kernel = false;
         }
-        auto remap = [&](std::vector<Group> g) {
+        if (!w.kernel) {
+            // ordinary sweeps over the pass's gates (all qubits count)
+            mem.clear();
+            for (int m : pg[i].members)
+                mem.push_back(gates[size_t(m)]);
+            std::vector<Group> g = group_greedy(mem, max_fused);
             for (Group &x : g)
                 for (int &m : x.members)
                     m = pg[i].members[size_t(m)];
-            return g;
-        };
-        w.subs = remap(group_greedy(mem, 4));
-        w.kernel = tile_fits && __builtin_popcountll(w.qmask) <= kMaxPassQubits;
-        for (const Group &g : w.subs)
-            if (__builtin_popcountll(g.qmask) > 4)
-                w.kernel = false;
-        if (!w.kernel)
-            w.subs = remap(group_greedy(mem, max_fused));
+            w.subs = g;
+            w.front.assign(g.size(), {});
+            w.back.assign(g.size(), {});
+            w.vq.assign(g.size(), 0);
+            w.qmask = pdep[i];
+            w.omask = 0;
+        }
     }
     return out;
+}
+
+// Relative time of a pass plan in units of one HBM round trip of the state:
+// a kernel pass costs max(1, 0.53 + 0.22 nsub) (the matrix cores bind from
+// three blocks on: measured slope and intercept of the pass kernel on
+// MI355X, the same in both precisions to within a few percent); a block
+// carrying per-tile phase terms costs 0.31 instead of 0.22 (measured); a
+// sweep costs 1.
+static double pass_plan_cost(const std::vector<PassGroup> &plan)
+{
+    double c = 0.0;
+    for (const PassGroup &w : plan) {
+        if (!w.kernel) {
+            c += double(w.subs.size());
+            continue;
+        }
+        double b = 0.53;
+        for (size_t i = 0; i < w.subs.size(); ++i)
+            b += (w.front[i].empty() && w.back[i].empty()) ? 0.22 : 0.31;
+        c += std::max(1.0, b);
+    }
+    return c;
+}
+
+std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
+                                   const int *phys)
+{
+    std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0);
+    double cbest = pass_plan_cost(best);
+    bool any_phase = false;
+    for (const Block &g : gates)
+        any_phase = any_phase || is_phase_gate(g);
+    for (int ph = 1; ph <= 2 && any_phase; ++ph) {
+        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph);
+        const double c = pass_plan_cost(p);
+        if (c < cbest) {
+            best.swap(p);
+            cbest = c;
+        }
+    }
+    return best;
 }
 
 std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)

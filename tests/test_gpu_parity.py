@@ -487,6 +487,74 @@ def test_pass_plan_after_relayout_and_profile_records(dtype):
         assert all(r["k"] <= 8 and r["ms"] > 0 for r in recs if r["kind_name"] == "pass")
 
 
+def phase_circuit(n, seed, layers=6):
+    """Layers of U3 on every qubit and diagonal gates on random qubits across
+    the register: CP (angles up to +-20 rad), CZ, RZ, doubly controlled P and
+    2-qubit diagonal matrices.  Pass plans take most of them as per-tile
+    phases on qubits outside the pass tile."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            gates.append(Gate("u3", (q,), (), tuple(float(x) for x in rng.uniform(0, 2 * math.pi, 3))))
+        for _ in range(n):
+            kind = int(rng.integers(0, 5))
+            qs = [int(x) for x in rng.permutation(n)[:3]]
+            if kind == 0:
+                gates.append(W.cp(qs[0], qs[1], float(rng.uniform(-20, 20))))
+            elif kind == 1:
+                gates.append(W.cz(qs[0], qs[1]))
+            elif kind == 2:
+                gates.append(Gate("rz", (qs[0],), (), (float(rng.uniform(-9, 9)),)))
+            elif kind == 3:
+                gates.append(Gate("p", (qs[0],), (qs[1], qs[2]), (float(rng.uniform(0, 2 * math.pi)),)))
+            else:
+                d = np.diag(np.exp(1j * rng.uniform(0, 2 * math.pi, 4)))
+                gates.append(Gate("matrix", (qs[0], qs[1]), (), (), d))
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [13, 16, 20])
+def test_pass_plan_phase_gates_match_oracle(dtype, n):
+    gates = phase_circuit(n, 40 + n)
+    want = oracle.run(gates, n)
+    for pq in (6, 8):
+        say(f"phase passes n={n} {DNAME[dtype]} pass_qubits={pq}")
+        with State(n, dtype) as s:
+            st = B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, pq))
+            assert maxerr(s.host(), want) <= TOL[dtype]
+            assert st["gates"] == len(gates)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pass_plan_phase_gates_after_relayout(dtype):
+    n = 18
+    a = phase_circuit(n, 3, 2)
+    b = phase_circuit(n, 4, 4) + W.qpe_circuit(8, 77)
+    want = oracle.run(list(a) + list(b), n)
+    with State(n, dtype) as s:
+        B.sv_apply_circuit(s.h, a, B.make_opts(B.SV_PLAN_PASSES))
+        B.sv_swap_bits(s.h, 0, n - 6, 6)
+        B.sv_swap_bits(s.h, 3, 9, 2)
+        say(f"phase passes after relayout {DNAME[dtype]} map={B.sv_qubit_map(s.h, n)}")
+        B.sv_apply_circuit(s.h, b, B.make_opts(B.SV_PLAN_PASSES))
+        assert maxerr(s.host(), want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pass_plan_qpe_exact_phase(dtype):
+    k, m = 15, 0x5A5A & ((1 << 15) - 1)
+    n = k + 1
+    with State(n, dtype) as s:
+        st = B.sv_apply_circuit(s.h, W.qpe_circuit(k, m), B.make_opts(B.SV_PLAN_PASSES))
+        say(f"qpe passes n={n} {DNAME[dtype]}: {st['sweeps']} sweeps")
+        out = B.sv_sample(s.h, W.uniforms(5, 1000))
+        assert np.all(out == (m | (1 << k)))
+        a = s.host()
+        assert abs(abs(a[m | (1 << k)]) - 1.0) <= TOL[dtype] * 10
+
+
 def test_pass_plan_rejects_bad_options():
     with State(12, B.SV_C64) as s:
         for opts in (B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 3),
