@@ -503,12 +503,33 @@ static void phase_monomials(const Block &g, int qubits[kMaxPhaseQubits], int &nq
                 alpha[size_t(x)] -= alpha[size_t(x ^ (1 << b))];
 }
 
-// A phase gate with its qubits outside the tile fixed: `ones` holds the
-// logical qubits (among those outside tmask) whose index bit is 1.  Returns
-// the diagonal block on its in-tile qubits; with none left, k = 0 and U[0]
-// is the scalar phase.
+// A gate with its qubits outside the tile fixed: `ones` holds the logical
+// qubits (among those outside tmask) whose index bit is 1.  A phase gate
+// (diagonal, <= kMaxPhaseQubits qubits) becomes the diagonal block on its
+// in-tile qubits (with none left, k = 0 and U[0] is the scalar phase); any
+// other gate has only controls outside, and
+// becomes itself on its in-tile controls where those outer controls are all 1,
+// else the identity (k = 0, U[0] = 1).
 static Block restrict_phase(const Block &g, uint64_t tmask, uint64_t ones)
 {
+    if (!is_phase_gate(g)) {
+        Block o = g;
+        o.c = 0;
+        for (int j = 0; j < g.c; ++j) {
+            const int q = g.controls[j];
+            if ((tmask >> q) & 1) {
+                o.controls[o.c++] = q;
+            } else if (!((ones >> q) & 1)) {
+                Block id;
+                id.k = 0;
+                id.U.assign(1, cd(1.0, 0.0));
+                id.diag = true;
+                id.ngates = g.ngates;
+                return id;
+            }
+        }
+        return o;
+    }
     int qs[kMaxPhaseQubits + 1], nq = 0;
     for (int j = 0; j < g.k; ++j)
         qs[nq++] = g.targets[j];

@@ -73,6 +73,10 @@ constexpr int kPassLowBits = 6;
 // tile is staged as one fused matrix per value of those index bits.
 constexpr int kMaxVariantBits = 3;
 bool is_phase_gate(const Block &b);
+// Qubits of a gate that may lie outside a pass tile: every qubit of a phase
+// gate, the controls of any other gate (per tile it is then the gate or the
+// identity).
+uint64_t outer_capable(const Block &b);
 // One pass of an SV_PLAN_PASSES plan: the greedy groups of the circuit with a
 // pass_qubits budget on their tile qubits (qmask); phase gates may also touch
 // qubits outside the tile (omask), which are constant within each tile.  A

@@ -513,6 +513,16 @@ bool is_phase_gate(const Block &b)
     return b.diag && b.k + b.c <= kMaxPhaseQubits;
 }
 
+uint64_t outer_capable(const Block &b)
+{
+    if (is_phase_gate(b))
+        return qubit_mask(b);
+    uint64_t m = 0;
+    for (int j = 0; j < b.c; ++j)
+        m |= uint64_t(1) << b.controls[j];
+    return m;
+}
+
 // Qubits a gate acts on non-diagonally (the targets of a non-diagonal matrix;
 // controls and diagonal matrices only multiply by phases).
 static uint64_t nondiag_mask(const Block &b)
@@ -542,7 +552,7 @@ static void pass_subblocks(const std::vector<Block> &gates, const std::vector<in
     for (size_t i = 0; i < members.size(); ++i) {
         const Block &g = gates[size_t(members[i])];
         const uint64_t qm = qubit_mask(g);
-        phase[i] = (qm & ~tmask) != 0;  // only phase gates reach outside the tile
+        phase[i] = (qm & ~tmask) != 0;  // phase gates, or controls, outside the tile
         depm[i] = budm[i] = qm & tmask;
     }
     const std::vector<Group> sub = greedy_masks(depm, budm, nullptr, 4, 64, nullptr);
@@ -563,6 +573,36 @@ static void pass_subblocks(const std::vector<Block> &gates, const std::vector<in
             w.front.push_back({});
             w.back.push_back({});
             w.vq.push_back(outer);
+            continue;
+        }
+        bool nondiag_outer = false;
+        for (int i : sg.members)
+            if (phase[size_t(i)] && !is_phase_gate(gates[size_t(members[size_t(i)])]))
+                nondiag_outer = true;
+        if (nondiag_outer) {
+            // a gate other than a phase gate, with controls outside the
+            // tile, has no phase form: split into consecutive parts of
+            // <= kMaxVariantBits outer qubits, each staged with variants
+            std::vector<int> part;
+            uint64_t pq = 0, po = 0;
+            for (int i : sg.members) {
+                const uint64_t qm = qubit_mask(gates[size_t(members[size_t(i)])]);
+                if (!part.empty() && __builtin_popcountll(po | (qm & ~tmask)) > kMaxVariantBits) {
+                    w.subs.push_back(Group{part, pq});
+                    w.front.push_back({});
+                    w.back.push_back({});
+                    w.vq.push_back(po);
+                    part.clear();
+                    pq = po = 0;
+                }
+                part.push_back(members[size_t(i)]);
+                pq |= depm[size_t(i)];
+                po |= qm & ~tmask;
+            }
+            w.subs.push_back(Group{part, pq});
+            w.front.push_back({});
+            w.back.push_back({});
+            w.vq.push_back(po);
             continue;
         }
         // sg.members index `members`; walk them in order, splitting where a
@@ -621,12 +661,13 @@ static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pas
     for (size_t i = 0; i < gates.size(); ++i) {
         const Block &g = gates[i];
         depm[i] = minm[i] = qubit_mask(g);
-        if (phases > 0 && is_phase_gate(g)) {
+        const uint64_t cap = phases > 0 ? outer_capable(g) : 0;
+        if (cap) {
             uint64_t low = 0;
             for (int q = 0; q < 64; ++q)
-                if (((depm[i] >> q) & 1) && (phys ? phys[q] : q) < kPassLowBits)
+                if (((cap >> q) & 1) && (phys ? phys[q] : q) < kPassLowBits)
                     low |= uint64_t(1) << q;
-            minm[i] = low;
+            minm[i] = (depm[i] & ~cap) | low;
         }
     }
     std::vector<uint64_t> pdep;
@@ -699,7 +740,7 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
     double cbest = pass_plan_cost(best);
     bool any_phase = false;
     for (const Block &g : gates)
-        any_phase = any_phase || is_phase_gate(g);
+        any_phase = any_phase || outer_capable(g) != 0;
     for (int ph = 1; ph <= 2 && any_phase; ++ph) {
         std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph);
         const double c = pass_plan_cost(p);

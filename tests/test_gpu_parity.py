@@ -527,6 +527,46 @@ def test_pass_plan_phase_gates_match_oracle(dtype, n):
             assert st["gates"] == len(gates)
 
 
+def control_circuit(n, seed, layers=6):
+    """Layers of H/U3 and controlled non-diagonal gates whose controls fall
+    anywhere in the register: CX, doubly controlled U3 and controlled 2-qubit
+    matrices, with some CZ.  Pass plans stage a block whose controls lie
+    outside the tile as one matrix per value of those control bits."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for layer in range(layers):
+        for q in range(n):
+            if layer % 2:
+                gates.append(Gate("h", (q,)))
+            else:
+                gates.append(Gate("u3", (q,), (), tuple(float(x) for x in rng.uniform(0, 2 * math.pi, 3))))
+        for _ in range(n):
+            kind = int(rng.integers(0, 4))
+            qs = [int(x) for x in rng.permutation(n)[:4]]
+            if kind == 0:
+                gates.append(W.cx(qs[0], qs[1]))
+            elif kind == 1:
+                gates.append(Gate("u3", (qs[0],), (qs[1], qs[2]), tuple(float(x) for x in rng.uniform(0, 2 * math.pi, 3))))
+            elif kind == 2:
+                gates.append(Gate("matrix", (qs[0], qs[1]), (qs[2],), (), W.haar_unitary(rng, 4)))
+            else:
+                gates.append(W.cz(qs[0], qs[1]))
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [14, 20])
+def test_pass_plan_outer_controls_match_oracle(dtype, n):
+    gates = control_circuit(n, 60 + n)
+    want = oracle.run(gates, n)
+    for pq in (6, 8):
+        say(f"outer-control passes n={n} {DNAME[dtype]} pass_qubits={pq}")
+        with State(n, dtype) as s:
+            st = B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, pq))
+            assert maxerr(s.host(), want) <= TOL[dtype]
+            assert st["gates"] == len(gates)
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_pass_plan_phase_gates_after_relayout(dtype):
     n = 18
