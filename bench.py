@@ -156,6 +156,17 @@ def main():
                  for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms"])}
 
     traffic = counter_traffic(dom_key, n, dtype, args)
+    # A pass launch also runs its blocks on the matrix cores: the record's
+    # flops count 126 per amplitude per 16 x 16 complex block; the kernel
+    # executes three real 16 x 16 products (96 flops per amplitude).
+    mfma_side = {}
+    if dom_key[0] == "pass" and args.precision == "native":
+        mpeak = 157.3e12 if dtype == B.SV_C64 else 78.6e12
+        mflops = dom["flops"] / dom["launches"] * 96.0 / 126.0
+        mfma_side = {"mfma_flops_per_launch": mflops,
+                     "mfma_frac": round(mflops / (avg_ms / 1e3) / mpeak, 4),
+                     "mfma_peak_TFLOP/s": mpeak / 1e12,
+                     "blocks_per_launch": round(dom["flops"] / dom["launches"] / (126.0 * 2.0 ** n), 2)}
     plain = None
     if not args.no_plain and args.mode != "plain":
         popts = B.make_opts(B.SV_PLAN_PLAIN)
@@ -246,7 +257,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": cname(dom_key), "avg_launch_ms": round(avg_ms, 5),
-                     "bytes_per_launch": avg_bytes},
+                     "bytes_per_launch": avg_bytes, **mfma_side},
         "kernels": breakdown,
         "plain": plain,
         "copy_calibration": copy_cal,

@@ -71,7 +71,7 @@ constexpr int kMaxPhaseQubits = 4;
 constexpr int kPassLowBits = 6;
 // A pass block whose phase gates reach at most this many qubits outside the
 // tile is staged as one fused matrix per value of those index bits.
-constexpr int kMaxVariantBits = 3;
+constexpr int kMaxVariantBits = 4;
 bool is_phase_gate(const Block &b);
 // Qubits of a gate that may lie outside a pass tile: every qubit of a phase
 // gate, the controls of any other gate (per tile it is then the gate or the
