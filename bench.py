@@ -30,13 +30,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["layered", "share", "batch", "su4", "rcs", "qpe"], default="layered",
+    ap.add_argument("--workload", choices=["layered", "share", "batch", "su4", "rcs", "qpe", "tfim"], default="layered",
                     help="layered: 28-qubit random layered circuit (the headline line); share: 34q complex128 / "
                          "35q complex64 share with 6-bit exchanges every 2 layers; batch: 512 HEA circuits "
                          "of 10..22 qubits in one graph launch vs one launch per gate; su4: 30-qubit U3 + "
-                         "SU(4) circuit, depth 40, greedy vs learned fusion plan; rcs / qpe: the paper's "
-                         "random-circuit and phase-estimation workloads (33 qubits complex64, 1000 shots), "
-                         "time to solution")
+                         "SU(4) circuit, depth 40, greedy vs learned fusion plan; rcs / qpe / tfim: the "
+                         "paper's random-circuit, phase-estimation and Trotterised transverse-field Ising "
+                         "workloads (33 qubits complex64, 1000 shots), time to solution")
     ap.add_argument("--qubits", type=int, default=None, help="28 (layered) or 33 (rcs, qpe)")
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--mode", choices=["plain", "greedy", "learned", "passes"], default="passes")
@@ -80,7 +80,7 @@ def main():
         return bench_share(args)
     if args.workload == "su4":
         return bench_su4(args)
-    if args.workload in ("rcs", "qpe"):
+    if args.workload in ("rcs", "qpe", "tfim"):
         return bench_paper33(args)
     n = args.qubits or 28
     dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
@@ -374,8 +374,10 @@ def bench_su4(args):
 def bench_paper33(args):
     """The paper's single-GPU workloads (Sec. 2.2), synthesised, at 33 qubits
     complex64: random circuit sampling (30n gates: CZ with probability 0.25,
-    else H/RX/RY/RZ) or textbook phase estimation of an exactly representable
-    phase on n - 1 counting qubits.  Time to solution per circuit = reset, the
+    else H/RX/RY/RZ), textbook phase estimation of an exactly representable
+    phase on n - 1 counting qubits, or 10 first-order Trotter steps (dt = 0.1,
+    J = h = 1) of the transverse-field Ising model on a periodic 3 x 11
+    triangular lattice, bonds as CX RZ CX.  Time to solution per circuit = reset, the
     circuit and 1000 shots, synchronised, for the pass plan and the greedy
     plan.  Phase estimation is checked in the same run: every shot must return
     the phase register value m."""
@@ -390,6 +392,12 @@ def bench_paper33(args):
         gates = W.rcs_circuit(n, W.circuit_seed(6, 1))
         want = None
         paper = {"A100_s": 5.907, "gates": 30 * 33}
+    elif args.workload == "tfim":
+        if n % 3:
+            raise SystemExit("tfim needs a multiple of 3 qubits (3 x n/3 lattice)")
+        gates = W.tfim_trotter(3, n // 3, 10, 0.1, 1.0, 1.0, "cx")
+        want = None
+        paper = {"A100_s": 71.589, "gates": 2987, "note": "HamLib TFIM lattice, not this synthetic one"}
     else:
         k = n - 1
         m = 0x5A5A5A5A5A5A5A5A & ((1 << k) - 1)
@@ -434,8 +442,9 @@ def bench_paper33(args):
         log(f"  {res[name]}")
     B.sv_destroy(h)
     best = min(res, key=lambda x: res[x]["s_per_circuit"])
-    label = ("random circuit sampling (30n gates, CZ p=0.25 else H/RX/RY/RZ)" if args.workload == "rcs" else
-             f"phase estimation, {n - 1} counting qubits, exact phase")
+    label = {"rcs": "random circuit sampling (30n gates, CZ p=0.25 else H/RX/RY/RZ)",
+             "qpe": f"phase estimation, {n - 1} counting qubits, exact phase",
+             "tfim": f"transverse-field Ising, periodic 3 x {n // 3} triangular lattice, 10 Trotter steps"}[args.workload]
     out = {"metric": "time to solution per circuit incl. 1000 shots", "value": res[best]["s_per_circuit"],
            "unit": "s", "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "dtype": "fp32", "data": "synthetic",

@@ -792,9 +792,10 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
 
 // Run a circuit as LDS passes (SV_PLAN_PASSES), fused, uploaded and launched
 // in chunks of 1, 2, 4, ... passes as in run_groups.
-int run_passes(sv_state *h, const std::vector<Block> &gates, int pass_qubits, int max_fused, int precision, int ngates,
-               sv_run_stats *st)
+int run_passes(sv_state *h, const std::vector<Block> &circuit, int pass_qubits, int max_fused, int precision,
+               int ngates, sv_run_stats *st)
 {
+    const std::vector<Block> gates = prefuse_diagonal_pairs(circuit);
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
     const std::vector<PassGroup> pg =

@@ -371,8 +371,8 @@ int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gate
     };
     // the sweep a group becomes: its shape, padded to four targets where
     // execution pads (the pad is the lowest free qubit >= 6)
-    auto shape_record = [&](const Group &g) {
-        Block b = group_shape(gates, g);
+    auto shape_record = [&](const std::vector<Block> &gl, const Group &g) {
+        Block b = group_shape(gl, g);
         if (b.k == 3 && pads_to_four(n, dtype, b.c, precision)) {
             uint64_t used = qubit_mask(b);
             int pick = -1;
@@ -388,11 +388,12 @@ int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gate
     };
     for (int k = 1; k <= max_fused; ++k)
         for (const Group &g : group_greedy(gates, k))
-            add(shape_record(g), k);
-    for (const PassGroup &w : plan_passes(gates, kMaxPassQubits, max_fused, n, pass_tile_log(dtype), nullptr)) {
+            add(shape_record(gates, g), k);
+    const std::vector<Block> pgates = prefuse_diagonal_pairs(gates);
+    for (const PassGroup &w : plan_passes(pgates, kMaxPassQubits, max_fused, n, pass_tile_log(dtype), nullptr)) {
         if (!w.kernel) {
             for (const Group &g : w.subs)
-                add(shape_record(g), 0);
+                add(shape_record(pgates, g), 0);
             continue;
         }
         sv_sweep_record r{};

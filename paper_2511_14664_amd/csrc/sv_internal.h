@@ -97,6 +97,11 @@ struct PassGroup {
     std::vector<uint64_t> vq;
     int ngates = 0;
 };
+// Runs of gates on one qubit pair whose product is diagonal (CX RZ CX =
+// exp(-i theta/2 Z Z)) become one phase gate, placed at the run's first gate
+// (the gates skipped over act on other qubits and commute with the run), so
+// that pass planning may keep one of the pair outside the tile.
+std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates);
 // phys: logical -> physical qubit map (nullptr: identity); T0: smallest pass
 // tile (log2 amplitudes) of the state's dtype.
 std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,

@@ -651,6 +651,53 @@ static void pass_subblocks(const std::vector<Block> &gates, const std::vector<in
     }
 }
 
+std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates)
+{
+    const size_t N = gates.size();
+    std::vector<char> used(N, 0);
+    std::vector<Block> out;
+    out.reserve(N);
+    std::vector<const Block *> run;
+    for (size_t i = 0; i < N; ++i) {
+        if (used[i])
+            continue;
+        const Block &g = gates[i];
+        const uint64_t pair = qubit_mask(g);
+        if (g.diag || __builtin_popcountll(pair) != 2) {
+            out.push_back(g);
+            continue;
+        }
+        // gates after i on the pair's qubits, up to the first that also
+        // touches another qubit; gates on other qubits commute past the run
+        run.assign(1, &g);
+        std::vector<size_t> idx;
+        bool fused = false;
+        for (size_t j = i + 1; j < N && run.size() < 16; ++j) {
+            if (used[j])
+                continue;
+            const uint64_t m = qubit_mask(gates[j]);
+            if ((m & pair) == 0)
+                continue;
+            if ((m & ~pair) != 0)
+                break;
+            run.push_back(&gates[j]);
+            idx.push_back(j);
+            Block f = fuse(run, pair, true);
+            if (matrix_is_diagonal(f.U, 4)) {
+                f.diag = true;
+                out.push_back(std::move(f));
+                for (size_t x : idx)
+                    used[x] = 1;
+                fused = true;
+                break;
+            }
+        }
+        if (!fused)
+            out.push_back(g);
+    }
+    return out;
+}
+
 // One pass plan.  phases: 0 = phase gates count all their qubits (no outer
 // qubits); 1 = all their qubits when that fits, else only those at low
 // physical positions; 2 = only those at low physical positions.

@@ -1,13 +1,15 @@
 """The paper's single-GPU workloads (Sec. 2.2), synthesised: random circuit
-sampling (30n gates) and textbook phase estimation at 33 qubits complex64
-(64 GiB), the size the paper runs on one GPU.
+sampling (30n gates), textbook phase estimation and Trotterised
+transverse-field Ising evolution at 33 qubits complex64 (64 GiB), the size the
+paper runs on one GPU.
 
 No host here holds a 33-qubit FP64 reference, so the full-size cases are
 checked through results fixed by the mathematics: phase estimation of an
-exactly representable phase returns the phase register value on every shot,
-and a random circuit followed by its adjoint returns to |0...0>.  A reduced
-twin of the random-circuit generator at 20 qubits is compared with the FP64
-reference amplitude by amplitude under every plan.
+exactly representable phase returns the phase register value on every shot, a
+random circuit or an Ising evolution followed by its adjoint returns to
+|0...0>, and without a transverse field the Ising evolution only multiplies
+|0...0> by exp(i J dt E steps).  Reduced twins of the generators are compared
+with the FP64 reference amplitude by amplitude under every plan.
 """
 import numpy as np
 import pytest
@@ -83,5 +85,63 @@ def test_rcs_33q_mirror_returns_to_zero():
         assert float(np.max(np.abs(a[1:]))) <= 1e-4
         p = B.sv_probabilities(h, [n - 1])
         assert abs(p[0] - 1.0) <= 1e-4 and abs(p.sum() - 1.0) <= 1e-4
+    finally:
+        B.sv_destroy(h)
+
+
+@pytest.mark.parametrize("zz", ["cx", "diag"])
+@pytest.mark.parametrize("plan", ["plain", "greedy", "passes"])
+@pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64], ids=["c128", "c64"])
+def test_tfim_twin_18q_matches_reference(dtype, plan, zz):
+    rows, cols = 3, 6
+    n = rows * cols
+    gates = W.tfim_trotter(rows, cols, 4, 0.1, 1.0, 1.0, zz)
+    want = oracle.run(gates, n)
+    say(f"tfim twin n={n} plan={plan} zz={zz}")
+    h = B.sv_create(n, dtype)
+    try:
+        B.sv_apply_circuit(h, gates, PLANS[plan])
+        got = B.sv_copy_to_host(h, n, dtype).astype(np.complex128)
+        assert float(np.max(np.abs(got - want))) <= TOL[dtype]
+    finally:
+        B.sv_destroy(h)
+
+
+@pytest.mark.parametrize("zz", ["cx", "diag"])
+def test_tfim_33q_without_field_is_a_phase(zz):
+    import torch
+
+    rows, cols, steps, dt, J = 3, 11, 10, 0.1, 1.0
+    n = rows * cols
+    E = len(W.triangular_lattice_edges(rows, cols))
+    torch.cuda.empty_cache()
+    say(f"tfim h=0 n={n} zz={zz}")
+    h = B.sv_create(n, B.SV_C64)
+    try:
+        B.sv_apply_circuit(h, W.tfim_trotter(rows, cols, steps, dt, J, 0.0, zz), PLANS["passes"])
+        a = B.sv_copy_to_host(h, n, B.SV_C64, 0, 1 << 12)
+        assert abs(a[0] - np.exp(1j * J * dt * E * steps)) <= 2e-5
+        assert float(np.max(np.abs(a[1:]))) <= 2e-5
+        p = B.sv_probabilities(h, [n - 2, n - 1])
+        assert abs(p[0] - 1.0) <= 1e-5
+    finally:
+        B.sv_destroy(h)
+
+
+def test_tfim_33q_mirror_returns_to_zero():
+    import torch
+
+    rows, cols = 3, 11
+    n = rows * cols
+    gates = W.tfim_trotter(rows, cols, 10, 0.1, 1.0, 1.0, "cx")
+    torch.cuda.empty_cache()
+    say(f"tfim mirror n={n}")
+    h = B.sv_create(n, B.SV_C64)
+    try:
+        B.sv_apply_circuit(h, gates, PLANS["passes"])
+        B.sv_apply_circuit(h, W.inverse(gates), PLANS["passes"])
+        a = B.sv_copy_to_host(h, n, B.SV_C64, 0, 1 << 12)
+        assert abs(a[0] - 1.0) <= 1e-4
+        assert float(np.max(np.abs(a[1:]))) <= 1e-4
     finally:
         B.sv_destroy(h)

@@ -336,6 +336,56 @@ def test_bitswap_relayout_keeps_logical_state():
     assert np.max(np.abs(back - want)) < 1e-14
 
 
+def test_triangular_lattice_structure():
+    for rows, cols in ((3, 3), (3, 11), (4, 5)):
+        e = W.triangular_lattice_edges(rows, cols)
+        n = rows * cols
+        assert len(e) == 3 * n
+        assert len({frozenset(x) for x in e}) == 3 * n and all(a != b for a, b in e)
+        deg = np.bincount(np.array(e).reshape(-1), minlength=n)
+        assert np.all(deg == 6)
+    with pytest.raises(ValueError):
+        W.triangular_lattice_edges(2, 5)
+
+
+def full_op(ops_by_qubit, n):
+    """Kronecker product of one-qubit matrices {qubit: M} (identity elsewhere)."""
+    return kron_chain([ops_by_qubit.get(q, I2) for q in reversed(range(n))])
+
+
+@pytest.mark.parametrize("zz", ["cx", "diag"])
+def test_tfim_trotter_vs_matrix_exponentials(zz):
+    """Each Trotter factor rebuilt independently as scipy's expm of the Pauli
+    sums of the TFIM Hamiltonian (H = -J sum ZZ - h sum X) on 9 qubits."""
+    rows, cols, steps, dt, J, h = 3, 3, 3, 0.13, 0.9, 1.7
+    n = rows * cols
+    a = oracle.run(W.tfim_trotter(rows, cols, steps, dt, J, h, zz), n)
+    zz_sum = sum(full_op({p: PZ, q: PZ}, n) for p, q in W.triangular_lattice_edges(rows, cols))
+    x_sum = sum(full_op({q: PX}, n) for q in range(n))
+    step = scipy.linalg.expm(1j * h * dt * x_sum) @ scipy.linalg.expm(1j * J * dt * zz_sum)
+    want = np.zeros(1 << n, dtype=np.complex128)
+    want[0] = 1.0
+    for _ in range(steps):
+        want = step @ want
+    assert np.max(np.abs(a - want)) < 1e-12
+
+
+def test_tfim_closed_forms():
+    rows, cols, steps, dt = 3, 4, 5, 0.21
+    n = rows * cols
+    E = len(W.triangular_lattice_edges(rows, cols))
+    # no field: the Ising part is diagonal and |0...0> only picks up exp(i J dt E steps)
+    a = oracle.run(W.tfim_trotter(rows, cols, steps, dt, J=1.3, h=0.0), n)
+    assert abs(a[0] - np.exp(1j * 1.3 * dt * E * steps)) < 1e-13
+    assert np.max(np.abs(a[1:])) < 1e-13
+    # no coupling: a product of X rotations by 2 h dt steps on every qubit
+    a = oracle.run(W.tfim_trotter(rows, cols, steps, dt, J=0.0, h=0.8, zz="diag"), n)
+    for q in (0, 5, n - 1):
+        s = ["I"] * n
+        s[q] = "Z"
+        assert abs(oracle.expect_pauli(a, "".join(s)) - math.cos(2 * 0.8 * dt * steps)) < 1e-13
+
+
 def test_golden_paper_sizes():
     with open(os.path.join(GOLDEN, "paper_figures.json")) as f:
         gold = json.load(f)

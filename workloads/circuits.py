@@ -265,6 +265,50 @@ def qpe_circuit(k: int, m: int) -> List[Gate]:
     return gates
 
 
+def triangular_lattice_edges(rows: int, cols: int) -> List[Tuple[int, int]]:
+    """Nearest-neighbour pairs of a triangular lattice of rows x cols sites with
+    periodic boundaries in both directions (site (r, c) is qubit r * cols + c):
+    each site bonds to its right, lower and lower-right neighbours, 3 rows*cols
+    distinct bonds for rows, cols >= 3 (every site has six neighbours).  Stands
+    in for the HamLib TFIM lattice of paper Sec. 2.2, whose data is not
+    available here."""
+    if rows < 3 or cols < 3:
+        raise ValueError("need rows, cols >= 3 for distinct periodic bonds")
+    edges = []
+    for r in range(rows):
+        for c in range(cols):
+            q = r * cols + c
+            for dr, dc in ((0, 1), (1, 0), (1, 1)):
+                edges.append((q, ((r + dr) % rows) * cols + (c + dc) % cols))
+    return edges
+
+
+def tfim_trotter(rows: int, cols: int, steps: int, dt: float, J: float = 1.0, h: float = 1.0,
+                 zz: str = "cx") -> List[Gate]:
+    """First-order Suzuki-Trotter circuit for the transverse-field Ising model
+    H = -J sum_<i,j> Z_i Z_j - h sum_i X_i (paper Eq. of the TFIM, Sec. 2.2) on
+    the periodic triangular lattice: per step exp(i J dt Z_a Z_b) on every bond,
+    then exp(i h dt X_q) = RX(-2 h dt) on every site.  The bond factor is
+    exp(-i theta/2 Z_a Z_b) with theta = -2 J dt, given as CX(a, b) RZ_b(theta)
+    CX(a, b) (zz="cx", the gate-level form of circuit benchmarks) or as its
+    diagonal 4 x 4 matrix (zz="diag", an input matrix like the Haar unitaries)."""
+    edges = triangular_lattice_edges(rows, cols)
+    theta, phi = -2.0 * J * dt, -2.0 * h * dt
+    gates: List[Gate] = []
+    for _ in range(steps):
+        for a, b in edges:
+            if zz == "cx":
+                gates += [cx(a, b), Gate("rz", (b,), (), (theta,)), cx(a, b)]
+            elif zz == "diag":
+                gates.append(Gate("matrix", (a, b), (), (),
+                                  np.diag(np.exp(-0.5j * theta * np.array([1.0, -1.0, -1.0, 1.0])))))
+            else:
+                raise ValueError(zz)
+        for q in range(rows * cols):
+            gates.append(Gate("rx", (q,), (), (phi,)))
+    return gates
+
+
 def uniforms(seed: int, shots: int) -> np.ndarray:
     """Sampling uniforms in [0, 1) (the random numbers the sampler consumes)."""
     return np.random.default_rng(seed).random(shots)
