@@ -364,6 +364,18 @@ int sv_plan_block(sv_plan_handle p, int i, int *k, int *targets, int *c, int *co
 int sv_apply_plan(sv_handle h, sv_plan_handle p, sv_run_stats *stats);
 int sv_plan_destroy(sv_plan_handle p);
 
+/* Structure of the LDS pass plan (SV_PLAN_PASSES, paper Sec. 2.1 fusion
+ * applied as several fused blocks per sweep of the state) that
+ * sv_apply_circuit would use for this gate list on a fresh n-qubit state of
+ * dtype (every qubit at its own index bit).  Host only: no device work.
+ * opts: as for sv_apply_circuit, mode SV_PLAN_PASSES (NULL: defaults).  On
+ * success out[0..7] receive: passes; passes run by the pass kernel; blocks in
+ * those passes; blocks staged as per-tile matrix variants; blocks carrying
+ * per-tile phase terms; ordinary sweeps (passes that fall back to fused
+ * sweeps); input gates the plan applies (each input gate exactly once, so
+ * this equals ngates); 0.  SV_EINVAL for invalid gates or options. */
+int sv_pass_plan_info(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts *opts, int64_t *out);
+
 #ifdef __cplusplus
 }
 #endif

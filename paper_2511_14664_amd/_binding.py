@@ -91,6 +91,7 @@ def _load():
         "sv_plan_block": ([P, I, P, P, P, P, P, P], I),
         "sv_apply_plan": ([P, P, ctypes.POINTER(sv_run_stats)], I),
         "sv_plan_destroy": ([P], I),
+        "sv_pass_plan_info": ([I, I, ctypes.POINTER(sv_gate), I, ctypes.POINTER(sv_plan_opts), P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -259,6 +260,16 @@ def sv_plan_create(n: int, dtype: int, gates, opts: Optional[sv_plan_opts] = Non
     _check(_lib.sv_plan_create(n, dtype, circ.array, circ.n_gates, ctypes.byref(o), ctypes.byref(p)),
            "sv_plan_create")
     return p.value
+
+
+def sv_pass_plan_info(n: int, dtype: int, gates, opts: Optional[sv_plan_opts] = None) -> dict:
+    circ = _as_circuit(gates)
+    out = np.zeros(8, dtype=np.int64)
+    o = opts if opts is not None else make_opts(SV_PLAN_PASSES)
+    _check(_lib.sv_pass_plan_info(n, dtype, circ.array, circ.n_gates, ctypes.byref(o), out.ctypes.data),
+           "sv_pass_plan_info")
+    keys = ("passes", "kernel_passes", "blocks", "variant_blocks", "term_blocks", "sweeps", "gates")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def sv_plan_num_blocks(p: int) -> int:

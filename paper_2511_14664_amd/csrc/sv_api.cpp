@@ -1573,6 +1573,78 @@ int sv_profile_read(sv_handle h, sv_sweep_record *out, int max, int *count)
     return SV_OK;
 }
 
+int sv_pass_plan_info(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts *opts, int64_t *out)
+{
+    clear_error();
+    uint64_t bytes;
+    int rc = sv_state_bytes(n, dtype, &bytes);
+    if (rc != SV_OK)
+        return rc;
+    if (!out) {
+        set_error("NULL output");
+        return SV_EINVAL;
+    }
+    sv_plan_opts o{};
+    o.mode = SV_PLAN_PASSES;
+    o.max_fused = 5;
+    if (opts)
+        o = *opts;
+    if (o.mode != SV_PLAN_PASSES) {
+        set_error("sv_pass_plan_info describes SV_PLAN_PASSES plans");
+        return SV_EINVAL;
+    }
+    if (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS) {
+        set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
+        return SV_EINVAL;
+    }
+    if (o.pass_qubits != 0 && (o.pass_qubits < 4 || o.pass_qubits > kMaxPassQubits)) {
+        set_error("pass_qubits %d: 4..%d (0 for %d)", o.pass_qubits, kMaxPassQubits, kMaxPassQubits);
+        return SV_EINVAL;
+    }
+    sv_plan_opts plain = o;
+    plain.mode = SV_PLAN_PLAIN;
+    plain.pass_qubits = 0;
+    std::vector<Block> gates_b;
+    rc = plan_circuit(n, dtype, gates, ngates, plain, gates_b);
+    if (rc != SV_OK)
+        return rc;
+    const std::vector<Block> pg = prefuse_diagonal_pairs(gates_b);
+    const std::vector<PassGroup> plan =
+        plan_passes(pg, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, n, pass_tile_log(dtype), nullptr);
+    int64_t r[8] = {};
+    std::vector<char> seen(pg.size(), 0);
+    bool twice = false;
+    auto cover = [&](int m) {
+        twice = twice || seen[size_t(m)];
+        seen[size_t(m)] = 1;
+        r[6] += pg[size_t(m)].ngates;
+    };
+    for (const PassGroup &w : plan) {
+        r[0] += 1;
+        if (w.kernel) {
+            r[1] += 1;
+            r[2] += int64_t(w.subs.size());
+            for (size_t i = 0; i < w.subs.size(); ++i) {
+                r[3] += w.vq[i] != 0;
+                r[4] += !w.front[i].empty() || !w.back[i].empty();
+                for (int m : w.front[i])
+                    cover(m);
+                for (int m : w.back[i])
+                    cover(m);
+            }
+        } else {
+            r[5] += int64_t(w.subs.size());
+        }
+        for (const Group &g : w.subs)
+            for (int m : g.members)
+                cover(m);
+    }
+    if (twice)
+        r[6] = -1;  // a gate placed twice: reported as an impossible count
+    std::copy(r, r + 8, out);
+    return SV_OK;
+}
+
 int sv_plan_create(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts *opts, sv_plan_handle *out)
 {
     clear_error();

@@ -144,3 +144,72 @@ def test_greedy_fusion_ratio_on_28q_layers():
     nb = B.sv_plan_num_blocks(p)
     B.sv_plan_destroy(p)
     assert nb < len(gates) / 3, (nb, len(gates))
+
+
+# ---------------------------------------------------------------------------
+# LDS pass plans (host-only structure)
+# ---------------------------------------------------------------------------
+def wide_and_controlled(n, seed):
+    """Layered circuit plus controlled gates, a 5-target matrix (no pass kernel
+    takes it) and diagonal gates across the register."""
+    rng = np.random.default_rng(seed)
+    g = list(W.layered_u3_pairing(n, 4, W.circuit_seed(7, seed), "cx_or_cz"))
+    q = [int(x) for x in rng.permutation(n)[:5]]
+    g.append(Gate("matrix", tuple(q), (), (), W.haar_unitary(rng, 32)))
+    for _ in range(3 * n):
+        a, b, c = (int(x) for x in rng.permutation(n)[:3])
+        g.append(W.cp(a, b, float(rng.uniform(0, 6))))
+        g.append(Gate("u3", (a,), (b, c), tuple(float(x) for x in rng.uniform(0, 6, 3))))
+    return g
+
+
+@pytest.mark.parametrize("n,gates", [
+    (28, W.layered_u3_pairing(28, 20, W.circuit_seed(2, 1), "cx_or_cz")),
+    (33, W.rcs_circuit(33, W.circuit_seed(6, 1))),
+    (33, W.qpe_circuit(32, 0x5A5A5A5A)),
+    (33, W.tfim_trotter(3, 11, 10, 0.1, 1.0, 1.0, "cx")),
+    (30, W.u3_su4_layers(30, 40, W.circuit_seed(5, 1))),
+    (20, wide_and_controlled(20, 3)),
+    (10, wide_and_controlled(10, 4)),
+], ids=["layered28", "rcs33", "qpe33", "tfim33", "su4_30", "wide20", "small10"])
+def test_pass_plan_covers_every_gate_once(n, gates):
+    for dtype in (B.SV_C64, B.SV_C128):
+        for pq in (4, 6, 8):
+            info = B.sv_pass_plan_info(n, dtype, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, pq))
+            assert info["gates"] == len(gates), (dtype, pq, info)
+            assert info["kernel_passes"] <= info["passes"]
+            assert info["variant_blocks"] + info["term_blocks"] <= info["blocks"]
+
+
+def test_pass_plan_structure_on_the_paper_workloads():
+    c64 = B.SV_C64
+    layered = B.sv_pass_plan_info(28, c64, W.layered_u3_pairing(28, 20, W.circuit_seed(2, 1), "cx_or_cz"))
+    assert layered["passes"] <= 31 and layered["sweeps"] == 0
+    # phase estimation: controlled-phase ladders across the tile boundary
+    # (greedy 5-qubit fusion needs 121 sweeps, tile qubits alone 61 passes)
+    qpe = B.sv_pass_plan_info(33, c64, W.qpe_circuit(32, 0x5A5A5A5A))
+    assert qpe["passes"] <= 13 and qpe["term_blocks"] > 0
+    # CX RZ CX bonds fuse into diagonal phase gates: the same plan as the
+    # diagonal-matrix form of the bonds
+    cx = B.sv_pass_plan_info(33, c64, W.tfim_trotter(3, 11, 10, 0.1, 1.0, 1.0, "cx"))
+    dg = B.sv_pass_plan_info(33, c64, W.tfim_trotter(3, 11, 10, 0.1, 1.0, 1.0, "diag"))
+    assert {k: v for k, v in cx.items() if k != "gates"} == {k: v for k, v in dg.items() if k != "gates"}
+    assert cx["passes"] <= 60
+    # dense SU(4) and U3 gates have no diagonal or controlled form
+    su4 = B.sv_pass_plan_info(30, c64, W.u3_su4_layers(30, 40, W.circuit_seed(5, 1)))
+    assert su4["variant_blocks"] == 0 and su4["term_blocks"] == 0
+    # below the pass tile every pass falls back to fused sweeps
+    small = B.sv_pass_plan_info(10, c64, wide_and_controlled(10, 4))
+    assert small["kernel_passes"] == 0 and small["sweeps"] > 0
+
+
+def test_pass_plan_info_rejects_bad_input():
+    g = [Gate("h", (0,))]
+    for opts in (B.make_opts(B.SV_PLAN_GREEDY, 5), B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 3),
+                 B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 9), B.make_opts(B.SV_PLAN_PASSES, 0)):
+        with pytest.raises(B.SvError):
+            B.sv_pass_plan_info(12, B.SV_C64, g, opts)
+    with pytest.raises(B.SvError):
+        B.sv_pass_plan_info(12, B.SV_C64, [Gate("h", (12,))])
+    with pytest.raises(B.SvError):
+        B.sv_pass_plan_info(0, B.SV_C64, g)
