@@ -86,6 +86,14 @@ __device__ __forceinline__ uint32_t swz(uint32_t x)
     return x ^ ((x >> 6) & 63u);
 }
 
+// The same without touching bit 0 (bits 7..11 into bits 1..5): an amplitude
+// pair (2m, 2m + 1) stays adjacent and in order, so a tile sweep moves it as
+// one 16-byte LDS access.  Also linear over XOR and its own inverse.
+__device__ __forceinline__ uint32_t swz_p(uint32_t x)
+{
+    return x ^ ((x >> 6) & 62u);
+}
+
 // Geometry of one LDS tile: the amplitudes spanned by the k target bits and
 // the m lowest free bits, for one value of all other bits.  Tile-local index
 // x lists the tile bits in ascending physical order.
@@ -215,12 +223,14 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v)
 // compiler hoist the per-tile constants into registers.  PAIR (complex64
 // with physical bit 0 inside the tile) moves amplitude pairs as 16-byte
 // accesses.  NTH is the workgroup size (256 or 512 threads); REMAT
-// recomputes the store addresses after compute() instead of keeping them.
+// recomputes the store addresses after compute() instead of keeping them;
+// PSWZ lays the tile out with swz_p (pairs as 16-byte LDS accesses; the
+// tile must then be 16-byte aligned and compute() must use swz_p).
 //
 // compute(tile) starts after a barrier that follows the tile's LDS writes; it
 // must leave its results in the same LDS slots and end with __syncthreads().
 // ---------------------------------------------------------------------------
-template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, bool REMAT = false, typename F>
+template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, bool REMAT = false, bool PSWZ = false, typename F>
 __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a, typename CT<R>::C *tile,
                                            F &&compute)
 {
@@ -260,8 +270,12 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
 #pragma unroll
             for (int s = 0; s < OPT / 2; ++s) {
                 const uint32_t x = 2u * uint32_t(s * NTH + tid);
-                tile[swz(x)] = make_float2(q[s].x, q[s].y);
-                tile[swz(x + 1)] = make_float2(q[s].z, q[s].w);
+                if constexpr (PSWZ) {
+                    *reinterpret_cast<float4 *>(&tile[swz_p(x)]) = q[s];
+                } else {
+                    tile[swz(x)] = make_float2(q[s].x, q[s].y);
+                    tile[swz(x + 1)] = make_float2(q[s].z, q[s].w);
+                }
             }
         } else {
             const C *v = reinterpret_cast<const C *>(st);
@@ -277,7 +291,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
                 C q;
                 q.x = qr[s];
                 q.y = qi[s];
-                tile[swz(uint32_t(s * NTH + tid))] = q;
+                tile[PSWZ ? swz_p(uint32_t(s * NTH + tid)) : swz(uint32_t(s * NTH + tid))] = q;
             }
         }
         __syncthreads();
@@ -307,14 +321,19 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
 #pragma unroll
             for (int s = 0; s < OPT / 2; ++s) {
                 const uint32_t x = 2u * uint32_t(s * NTH + tid2);
-                const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
-                st_nt(&v4[(base + offset2(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
+                if constexpr (PSWZ) {
+                    st_nt(&v4[(base + offset2(s)) >> 1], *reinterpret_cast<const float4 *>(&tile[swz_p(x)]));
+                } else {
+                    const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
+                    st_nt(&v4[(base + offset2(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
+                }
             }
         } else {
             C *v = reinterpret_cast<C *>(st);
 #pragma unroll
             for (int s = 0; s < OPT; ++s)
-                st_nt(&v[base + offset2(s)], tile[swz(uint32_t(s * NTH + tid2))]);
+                st_nt(&v[base + offset2(s)],
+                      tile[PSWZ ? swz_p(uint32_t(s * NTH + tid2)) : swz(uint32_t(s * NTH + tid2))]);
         }
     }
 }

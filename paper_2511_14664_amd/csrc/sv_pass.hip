@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
     constexpr bool F64 = std::is_same<R, double>::value;
     static_assert(NGS % NW == 0 && PER_WAVE >= 1, "tile shape");
 
-    __shared__ C tile[1 << TA_LOG];
+    __shared__ __align__(16) C tile[1 << TA_LOG];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
         }
     };
 
-    tile_sweep<R, TA_LOG, PAIR, NTH, true>(st, a, tile, [&](C *t) {
+    tile_sweep<R, TA_LOG, PAIR, NTH, true, true>(st, a, tile, [&](C *t) {
         // phases of block sb + 1 are folded in at the end of iteration sb,
         // where no accumulator is live
         apply_phases(subs[0]);
@@ -232,11 +232,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
             // byte offsets into the tile (the XOR parts scale with it)
             constexpr int SH = F64 ? 4 : 3;
             const uint32_t gl = deposit(uint32_t(bj));
-            const uint32_t in_lane = swz(xb_lane | gl) << SH, out_lane = swz(xo_lane | gl) << SH;
+            const uint32_t in_lane = swz_p(xb_lane | gl) << SH, out_lane = swz_p(xo_lane | gl) << SH;
             uint32_t hj[PER_WAVE];
 #pragma unroll
             for (int j = 0; j < PER_WAVE; ++j)
-                hj[j] = swz(deposit(uint32_t(wave + NW * j) * NT)) << SH;
+                hj[j] = swz_p(deposit(uint32_t(wave + NW * j) * NT)) << SH;
             char *tb = reinterpret_cast<char *>(t);
             AccT p1[PER_WAVE], p2[PER_WAVE], p3[PER_WAVE];
 #pragma unroll
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const uint32_t ss = swz(d.xc[s * KT]) << SH;
+                const uint32_t ss = swz_p(d.xc[s * KT]) << SH;
                 const R us = ur[s] + ui[s];
 #pragma unroll
                 for (int j = 0; j < PER_WAVE; ++j) {
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 // accumulator row: 4 (lane / 16) + r (FP32), 4 r + lane / 16 (FP64)
-                const uint32_t rr = swz(d.xc[F64 ? 4 * r : r]) << SH;
+                const uint32_t rr = swz_p(d.xc[F64 ? 4 * r : r]) << SH;
 #pragma unroll
                 for (int j = 0; j < PER_WAVE; ++j) {
                     C y;
