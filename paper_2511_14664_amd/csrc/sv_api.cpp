@@ -599,6 +599,7 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
         std::vector<const Block *> mem;
         std::vector<double> alpha;
         uint64_t moff = mats;
+        uint32_t pslot = 0;
         std::vector<Block> restricted;
         for (size_t i = 0; i < nsub; ++i) {
             const uint64_t vq = w.vq[i];
@@ -741,6 +742,13 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
                     }
                 }
             d.nterm = uint32_t(nt - first);
+            if (d.nterm > 0) {
+                if (pslot >= uint32_t(kMaxTermBlocks)) {
+                    set_error("pass %zu: more than %d blocks with phase terms", index, kMaxTermBlocks);
+                    return SV_EINVAL;
+                }
+                d.pslot = pslot++;
+            }
             desc[i] = d;
             // U (x) I on the padding slots: row/column bits >= b.k must agree
             for (uint32_t var = 0; var < (1u << nv); ++var) {

@@ -176,8 +176,13 @@ struct PassSub {
     uint32_t nterm;       // number of phase terms (0: the matrix alone)
     uint32_t nvar;        // matrix variants 2^nvar, selected by the tile's index bits vpos[0..nvar)
     uint8_t vpos[8];
-    uint64_t pad[2];
+    uint32_t pslot;       // with nterm > 0: this block's row of the per-tile angle table (< kMaxTermBlocks)
+    uint32_t pad0b;
+    uint64_t pad;
 };
+// Blocks carrying phase terms per pass (rows of the kernel's per-tile angle
+// table in LDS); a pass with more runs as ordinary sweeps.
+constexpr int kMaxTermBlocks = 16;
 static_assert(sizeof(PassSub) == 128, "pass block descriptor layout");
 // One monomial of a per-tile phase: where the tile's outer index bits cover
 // omask (physical bits), entry (r, c) of the block matrix gains the angle

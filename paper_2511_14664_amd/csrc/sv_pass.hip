@@ -103,7 +103,7 @@ __device__ __forceinline__ void turn_sincos(uint64_t u, double &sn, double &cs)
 }
 
 template <typename R, int TA_LOG, bool PAIR, int NTH, bool PHASES>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThreads && std::is_same<R, float>::value && PAIR ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThreads && std::is_same<R, float>::value && PAIR && !PHASES ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
                                                    const PassSub *__restrict__ subs, int nsub,
                                                    const char *__restrict__ mats)
 {
@@ -145,21 +145,25 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
     R ur[NS], ui[NS];
     load_u(0, ur, ui);  // in flight with the tile's loads
 
-    auto apply_phases = [&](const PassSub &d) {
-        if (PHASES && d.nterm > 0) {
-            // Phase gates reaching outside the tile: on this tile they are
-            // diagonal phases on the block's slots, folded into U as
-            // U[r][c] * exp(i (front(c) + back(r))).  Angles are summed in
-            // fixed-point turns (exact, wrapping mod 2 pi): 32 bits for
-            // complex64, 64 for complex128.
-            using TurnT = typename std::conditional<F64, uint64_t, uint32_t>::type;
+    // Per-tile phase angles of the blocks carrying phase terms, in an LDS
+    // table: row pslot holds the 16 column angles (front terms) and the 16
+    // row angles (back terms) of that block on this tile, in fixed-point
+    // turns (exact sums wrapping mod 2 pi: 32 bits for complex64, 64 for
+    // complex128).  Wave w fills the rows of term blocks w, w + NW, ...: lane
+    // m < 16 sums the front monomials with slot mask m whose outer bits this
+    // tile has, lane 16 + m the back ones; a subset sum over the four mask
+    // bits across lanes then gives angle(c) = sum of the monomials m within c.
+    using TurnT = typename std::conditional<F64, uint64_t, uint32_t>::type;
+    __shared__ TurnT angles[PHASES ? kMaxTermBlocks * 32 : 1];
+    auto fill_angles = [&]() {
+        for (int sb = 0; sb < nsub; ++sb) {
+            const PassSub &d = subs[sb];
+            if (d.nterm == 0 || int(d.pslot % NW) != wave)
+                continue;
             const PassTerm *tm = reinterpret_cast<const PassTerm *>(mats + d.t_off);
-            TurnT turn[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-                turn[s] = 0;
-            // terms in groups of four, loads first (the scalar loads of a
-            // group are in flight together)
+            const uint32_t my_mask = uint32_t(lane & 15), my_back = uint32_t(lane >> 4);
+            TurnT acc = 0;
+            // terms in groups of four, loads first (in flight together)
             constexpr uint32_t G = 4;
             for (uint32_t e0 = 0; e0 < d.nterm; e0 += G) {
                 uint64_t om[G], tq[G];
@@ -176,24 +180,30 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
                 for (uint32_t j = 0; j < G; ++j) {
                     if (e0 + j >= d.nterm || (tbase & om[j]) != om[j])
                         continue;
-                    const TurnT tu = TurnT(F64 ? tq[j] : (tq[j] >> 32));
-                    if (bk[j]) {
-                        if ((uint32_t(ai) & sm[j]) == sm[j])
-#pragma unroll
-                            for (int s = 0; s < NS; ++s)
-                                turn[s] += tu;
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < NS; ++s)
-                            if ((uint32_t(s * KT + akk) & sm[j]) == sm[j])
-                                turn[s] += tu;
-                    }
+                    if (sm[j] == my_mask && bk[j] == my_back)
+                        acc += TurnT(F64 ? tq[j] : (tq[j] >> 32));
                 }
             }
 #pragma unroll
+            for (int bit = 1; bit < 16; bit <<= 1) {
+                const TurnT other = __shfl_xor(acc, bit);
+                if (lane & bit)
+                    acc += other;
+            }
+            if (lane < 32)
+                angles[d.pslot * 32 + uint32_t(lane)] = acc;
+        }
+    };
+    // U[r][c] * exp(i (front(c) + back(r))) for this lane's fragment of a
+    // block carrying phase terms (table filled for this tile)
+    auto apply_phases = [&](const PassSub &d) {
+        if (PHASES && d.nterm > 0) {
+            const TurnT *row = angles + d.pslot * 32;
+            const TurnT tb = row[16 + ai];
+#pragma unroll
             for (int s = 0; s < NS; ++s) {
                 R sn, cs;
-                turn_sincos(turn[s], sn, cs);
+                turn_sincos(TurnT(row[s * KT + akk] + tb), sn, cs);
                 const R r0 = ur[s], i0 = ui[s];
                 ur[s] = r0 * cs - i0 * sn;
                 ui[s] = r0 * sn + i0 * cs;
@@ -202,6 +212,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThr
     };
 
     tile_sweep<R, TA_LOG, PAIR, NTH, true, true>(st, a, tile, [&](C *t) {
+        if (PHASES) {
+            fill_angles();
+            __syncthreads();
+        }
         // phases of block sb + 1 are folded in at the end of iteration sb,
         // where no accumulator is live
         apply_phases(subs[0]);

@@ -734,9 +734,14 @@ static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pas
         w.kernel = n >= T0 && q >= 1 && q <= kMaxPassQubits && n - o >= T0;
         if (w.kernel) {
             pass_subblocks(gates, pg[i].members, w.qmask, w);
-            for (const Group &g : w.subs)
-                if (__builtin_popcountll(g.qmask) > 4)
+            int term_blocks = 0;
+            for (size_t j = 0; j < w.subs.size(); ++j) {
+                if (__builtin_popcountll(w.subs[j].qmask) > 4)
                     w.kernel = false;
+                term_blocks += !w.front[j].empty() || !w.back[j].empty();
+            }
+            if (term_blocks > kMaxTermBlocks)
+                w.kernel = false;
         }
         if (!w.kernel) {
             // ordinary sweeps over the pass's gates (all qubits count)
