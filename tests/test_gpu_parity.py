@@ -567,6 +567,34 @@ def test_pass_plan_outer_controls_match_oracle(dtype, n):
             assert st["gates"] == len(gates)
 
 
+def term_heavy_circuit(n, reps, seed):
+    """H on qubits 0..7, then controlled phases from each of them to six
+    random qubits above, repeated: blocks whose phase gates reach many qubits
+    outside the tile (per-tile phase terms), split where an H follows."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(reps):
+        for q in range(8):
+            gates.append(Gate("h", (q,)))
+        for q in range(8):
+            for o in rng.permutation(np.arange(8, n))[:6]:
+                gates.append(W.cp(q, int(o), float(rng.uniform(-3, 3))))
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pass_plan_term_heavy_matches_oracle(dtype):
+    n = 20
+    gates = term_heavy_circuit(n, 12, 5)
+    info = B.sv_pass_plan_info(n, dtype, gates)
+    assert info["term_blocks"] >= 20 and info["gates"] == len(gates)
+    want = oracle.run(gates, n)
+    say(f"term-heavy passes n={n} {DNAME[dtype]}: {info}")
+    with State(n, dtype) as s:
+        B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES))
+        assert maxerr(s.host(), want) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_pass_plan_phase_gates_after_relayout(dtype):
     n = 18
