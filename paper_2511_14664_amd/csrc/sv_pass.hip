@@ -6,11 +6,11 @@
 // the lowest free index bits (2^12 complex64 or 2^11 complex128 amplitudes on
 // 256 threads, so that contiguous runs stay at least 128 bytes; twice that on
 // 512 threads for passes of at most two (complex64) or three (complex128)
-// blocks, which are bound by HBM).  Every block is applied
-// to the tile in LDS before the tile goes back to HBM: the state moves once
-// per pass instead of once per block, which is the same product of unitaries
-// in the same order (paper Sec. 2.1: gate application as sweeps over the
-// amplitudes; Sec. 2.2: gate fusion to cut the number of sweeps).
+// blocks, which are bound by HBM).  Every block is applied to the tile in LDS
+// before the tile goes back to HBM: the state moves once per pass instead of
+// once per block, which is the same product of unitaries in the same order
+// (paper Sec. 2.1: gate application as sweeps over the amplitudes; Sec. 2.2:
+// gate fusion to cut the number of sweeps).
 //
 // Each block is a dense 16 x 16 unitary on four tile slots (smaller blocks
 // are padded with identity on other tile slots by the host).  It runs as the
@@ -22,13 +22,15 @@
 // are read with scalar loads; the U fragment of the next block is fetched
 // while the current one is multiplied.
 //
-// Diagonal gates may also act on qubits outside the tile.  Those index bits
-// are constant within a tile, so on each tile such a gate is a diagonal
-// phase on the block's slots.  A block whose gates reach few outer qubits is
-// stored as one fused matrix per value of those bits and the tile picks its
-// variant; otherwise the phases are folded into the block's matrix as a
-// column phase (applied before the block) or a row phase (after it), from a
-// list of monomials (outer-bit mask, slot mask, angle) per block.
+// Gates may also reach qubits outside the tile: diagonal gates with any of
+// their qubits, other gates with their controls.  Those index bits are
+// constant within a tile, so on each tile such a gate is a diagonal phase on
+// the block's slots, or the gate itself or the identity.  A block whose gates
+// reach at most four outer qubits is stored as one fused matrix per value of
+// those bits and the tile picks its variant; otherwise (phase gates only) the
+// phases are folded into the block's matrix as a column phase (applied before
+// the block) or a row phase (after it), from a list of monomials (outer-bit
+// mask, slot mask, angle) per block evaluated once per tile into LDS.
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -102,10 +104,15 @@ __device__ __forceinline__ void turn_sincos(uint64_t u, double &sn, double &cs)
         cs = -cs;
 }
 
+// Residency target: five workgroups per CU fill the LDS with 32 KiB tiles,
+// so the complex64 256-thread kernel without phase terms is held to 96
+// registers (which also keeps the matrix products in VGPR form, without
+// accumulator copies); the others stay at four.
 template <typename R, int TA_LOG, bool PAIR, int NTH, bool PHASES>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == kThreads && std::is_same<R, float>::value && PAIR && !PHASES ? 5 : 4))) void k_pass(R *__restrict__ st, const TileArgs a,
-                                                   const PassSub *__restrict__ subs, int nsub,
-                                                   const char *__restrict__ mats)
+__global__ __launch_bounds__(NTH)
+__attribute__((amdgpu_waves_per_eu(NTH == kThreads && std::is_same<R, float>::value && PAIR && !PHASES ? 5 : 4)))
+void k_pass(R *__restrict__ st, const TileArgs a, const PassSub *__restrict__ subs, int nsub,
+            const char *__restrict__ mats)
 {
     using C = typename CT<R>::C;
     using AccT = typename PassAcc<R>::T;
