@@ -137,10 +137,11 @@ def main():
     for r in recs:
         # every pass moves the whole state whatever its width: one class
         key = (r["kind_name"], None if r["kind_name"] == "pass" else r["k"])
-        c = classes.setdefault(key, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0})
+        c = classes.setdefault(key, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "mfma_flops": 0.0, "launches": 0})
         c["ms"] += r["ms"]
         c["bytes"] += r["bytes"]
         c["flops"] += r["flops"]
+        c["mfma_flops"] += r["mfma_flops"]
         c["launches"] += 1
     sweep_ms = sum(c["ms"] for c in classes.values()) / args.steps
     sweep_bytes = sum(c["bytes"] for c in classes.values()) / args.steps
@@ -156,17 +157,19 @@ def main():
                  for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms"])}
 
     traffic = counter_traffic(dom_key, n, dtype, args)
-    # A pass launch also runs its blocks on the matrix cores: the record's
-    # flops count 126 per amplitude per 16 x 16 complex block; the kernel
-    # executes three real 16 x 16 products (96 flops per amplitude).
+    # A pass launch also runs its blocks on the matrix cores: a d x d complex
+    # block costs 8 d - 2 algorithmic flops per amplitude and three real
+    # d x d products (6 d flops per amplitude) on the matrix cores, so the
+    # two totals also give the number of blocks.
     mfma_side = {}
     if dom_key[0] == "pass" and args.precision == "native":
         mpeak = 157.3e12 if dtype == B.SV_C64 else 78.6e12
-        mflops = dom["flops"] / dom["launches"] * 96.0 / 126.0
+        mflops = dom["mfma_flops"] / dom["launches"]
+        blocks = (dom["mfma_flops"] * 8.0 / 6.0 - dom["flops"]) / (2.0 * 2.0 ** n) / dom["launches"]
         mfma_side = {"mfma_flops_per_launch": mflops,
                      "mfma_frac": round(mflops / (avg_ms / 1e3) / mpeak, 4),
                      "mfma_peak_TFLOP/s": mpeak / 1e12,
-                     "blocks_per_launch": round(dom["flops"] / dom["launches"] / (126.0 * 2.0 ** n), 2)}
+                     "blocks_per_launch": round(blocks, 2)}
     plain = None
     if not args.no_plain and args.mode != "plain":
         popts = B.make_opts(B.SV_PLAN_PLAIN)

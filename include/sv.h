@@ -236,9 +236,10 @@ typedef struct sv_sweep_record {
     int32_t highest_target;  /* highest target bit (hi for SV_SWEEP_BITSWAP) */
     int32_t num_gates;       /* input gates applied by this sweep */
     double bytes;            /* algorithmic HBM bytes */
-    double flops;
+    double flops;            /* algorithmic: 8 d - 2 per amplitude per dense d x d complex block */
     float ms;                /* HIP-event duration on the handle's stream */
     int32_t reserved;
+    double mfma_flops;       /* real flops a pass executes on the matrix cores (0: other sweeps) */
 } sv_sweep_record;
 
 /* enable != 0: bracket every subsequent sweep of this handle with a pair of

@@ -309,7 +309,7 @@ class sv_sweep_record(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("c", ctypes.c_int32),
                 ("lowest_target", ctypes.c_int32), ("highest_target", ctypes.c_int32),
                 ("num_gates", ctypes.c_int32), ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32), ("mfma_flops", ctypes.c_double)]
 
 
 SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap",

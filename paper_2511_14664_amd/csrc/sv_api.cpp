@@ -774,7 +774,11 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     pr.rec.highest_target = hi;
     pr.rec.num_gates = w.ngates;
     pr.rec.bytes = 2.0 * double(h->bytes);
+    // every block a dense 16 x 16 complex matrix: 8 * 16 - 2 flops per
+    // amplitude; on the matrix cores three real products of 2 * 16 flops
+    // per amplitude each
     pr.rec.flops = double(nsub) * (8.0 * 16.0 - 2.0) * std::ldexp(1.0, h->n);
+    pr.rec.mfma_flops = double(nsub) * 6.0 * 16.0 * std::ldexp(1.0, h->n);
     int rc = prof_begin(h, pr);
     if (rc != SV_OK)
         return rc;

@@ -596,6 +596,54 @@ def test_pass_plan_term_heavy_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("kmax", [2, 3, 5])
+@pytest.mark.parametrize("n", [14, 20])
+def test_pass_plan_small_blocks_match_oracle(dtype, kmax, n):
+    """Pass blocks of at most kmax qubits (padded with identity to 16 x 16 on
+    other tile slots).  The profile records count 126 algorithmic and 96
+    matrix-core flops per amplitude per block."""
+    gates = pass_circuit(n, 60 + n)
+    want = oracle.run(gates, n)
+    say(f"small-block passes n={n} {DNAME[dtype]} max_fused={kmax}")
+    with State(n, dtype) as s:
+        B.sv_profile_read(s.h)
+        B.sv_profile_enable(s.h, True)
+        B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, kmax, B.SV_PREC_NATIVE, 8))
+        recs = [r for r in B.sv_profile_read(s.h) if r["kind_name"] == "pass"]
+        assert maxerr(s.host(), want) <= TOL[dtype]
+    assert recs
+    amps = 2.0 ** n
+    for r in recs:
+        blocks = r["flops"] / (126 * amps)
+        assert blocks >= 1 and blocks == int(blocks) and r["mfma_flops"] == 96 * amps * blocks
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("kind", ["layered", "controls", "phases"])
+@pytest.mark.parametrize("n", [23, 24])
+def test_pass_plan_large_states_match_oracle(dtype, kind, n):
+    """States of 2^11 .. 2^13 pass tiles (more tiles than resident
+    workgroups), with passes of three or more blocks, blocks with matrix
+    variants and blocks with phase terms."""
+    if kind == "layered":
+        gates = W.layered_u3_pairing(n, 8, W.circuit_seed(2, n), "cx_or_cz")
+    elif kind == "controls":
+        gates = control_circuit(n, 70 + n)
+    else:
+        gates = phase_circuit(n, 80 + n, 3)
+    want = oracle.run(gates, n)
+    say(f"large-state passes n={n} {DNAME[dtype]} {kind}")
+    with State(n, dtype) as s:
+        B.sv_profile_read(s.h)
+        B.sv_profile_enable(s.h, True)
+        B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES))
+        recs = [r for r in B.sv_profile_read(s.h) if r["kind_name"] == "pass"]
+        assert maxerr(s.host(), want) <= TOL[dtype]
+    blocks = [round(r["flops"] / (126 * 2.0 ** n)) for r in recs]
+    assert any(3 <= b <= 8 for b in blocks), blocks
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_pass_plan_phase_gates_after_relayout(dtype):
     n = 18
     a = phase_circuit(n, 3, 2)
