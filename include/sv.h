@@ -119,6 +119,10 @@ typedef struct sv_plan_opts {
     int32_t max_fused;    /* 1..6: widest fused block (greedy / learned; passes' fallback) */
     int32_t precision;    /* sv_precision */
     int32_t pass_qubits;  /* SV_PLAN_PASSES: 4..8 qubits per pass, 0 for 8; else must be 0 */
+    int32_t pass_orders;  /* SV_PLAN_PASSES: seeded random gate orders (consistent with the circuit's
+                             dependencies) tried when splitting a pass into blocks, beside circuit order and
+                             its reverse; the split with the cheapest blocks is kept.  0: by state size (8 from
+                             30 qubits, else none), -1: none, 1..64; else must be 0 */
 } sv_plan_opts;
 
 /* Counters filled by sv_apply_circuit / sv_apply_plan (may be NULL). */

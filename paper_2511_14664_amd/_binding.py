@@ -45,7 +45,7 @@ class sv_gate(ctypes.Structure):
 
 class sv_plan_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_fused", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("pass_qubits", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("pass_qubits", ctypes.c_int32), ("pass_orders", ctypes.c_int32)]
 
 
 class sv_run_stats(ctypes.Structure):
@@ -145,8 +145,8 @@ class Circuit:
 
 
 def make_opts(mode: int = SV_PLAN_PLAIN, max_fused: int = 5, precision: int = SV_PREC_NATIVE,
-              pass_qubits: int = 0) -> sv_plan_opts:
-    return sv_plan_opts(mode, max_fused, precision, pass_qubits)
+              pass_qubits: int = 0, pass_orders: int = 0) -> sv_plan_opts:
+    return sv_plan_opts(mode, max_fused, precision, pass_qubits, pass_orders)
 
 
 def _as_circuit(gates) -> Circuit:

@@ -805,13 +805,13 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
 // Run a circuit as LDS passes (SV_PLAN_PASSES), fused, uploaded and launched
 // in chunks of 1, 2, 4, ... passes as in run_groups.
 int run_passes(sv_state *h, const std::vector<Block> &circuit, int pass_qubits, int max_fused, int precision,
-               int ngates, sv_run_stats *st)
+               int pass_orders, int ngates, sv_run_stats *st)
 {
     const std::vector<Block> gates = prefuse_diagonal_pairs(circuit);
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
     const std::vector<PassGroup> pg =
-        plan_passes(gates, pass_qubits, max_fused, h->n, pass_tile_log(h->dtype), h->qmap);
+        plan_passes(gates, pass_qubits, max_fused, h->n, pass_tile_log(h->dtype), h->qmap, pass_orders);
     std::vector<PassWork> work(pg.size());
     uint64_t total = 0;
     for (size_t i = 0; i < pg.size(); ++i) {
@@ -1172,6 +1172,7 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
     sv_plan_opts plain = o;
     plain.mode = SV_PLAN_PLAIN;
     plain.pass_qubits = 0;
+    plain.pass_orders = 0;
     std::vector<Block> gates_b;
     rc = plan_circuit(h->n, h->dtype, gates, ngates, plain, gates_b);
     if (rc != SV_OK)
@@ -1190,10 +1191,14 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
                   kMaxPassQubits);
         return SV_EINVAL;
     }
+    if (o.mode == SV_PLAN_PASSES ? (o.pass_orders < -1 || o.pass_orders > kMaxPassOrders) : o.pass_orders != 0) {
+        set_error("pass_orders %d: -1..%d with SV_PLAN_PASSES, else 0", o.pass_orders, kMaxPassOrders);
+        return SV_EINVAL;
+    }
     DeviceGuard dg(h->device);
     if (o.mode == SV_PLAN_PASSES)
-        return run_passes(h, gates_b, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, o.precision, ngates,
-                          stats);
+        return run_passes(h, gates_b, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, o.precision,
+                          o.pass_orders, ngates, stats);
     std::vector<Group> groups;
     if (o.mode == SV_PLAN_PLAIN) {
         groups.reserve(gates_b.size());
@@ -1206,7 +1211,7 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
             if (rc != SV_OK)
                 return rc;
             if (k == 0)  // the pass plan ranks first
-                return run_passes(h, gates_b, kMaxPassQubits, o.max_fused, o.precision, ngates, stats);
+                return run_passes(h, gates_b, kMaxPassQubits, o.max_fused, o.precision, 0, ngates, stats);
         }
         groups = group_greedy(gates_b, k);
     }
@@ -1613,16 +1618,22 @@ int sv_pass_plan_info(int n, int dtype, const sv_gate *gates, int ngates, const 
         set_error("pass_qubits %d: 4..%d (0 for %d)", o.pass_qubits, kMaxPassQubits, kMaxPassQubits);
         return SV_EINVAL;
     }
+    if (o.pass_orders < -1 || o.pass_orders > kMaxPassOrders) {
+        set_error("pass_orders %d: -1..%d", o.pass_orders, kMaxPassOrders);
+        return SV_EINVAL;
+    }
     sv_plan_opts plain = o;
     plain.mode = SV_PLAN_PLAIN;
     plain.pass_qubits = 0;
+    plain.pass_orders = 0;
     std::vector<Block> gates_b;
     rc = plan_circuit(n, dtype, gates, ngates, plain, gates_b);
     if (rc != SV_OK)
         return rc;
     const std::vector<Block> pg = prefuse_diagonal_pairs(gates_b);
     const std::vector<PassGroup> plan =
-        plan_passes(pg, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, n, pass_tile_log(dtype), nullptr);
+        plan_passes(pg, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, n, pass_tile_log(dtype), nullptr,
+                    o.pass_orders);
     int64_t r[8] = {};
     std::vector<char> seen(pg.size(), 0);
     bool twice = false;

@@ -657,7 +657,7 @@ int sv_costmodel_rank(sv_costmodel_handle m, int n, int dtype, const sv_gate *ga
     if (rc != SV_OK)
         return rc;
     std::vector<Block> blocks;
-    sv_plan_opts o{SV_PLAN_PLAIN, max_fused, SV_PREC_NATIVE, 0};
+    sv_plan_opts o{SV_PLAN_PLAIN, max_fused, SV_PREC_NATIVE, 0, 0};
     if ((rc = plan_circuit(n, dtype, gates, ngates, o, blocks)) != SV_OK)
         return rc;
     return rank_plans(m, n, dtype, blocks, max_fused, SV_PREC_NATIVE, *chosen, predicted_ms);

@@ -104,8 +104,11 @@ struct PassGroup {
 std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates);
 // phys: logical -> physical qubit map (nullptr: identity); T0: smallest pass
 // tile (log2 amplitudes) of the state's dtype.
+// orders: random gate orders tried per pass when splitting it into blocks
+// (0: by state size, -1: none).
+constexpr int kMaxPassOrders = 64;
 std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
-                                   const int *phys);
+                                   const int *phys, int orders = 0);
 // A controlled block as a dense unitary on targets + controls (controls
 // become the high bits of the index); uncontrolled blocks are returned as is.
 Block densify(const Block &b);

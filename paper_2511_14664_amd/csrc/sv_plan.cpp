@@ -432,13 +432,18 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
     std::fill(last, last + 64, -1);
     auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
     auto fits = [&](uint64_t bud, uint64_t dep) { return popc(bud) <= kmax && popc(dep & ~bud) <= omax; };
+    // set bits of a mask, lowest first
+    auto each_bit = [](uint64_t x, auto &&f) {
+        while (x) {
+            f(__builtin_ctzll(x));
+            x &= x - 1;
+        }
+    };
     for (int i = 0; i < int(depm.size()); ++i) {
         const uint64_t gm = depm[size_t(i)];
         uint64_t gb = budm[size_t(i)];
         int cand = -1;
-        for (int q = 0; q < 64; ++q)
-            if ((gm >> q) & 1)
-                cand = std::max(cand, last[q]);
+        each_bit(gm, [&](int q) { cand = std::max(cand, last[q]); });
         int target = -1;
         if (cand >= 0) {
             if (fits(pb[cand].qmask | gb, pb[cand].dep | gm)) {
@@ -455,18 +460,14 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
             target = int(pb.size()) - 1;
         }
         if (fits(gb, gm)) {
-            for (int q = 0; q < 64; ++q) {
-                if (!((gm >> q) & 1))
-                    continue;
+            each_bit(gm, [&](int q) {
                 const int b = last[q];
                 if (b < 0 || b == target || !pb[b].alive)
-                    continue;
+                    return;
                 bool movable = true;
-                for (int r = 0; r < 64 && movable; ++r)
-                    if (((pb[b].dep >> r) & 1) && last[r] != b)
-                        movable = false;
+                each_bit(pb[b].dep, [&](int r) { movable = movable && last[r] == b; });
                 if (!movable || !fits(pb[target].qmask | pb[b].qmask | gb, pb[target].dep | pb[b].dep | gm))
-                    continue;
+                    return;
                 std::vector<int> merged = pb[b].members;
                 merged.insert(merged.end(), pb[target].members.begin(), pb[target].members.end());
                 pb[target].members.swap(merged);
@@ -474,17 +475,13 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
                 pb[target].dep |= pb[b].dep;
                 pb[b].alive = false;
                 pb[b].members.clear();
-                for (int r = 0; r < 64; ++r)
-                    if ((pb[b].dep >> r) & 1)
-                        last[r] = target;
-            }
+                each_bit(pb[b].dep, [&](int r) { last[r] = target; });
+            });
         }
         pb[target].members.push_back(i);
         pb[target].qmask |= gb;
         pb[target].dep |= gm;
-        for (int q = 0; q < 64; ++q)
-            if ((gm >> q) & 1)
-                last[q] = target;
+        each_bit(gm, [&](int q) { last[q] = target; });
     }
     std::vector<Group> out;
     std::vector<uint64_t> dep;
@@ -544,18 +541,84 @@ static uint64_t nondiag_mask(const Block &b)
 // applied before the block's matrix (front: it commutes with every member
 // before it) or after it (back: it commutes with every member after it), and
 // the block is split where neither holds.
-static void pass_subblocks(const std::vector<Block> &gates, const std::vector<int> &members, uint64_t tmask,
-                           PassGroup &w)
+// Candidate partitions of one pass's gates (items with qubit masks dep and
+// budget masks bud, in circuit order) into blocks of <= 4 tile qubits: the
+// greedy packing over several gate orders.  Items touching a common qubit
+// keep their relative order in every order tried, so each partition is the
+// circuit's product: the order given, its reverse (the blocks of a partition
+// valid for the reversed list, taken in reverse with their members in
+// reverse, are a valid partition of the list), and `trials` seeded random
+// orders consistent with the dependencies.  A block lists its items
+// in an order consistent with the dependencies (not necessarily ascending).
+static std::vector<std::vector<Group>> pass_partitions(const std::vector<uint64_t> &dep,
+                                                       const std::vector<uint64_t> &bud, int trials)
 {
-    std::vector<uint64_t> depm(members.size()), budm(members.size());
-    std::vector<char> phase(members.size(), 0);
-    for (size_t i = 0; i < members.size(); ++i) {
-        const Block &g = gates[size_t(members[i])];
-        const uint64_t qm = qubit_mask(g);
-        phase[i] = (qm & ~tmask) != 0;  // phase gates, or controls, outside the tile
-        depm[i] = budm[i] = qm & tmask;
+    const int m = int(dep.size());
+    std::vector<std::vector<Group>> out;
+    out.push_back(greedy_masks(dep, bud, nullptr, 4, 64, nullptr));
+    auto add = [&](const std::vector<int> &order, bool reversed) {
+        std::vector<uint64_t> d(static_cast<size_t>(m)), b(static_cast<size_t>(m));
+        for (int i = 0; i < m; ++i) {
+            d[size_t(i)] = dep[size_t(order[size_t(i)])];
+            b[size_t(i)] = bud[size_t(order[size_t(i)])];
+        }
+        std::vector<Group> g = greedy_masks(d, b, nullptr, 4, 64, nullptr);
+        for (Group &x : g)
+            for (int &i : x.members)
+                i = order[size_t(i)];
+        if (reversed) {
+            std::reverse(g.begin(), g.end());
+            for (Group &x : g)
+                std::reverse(x.members.begin(), x.members.end());
+        }
+        out.push_back(std::move(g));
+    };
+    std::vector<int> order(static_cast<size_t>(m));
+    for (int i = 0; i < m; ++i)
+        order[size_t(i)] = m - 1 - i;
+    add(order, true);
+    // random linear extensions: repeatedly take a random item whose
+    // predecessors (earlier items sharing a qubit) are all taken
+    uint64_t rng = 0x9E3779B97F4A7C15ull ^ uint64_t(m);
+    std::vector<int> npred(static_cast<size_t>(m));
+    std::vector<int> ready;
+    for (int trial = 0; trial < trials; ++trial) {
+        for (int i = 0; i < m; ++i) {
+            int c = 0;
+            for (int j = 0; j < i; ++j)
+                if (dep[size_t(j)] & dep[size_t(i)])
+                    ++c;
+            npred[size_t(i)] = c;
+        }
+        ready.clear();
+        for (int i = 0; i < m; ++i)
+            if (npred[size_t(i)] == 0)
+                ready.push_back(i);
+        order.clear();
+        while (!ready.empty()) {
+            rng ^= rng << 13;
+            rng ^= rng >> 7;
+            rng ^= rng << 17;
+            const size_t pick = size_t(rng % ready.size());
+            const int i = ready[pick];
+            ready[pick] = ready.back();
+            ready.pop_back();
+            order.push_back(i);
+            for (int j = i + 1; j < m; ++j)
+                if ((dep[size_t(i)] & dep[size_t(j)]) && --npred[size_t(j)] == 0)
+                    ready.push_back(j);
+        }
+        add(order, false);
     }
-    const std::vector<Group> sub = greedy_masks(depm, budm, nullptr, 4, 64, nullptr);
+    return out;
+}
+
+// The pass's blocks from one partition of its gates (sub: groups of
+// indices into members).
+static void pass_subblocks_from(const std::vector<Block> &gates, const std::vector<int> &members, uint64_t tmask,
+                                const std::vector<uint64_t> &depm, const std::vector<char> &phase,
+                                const std::vector<Group> &sub, PassGroup &w)
+{
     w.subs.clear();
     w.front.clear();
     w.back.clear();
@@ -651,6 +714,42 @@ static void pass_subblocks(const std::vector<Block> &gates, const std::vector<in
     }
 }
 
+// A pass's blocks: of the candidate partitions of its gates, the one whose
+// blocks cost least in the pass model (0.22 per block, 0.31 per block with
+// phase terms); the first candidate (circuit order) wins ties.
+static void pass_subblocks(const std::vector<Block> &gates, const std::vector<int> &members, uint64_t tmask,
+                           int trials, PassGroup &w)
+{
+    std::vector<uint64_t> depm(members.size());
+    std::vector<char> phase(members.size(), 0);
+    for (size_t i = 0; i < members.size(); ++i) {
+        const uint64_t qm = qubit_mask(gates[size_t(members[i])]);
+        phase[i] = (qm & ~tmask) != 0;  // phase gates, or controls, outside the tile
+        depm[i] = qm & tmask;
+    }
+    auto cost = [](const PassGroup &p) {
+        double c = 0;
+        for (size_t i = 0; i < p.subs.size(); ++i)
+            c += (p.front[i].empty() && p.back[i].empty()) ? 0.22 : 0.31;
+        return c;
+    };
+    double best = 0;
+    bool have = false;
+    PassGroup tmp;
+    for (const std::vector<Group> &sub : pass_partitions(depm, depm, trials)) {
+        pass_subblocks_from(gates, members, tmask, depm, phase, sub, tmp);
+        const double c = cost(tmp);
+        if (!have || c < best - 1e-9) {
+            best = c;
+            have = true;
+            w.subs.swap(tmp.subs);
+            w.front.swap(tmp.front);
+            w.back.swap(tmp.back);
+            w.vq.swap(tmp.vq);
+        }
+    }
+}
+
 std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates)
 {
     const size_t N = gates.size();
@@ -702,7 +801,7 @@ std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates)
 // qubits); 1 = all their qubits when that fits, else only those at low
 // physical positions; 2 = only those at low physical positions.
 static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n,
-                                        int T0, const int *phys, int phases)
+                                        int T0, const int *phys, int phases, int trials)
 {
     std::vector<uint64_t> depm(gates.size()), minm(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) {
@@ -733,7 +832,7 @@ static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pas
         const int q = __builtin_popcountll(w.qmask), o = __builtin_popcountll(w.omask);
         w.kernel = n >= T0 && q >= 1 && q <= kMaxPassQubits && n - o >= T0;
         if (w.kernel) {
-            pass_subblocks(gates, pg[i].members, w.qmask, w);
+            pass_subblocks(gates, pg[i].members, w.qmask, trials, w);
             int term_blocks = 0;
             for (size_t j = 0; j < w.subs.size(); ++j) {
                 if (__builtin_popcountll(w.subs[j].qmask) > 4)
@@ -786,20 +885,34 @@ static double pass_plan_cost(const std::vector<PassGroup> &plan)
 }
 
 std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
-                                   const int *phys)
+                                   const int *phys, int orders)
 {
-    std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0);
+    // Three candidate plans, each pass's gates partitioned in circuit order
+    // and in reverse; the cheapest is then re-partitioned over random gate
+    // orders as well.  By default only when the state is large enough for a
+    // block (~0.8 ms at 30 qubits) to outweigh the host time of the search.
+    constexpr int kSearchQubits = 30, kDefaultOrders = 8;
+    const int trials = orders > 0 ? std::min(orders, kMaxPassOrders)
+                                  : (orders == 0 && n >= kSearchQubits ? kDefaultOrders : 0);
+    std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0, 0);
     double cbest = pass_plan_cost(best);
+    int pbest = 0;
     bool any_phase = false;
     for (const Block &g : gates)
         any_phase = any_phase || outer_capable(g) != 0;
     for (int ph = 1; ph <= 2 && any_phase; ++ph) {
-        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph);
+        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph, 0);
         const double c = pass_plan_cost(p);
         if (c < cbest) {
             best.swap(p);
             cbest = c;
+            pbest = ph;
         }
+    }
+    if (trials > 0) {
+        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, pbest, trials);
+        if (pass_plan_cost(p) < cbest)
+            best.swap(p);
     }
     return best;
 }
@@ -832,8 +945,8 @@ int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_pl
         set_error("unknown plan mode %d", o.mode);
         return SV_EINVAL;
     }
-    if (o.pass_qubits != 0) {
-        set_error("pass_qubits must be 0 outside SV_PLAN_PASSES");
+    if (o.pass_qubits != 0 || o.pass_orders != 0) {
+        set_error("pass_qubits and pass_orders must be 0 outside SV_PLAN_PASSES");
         return SV_EINVAL;
     }
     if (o.mode != SV_PLAN_PLAIN && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {

@@ -203,6 +203,41 @@ def test_pass_plan_structure_on_the_paper_workloads():
     assert small["kernel_passes"] == 0 and small["sweeps"] > 0
 
 
+@pytest.mark.parametrize("n,gates", [
+    (28, W.layered_u3_pairing(28, 20, W.circuit_seed(2, 1), "cx_or_cz")),
+    (33, W.rcs_circuit(33, W.circuit_seed(6, 1))),
+    (33, W.qpe_circuit(32, 0x5A5A5A5A)),
+    (20, wide_and_controlled(20, 3)),
+], ids=["layered28", "rcs33", "qpe33", "wide20"])
+def test_pass_plan_gate_order_search(n, gates):
+    """Splitting each pass into blocks over random gate orders (pass_orders)
+    still covers every gate once, keeps the passes, and never raises the
+    blocks' cost in the pass model (0.22 per block, 0.31 with phase terms)
+    over circuit order and its reverse alone."""
+    def cost(i):
+        return 0.22 * (i["blocks"] - i["term_blocks"]) + 0.31 * i["term_blocks"]
+    base = B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, -1))
+    for orders in (0, 8, 32):
+        info = B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, orders))
+        assert info["gates"] == len(gates) and info["passes"] == base["passes"]
+        assert cost(info) <= cost(base) + 1e-9, (orders, info, base)
+        if orders == 0 and n < 30:
+            assert info == base  # no search below 30 qubits by default
+    # repeatable: the orders are seeded
+    a = B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 16))
+    assert a == B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 16))
+
+
+def test_pass_orders_option_bounds():
+    g = [Gate("h", (0,))]
+    for orders in (-2, 65):
+        with pytest.raises(B.SvError):
+            B.sv_pass_plan_info(20, B.SV_C64, g, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, orders))
+    with pytest.raises(B.SvError):
+        B.sv_plan_create(12, B.SV_C64, g, B.make_opts(B.SV_PLAN_GREEDY, 5, B.SV_PREC_NATIVE, 0, 4))
+    B.sv_pass_plan_info(20, B.SV_C64, g, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 64))
+
+
 def test_pass_plan_info_rejects_bad_input():
     g = [Gate("h", (0,))]
     for opts in (B.make_opts(B.SV_PLAN_GREEDY, 5), B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 3),

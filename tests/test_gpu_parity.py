@@ -644,6 +644,30 @@ def test_pass_plan_large_states_match_oracle(dtype, kind, n):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("kind", ["mixed", "phases", "controls", "terms"])
+@pytest.mark.parametrize("n", [14, 20])
+def test_pass_plan_gate_order_search_matches_oracle(dtype, kind, n):
+    """Passes split into blocks over random gate orders (pass_orders): a
+    block's gates run in an order consistent with the circuit's
+    dependencies, not in circuit order, with phase terms and matrix
+    variants folded in the same way."""
+    if kind == "mixed":
+        gates = pass_circuit(n, 90 + n)
+    elif kind == "phases":
+        gates = phase_circuit(n, 91 + n, 4)
+    elif kind == "controls":
+        gates = control_circuit(n, 92 + n, 4)
+    else:
+        gates = term_heavy_circuit(n, 6, 93 + n)
+    want = oracle.run(gates, n)
+    for orders in (-1, 32):
+        say(f"gate-order search n={n} {DNAME[dtype]} {kind} pass_orders={orders}")
+        with State(n, dtype) as s:
+            B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, orders))
+            assert maxerr(s.host(), want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_pass_plan_phase_gates_after_relayout(dtype):
     n = 18
     a = phase_circuit(n, 3, 2)
