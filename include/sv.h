@@ -121,8 +121,9 @@ typedef struct sv_plan_opts {
     int32_t pass_qubits;  /* SV_PLAN_PASSES: 4..8 qubits per pass, 0 for 8; else must be 0 */
     int32_t pass_orders;  /* SV_PLAN_PASSES: seeded random gate orders (consistent with the circuit's
                              dependencies) tried when splitting a pass into blocks, beside circuit order and
-                             its reverse; the split with the cheapest blocks is kept.  0: by state size (8 from
-                             30 qubits, else none), -1: none, 1..64; else must be 0 */
+                             its reverse, and for re-planning the whole circuit; the cheapest result in the
+                             pass cost model is kept.  0: by state size (8 from 32 qubits, else none), -1:
+                             none, 1..64; else must be 0 */
 } sv_plan_opts;
 
 /* Counters filled by sv_apply_circuit / sv_apply_plan (may be NULL). */
@@ -378,7 +379,9 @@ int sv_plan_destroy(sv_plan_handle p);
  * those passes; blocks staged as per-tile matrix variants; blocks carrying
  * per-tile phase terms; ordinary sweeps (passes that fall back to fused
  * sweeps); input gates the plan applies (each input gate exactly once, so
- * this equals ngates); 0.  SV_EINVAL for invalid gates or options. */
+ * this equals ngates); the plan's model time (the planner's objective, in
+ * thousandths of one HBM round trip of the state).  SV_EINVAL for invalid
+ * gates or options. */
 int sv_pass_plan_info(int n, int dtype, const sv_gate *gates, int ngates, const sv_plan_opts *opts, int64_t *out);
 
 #ifdef __cplusplus

@@ -268,7 +268,7 @@ def sv_pass_plan_info(n: int, dtype: int, gates, opts: Optional[sv_plan_opts] = 
     o = opts if opts is not None else make_opts(SV_PLAN_PASSES)
     _check(_lib.sv_pass_plan_info(n, dtype, circ.array, circ.n_gates, ctypes.byref(o), out.ctypes.data),
            "sv_pass_plan_info")
-    keys = ("passes", "kernel_passes", "blocks", "variant_blocks", "term_blocks", "sweeps", "gates")
+    keys = ("passes", "kernel_passes", "blocks", "variant_blocks", "term_blocks", "sweeps", "gates", "cost_milli")
     return {k: int(v) for k, v in zip(keys, out)}
 
 

@@ -1664,6 +1664,7 @@ int sv_pass_plan_info(int n, int dtype, const sv_gate *gates, int ngates, const 
     }
     if (twice)
         r[6] = -1;  // a gate placed twice: reported as an impossible count
+    r[7] = int64_t(std::llround(pass_plan_cost(plan) * 1000.0));
     std::copy(r, r + 8, out);
     return SV_OK;
 }

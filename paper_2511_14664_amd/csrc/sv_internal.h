@@ -104,11 +104,14 @@ struct PassGroup {
 std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates);
 // phys: logical -> physical qubit map (nullptr: identity); T0: smallest pass
 // tile (log2 amplitudes) of the state's dtype.
-// orders: random gate orders tried per pass when splitting it into blocks
-// (0: by state size, -1: none).
+// orders: random gate orders tried (0: by state size, -1: none), both for
+// splitting each pass into blocks and for re-planning the whole circuit.
 constexpr int kMaxPassOrders = 64;
 std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
                                    const int *phys, int orders = 0);
+// Model time of a pass plan in HBM round trips of the state (the planner's
+// objective).
+double pass_plan_cost(const std::vector<PassGroup> &plan);
 // A controlled block as a dense unitary on targets + controls (controls
 // become the high bits of the index); uncontrolled blocks are returned as is.
 Block densify(const Block &b);

@@ -868,7 +868,7 @@ static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pas
 // MI355X, the same in both precisions to within a few percent); a block
 // carrying per-tile phase terms costs 0.31 instead of 0.22 (measured); a
 // sweep costs 1.
-static double pass_plan_cost(const std::vector<PassGroup> &plan)
+double pass_plan_cost(const std::vector<PassGroup> &plan)
 {
     double c = 0.0;
     for (const PassGroup &w : plan) {
@@ -889,9 +889,11 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
 {
     // Three candidate plans, each pass's gates partitioned in circuit order
     // and in reverse; the cheapest is then re-partitioned over random gate
-    // orders as well.  By default only when the state is large enough for a
-    // block (~0.8 ms at 30 qubits) to outweigh the host time of the search.
-    constexpr int kSearchQubits = 30, kDefaultOrders = 8;
+    // orders as well, and re-planned over random orders of the whole
+    // circuit.  By default only when the state is large enough for a pass
+    // (~13 ms at 32 qubits) to outweigh the host time of the search (tens of
+    // ms on a few thousand gates).
+    constexpr int kSearchQubits = 32, kDefaultOrders = 8;
     const int trials = orders > 0 ? std::min(orders, kMaxPassOrders)
                                   : (orders == 0 && n >= kSearchQubits ? kDefaultOrders : 0);
     std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0, 0);
@@ -911,8 +913,80 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
     }
     if (trials > 0) {
         std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, pbest, trials);
-        if (pass_plan_cost(p) < cbest)
+        const double c = pass_plan_cost(p);
+        if (c < cbest) {
             best.swap(p);
+            cbest = c;
+        }
+        // The same plan over seeded random gate orders of the whole circuit
+        // (gates sharing a qubit keep their order; the others commute): the
+        // pass grouping sees other gates side by side.
+        const size_t m = gates.size();
+        std::vector<int> succ_head(m, -1), succ_next, succ_to, npred(m), order, ready;
+        {
+            int last[64];
+            std::fill(last, last + 64, -1);
+            for (size_t i = 0; i < m; ++i) {
+                uint64_t x = qubit_mask(gates[i]);
+                int preds[64], np = 0;
+                while (x) {
+                    const int q = __builtin_ctzll(x);
+                    x &= x - 1;
+                    if (last[q] >= 0 && std::find(preds, preds + np, last[q]) == preds + np)
+                        preds[np++] = last[q];
+                    last[q] = int(i);
+                }
+                for (int k = 0; k < np; ++k) {
+                    succ_next.push_back(succ_head[size_t(preds[k])]);
+                    succ_to.push_back(int(i));
+                    succ_head[size_t(preds[k])] = int(succ_to.size()) - 1;
+                }
+            }
+        }
+        uint64_t rng = 0xD1B54A32D192ED03ull ^ uint64_t(m);
+        std::vector<Block> pg(m);
+        for (int trial = 0; trial < trials; ++trial) {
+            std::fill(npred.begin(), npred.end(), 0);
+            for (int to : succ_to)
+                ++npred[size_t(to)];
+            ready.clear();
+            for (size_t i = 0; i < m; ++i)
+                if (npred[i] == 0)
+                    ready.push_back(int(i));
+            order.clear();
+            while (!ready.empty()) {
+                rng ^= rng << 13;
+                rng ^= rng >> 7;
+                rng ^= rng << 17;
+                const size_t pick = size_t(rng % ready.size());
+                const int i = ready[pick];
+                ready[pick] = ready.back();
+                ready.pop_back();
+                order.push_back(i);
+                for (int e = succ_head[size_t(i)]; e >= 0; e = succ_next[size_t(e)])
+                    if (--npred[size_t(succ_to[size_t(e)])] == 0)
+                        ready.push_back(succ_to[size_t(e)]);
+            }
+            for (size_t i = 0; i < m; ++i)
+                pg[i] = gates[size_t(order[i])];
+            std::vector<PassGroup> q = pass_plan(pg, pass_qubits, max_fused, n, T0, phys, pbest, trials);
+            const double cq = pass_plan_cost(q);
+            if (cq < cbest) {
+                for (PassGroup &w : q) {
+                    for (Group &g : w.subs)
+                        for (int &x : g.members)
+                            x = order[size_t(x)];
+                    for (auto &f : w.front)
+                        for (int &x : f)
+                            x = order[size_t(x)];
+                    for (auto &b : w.back)
+                        for (int &x : b)
+                            x = order[size_t(x)];
+                }
+                best.swap(q);
+                cbest = cq;
+            }
+        }
     }
     return best;
 }

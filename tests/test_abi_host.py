@@ -210,22 +210,21 @@ def test_pass_plan_structure_on_the_paper_workloads():
     (20, wide_and_controlled(20, 3)),
 ], ids=["layered28", "rcs33", "qpe33", "wide20"])
 def test_pass_plan_gate_order_search(n, gates):
-    """Splitting each pass into blocks over random gate orders (pass_orders)
-    still covers every gate once, keeps the passes, and never raises the
-    blocks' cost in the pass model (0.22 per block, 0.31 with phase terms)
-    over circuit order and its reverse alone."""
-    def cost(i):
-        return 0.22 * (i["blocks"] - i["term_blocks"]) + 0.31 * i["term_blocks"]
-    base = B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, -1))
+    """Planning over random gate orders (pass_orders: each pass split into
+    blocks, and the whole circuit re-planned) still covers every gate once
+    and never raises the plan's model time over circuit order and its
+    reverse alone; the orders are seeded, so plans repeat."""
+    def info(orders):
+        return B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, orders))
+    base = info(-1)
+    assert base["cost_milli"] >= 1000 * base["passes"] // 2
     for orders in (0, 8, 32):
-        info = B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, orders))
-        assert info["gates"] == len(gates) and info["passes"] == base["passes"]
-        assert cost(info) <= cost(base) + 1e-9, (orders, info, base)
-        if orders == 0 and n < 30:
-            assert info == base  # no search below 30 qubits by default
-    # repeatable: the orders are seeded
-    a = B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 16))
-    assert a == B.sv_pass_plan_info(n, B.SV_C64, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 16))
+        i = info(orders)
+        assert i["gates"] == len(gates)
+        assert i["cost_milli"] <= base["cost_milli"], (orders, i, base)
+        if orders == 0 and n < 32:
+            assert i == base  # no search below 32 qubits by default
+    assert info(16) == info(16)
 
 
 def test_pass_orders_option_bounds():
