@@ -28,10 +28,14 @@ def test_tiny_states_every_gate(dtype, n):
     for k in range(2, n + 1):
         gates.append(Gate("matrix", tuple(int(x) for x in rng.permutation(n)[:k]), (), (), W.haar_unitary(rng, 1 << k)))
     want = oracle.run(gates, n)
-    for mode in (B.SV_PLAN_PLAIN, B.SV_PLAN_GREEDY):
+    # pass plans below the pass tile fall back to fused sweeps (also with the
+    # gate-order search forced)
+    plans = [B.make_opts(B.SV_PLAN_PLAIN, min(6, n)), B.make_opts(B.SV_PLAN_GREEDY, min(6, n)),
+             B.make_opts(B.SV_PLAN_PASSES, min(6, n)), B.make_opts(B.SV_PLAN_PASSES, min(6, n), B.SV_PREC_NATIVE, 0, 8)]
+    for opts in plans:
         h = B.sv_create(n, dtype)
         try:
-            B.sv_apply_circuit(h, gates, B.make_opts(mode, min(6, n)))
+            B.sv_apply_circuit(h, gates, opts)
             got = B.sv_copy_to_host(h, n, dtype).astype(np.complex128)
             assert np.max(np.abs(got - want)) <= TOL[dtype]
             assert abs(B.sv_probabilities(h, [])[0] - 1) < 1e-5
