@@ -186,13 +186,17 @@ namespace {
 // Z-string expectations: sum_i |a_i|^2 (-1)^popcount(i & z_t), up to kMaxZ
 // strings per pass.  part[t * gridDim + block].
 //
-// Every index a thread visits is h + threadIdx.x with h a multiple of 256
-// that is the same across the workgroup, so the sign factors as
-// (-1)^popcount(h & z_t) * (-1)^popcount(threadIdx.x & z_t).  The first
-// factors of all strings form one wave-uniform word per h: lane t computes
-// the parity for string t and a ballot collects them.  The second factor is
-// applied once at the end.  Per amplitude and string the work is one FP64
-// FMA with a scalar +-1 operand.
+// A thread visits the indexes h0 + 256 u + threadIdx.x, u < 16, with h0 a
+// multiple of 4096 that is the same across the workgroup, so the sign
+// factors as (-1)^popcount(h0 & z_t) * (-1)^popcount(u & k_t) *
+// (-1)^popcount(threadIdx.x & z_t), k_t = bits 8 .. 11 of z_t.  The first
+// factors of all strings form one wave-uniform word per h0: lane t computes
+// the parity for string t and a ballot collects them.  The second is folded
+// into a Walsh transform of the thread's 16 probabilities over u, so each
+// string takes one coefficient, picked by its uniform k_t, per 16
+// amplitudes.  The third is applied once at the end.  Per 16 amplitudes
+// and string the work is one FP64 FMA with a scalar +-1 operand (the scalar
+// unit, shared by a CU's four SIMDs, otherwise bounds the sweep).
 // ---------------------------------------------------------------------------
 constexpr int kMaxZ = 32;
 struct ExpZArgs {
@@ -207,7 +211,8 @@ __global__ __launch_bounds__(kThreads) void k_expect_z(const R *__restrict__ st,
 {
     static_assert(NZ <= 64 && NZ <= kMaxZ, "one string per lane");
     using C = typename CT<R>::C;
-    constexpr int U = 4;  // independent loads in flight per thread
+    constexpr int LU = 4, U = 1 << LU;  // amplitudes per thread and step: index bits 8 .. 11
+    static_assert(kThreads == 256, "lane and wave bits 0 .. 7");
     __shared__ double sh[4];
     const C *v = reinterpret_cast<const C *>(st);
     const int lane = threadIdx.x & 63;
@@ -218,19 +223,37 @@ __global__ __launch_bounds__(kThreads) void k_expect_z(const R *__restrict__ st,
         acc[t] = 0.0;
     const uint64_t chunk = uint64_t(U) * kThreads;
     for (uint64_t h0 = uint64_t(blockIdx.x) * chunk; h0 < a.nelem; h0 += uint64_t(gridDim.x) * chunk) {
-        double p[U];
+        // every load in bounds (past the end: index 0, weight 0) and all of
+        // them issued before the first is used
+        C x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = h0 + uint64_t(u) * kThreads + threadIdx.x;
-            p[u] = i < a.nelem ? prob(v[i]) : 0.0;
+            x[u] = v[i < a.nelem ? i : 0];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        double w[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t h = h0 + uint64_t(u) * kThreads;  // workgroup-uniform
-            const uint64_t sgn = __ballot((__popcll(h & zl) & 1) != 0);
+        for (int u = 0; u < U; ++u)
+            w[u] = h0 + uint64_t(u) * kThreads + threadIdx.x < a.nelem ? prob(x[u]) : 0.0;
+        // Walsh transform over the step bits: w[k] = sum_u (-1)^popcount(u & k) p_u
 #pragma unroll
-            for (int t = 0; t < NZ; ++t)
-                acc[t] = fma(((sgn >> t) & 1) ? -1.0 : 1.0, p[u], acc[t]);
+        for (int b = 1; b < U; b <<= 1)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (!(u & b)) {
+                    const double x = w[u], y = w[u | b];
+                    w[u] = x + y;
+                    w[u | b] = x - y;
+                }
+        // h0 has bits 0 .. 11 clear: string t's sign is (-1)^popcount(h0 & z_t)
+        // (workgroup-uniform, one ballot) times coefficient k = bits 8 .. 11
+        // of z_t, times the lane part applied at the end
+        const uint64_t sgn = __ballot((__popcll(h0 & zl) & 1) != 0);
+#pragma unroll
+        for (int t = 0; t < NZ; ++t) {
+            const int k = int((a.z[t] >> 8) & (U - 1));
+            acc[t] = fma(((sgn >> t) & 1) ? -1.0 : 1.0, w[k], acc[t]);
         }
     }
 #pragma unroll
