@@ -122,7 +122,7 @@ typedef struct sv_plan_opts {
     int32_t pass_orders;  /* SV_PLAN_PASSES: seeded random gate orders (consistent with the circuit's
                              dependencies) tried when splitting a pass into blocks, beside circuit order and
                              its reverse, and for re-planning the whole circuit; the cheapest result in the
-                             pass cost model is kept.  0: by state size (8 from 32 qubits, else none), -1:
+                             pass cost model is kept.  0: by state size (16 from 32 qubits, else none), -1:
                              none, 1..64; else must be 0 */
 } sv_plan_opts;
 

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <future>
 
 #include "sv_internal.h"
 
@@ -893,17 +894,25 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
     // circuit.  By default only when the state is large enough for a pass
     // (~13 ms at 32 qubits) to outweigh the host time of the search (tens of
     // ms on a few thousand gates).
-    constexpr int kSearchQubits = 32, kDefaultOrders = 8;
+    constexpr int kSearchQubits = 32, kDefaultOrders = 16;
     const int trials = orders > 0 ? std::min(orders, kMaxPassOrders)
                                   : (orders == 0 && n >= kSearchQubits ? kDefaultOrders : 0);
-    std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0, 0);
-    double cbest = pass_plan_cost(best);
-    int pbest = 0;
     bool any_phase = false;
     for (const Block &g : gates)
         any_phase = any_phase || outer_capable(g) != 0;
+    // the candidates are independent: the two with outer qubits are planned
+    // on worker threads while this thread plans the first (they sit on the
+    // critical path of every circuit applied)
+    std::future<std::vector<PassGroup>> alt[2];
+    for (int ph = 1; ph <= 2 && any_phase; ++ph)
+        alt[ph - 1] = std::async(std::launch::async, [&, ph]() {
+            return pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph, 0);
+        });
+    std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0, 0);
+    double cbest = pass_plan_cost(best);
+    int pbest = 0;
     for (int ph = 1; ph <= 2 && any_phase; ++ph) {
-        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph, 0);
+        std::vector<PassGroup> p = alt[ph - 1].get();
         const double c = pass_plan_cost(p);
         if (c < cbest) {
             best.swap(p);
@@ -912,17 +921,13 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
         }
     }
     if (trials > 0) {
-        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, pbest, trials);
-        const double c = pass_plan_cost(p);
-        if (c < cbest) {
-            best.swap(p);
-            cbest = c;
-        }
         // The same plan over seeded random gate orders of the whole circuit
         // (gates sharing a qubit keep their order; the others commute): the
-        // pass grouping sees other gates side by side.
+        // pass grouping sees other gates side by side.  One task per order,
+        // each with its own seed, so the result does not depend on their
+        // timing; ties go to the earlier candidate.
         const size_t m = gates.size();
-        std::vector<int> succ_head(m, -1), succ_next, succ_to, npred(m), order, ready;
+        std::vector<int> succ_head(m, -1), succ_next, succ_to;
         {
             int last[64];
             std::fill(last, last + 64, -1);
@@ -943,17 +948,14 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
                 }
             }
         }
-        uint64_t rng = 0xD1B54A32D192ED03ull ^ uint64_t(m);
-        std::vector<Block> pg(m);
-        for (int trial = 0; trial < trials; ++trial) {
-            std::fill(npred.begin(), npred.end(), 0);
+        auto plan_order = [&](int trial) {
+            uint64_t rng = 0xD1B54A32D192ED03ull ^ (uint64_t(m) << 8) ^ uint64_t(trial + 1) * 0x9E3779B97F4A7C15ull;
+            std::vector<int> npred(m, 0), order, ready;
             for (int to : succ_to)
                 ++npred[size_t(to)];
-            ready.clear();
             for (size_t i = 0; i < m; ++i)
                 if (npred[i] == 0)
                     ready.push_back(int(i));
-            order.clear();
             while (!ready.empty()) {
                 rng ^= rng << 13;
                 rng ^= rng >> 7;
@@ -967,24 +969,40 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
                     if (--npred[size_t(succ_to[size_t(e)])] == 0)
                         ready.push_back(succ_to[size_t(e)]);
             }
+            std::vector<Block> pg(m);
             for (size_t i = 0; i < m; ++i)
                 pg[i] = gates[size_t(order[i])];
             std::vector<PassGroup> q = pass_plan(pg, pass_qubits, max_fused, n, T0, phys, pbest, trials);
-            const double cq = pass_plan_cost(q);
-            if (cq < cbest) {
-                for (PassGroup &w : q) {
-                    for (Group &g : w.subs)
-                        for (int &x : g.members)
-                            x = order[size_t(x)];
-                    for (auto &f : w.front)
-                        for (int &x : f)
-                            x = order[size_t(x)];
-                    for (auto &b : w.back)
-                        for (int &x : b)
-                            x = order[size_t(x)];
-                }
+            for (PassGroup &w : q) {
+                for (Group &g : w.subs)
+                    for (int &x : g.members)
+                        x = order[size_t(x)];
+                for (auto &f : w.front)
+                    for (int &x : f)
+                        x = order[size_t(x)];
+                for (auto &b : w.back)
+                    for (int &x : b)
+                        x = order[size_t(x)];
+            }
+            return q;
+        };
+        std::vector<std::future<std::vector<PassGroup>>> fut;
+        for (int trial = 0; trial < trials; ++trial)
+            fut.push_back(std::async(std::launch::async, plan_order, trial));
+        // meanwhile: the winner in circuit order, each pass split over random
+        // orders of its own gates
+        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, pbest, trials);
+        double c = pass_plan_cost(p);
+        if (c < cbest) {
+            best.swap(p);
+            cbest = c;
+        }
+        for (auto &f : fut) {
+            std::vector<PassGroup> q = f.get();
+            c = pass_plan_cost(q);
+            if (c < cbest) {
                 best.swap(q);
-                cbest = cq;
+                cbest = c;
             }
         }
     }
