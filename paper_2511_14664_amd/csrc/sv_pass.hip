@@ -104,6 +104,16 @@ __device__ __forceinline__ void turn_sincos(uint64_t u, double &sn, double &cs)
         cs = -cs;
 }
 
+// Integer add to an LDS word (wrapping).
+__device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v)
+{
+    atomicAdd(p, v);
+}
+__device__ __forceinline__ void lds_add(uint64_t *p, uint64_t v)
+{
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+}
+
 // Residency target: five workgroups per CU fill the LDS with 32 KiB tiles,
 // so the complex64 256-thread kernel without phase terms is held to 96
 // registers (which also keeps the matrix products in VGPR form, without
@@ -156,10 +166,12 @@ void k_pass(R *__restrict__ st, const TileArgs a, const PassSub *__restrict__ su
     // table: row pslot holds the 16 column angles (front terms) and the 16
     // row angles (back terms) of that block on this tile, in fixed-point
     // turns (exact sums wrapping mod 2 pi: 32 bits for complex64, 64 for
-    // complex128).  Wave w fills the rows of term blocks w, w + NW, ...: lane
-    // m < 16 sums the front monomials with slot mask m whose outer bits this
-    // tile has, lane 16 + m the back ones; a subset sum over the four mask
-    // bits across lanes then gives angle(c) = sum of the monomials m within c.
+    // complex128).  Wave w fills the rows of term blocks w, w + NW, ...: its
+    // lanes take the block's monomials e = lane, lane + 64, ... and each one
+    // whose outer bits this tile has adds its turn to the row's (side, slot
+    // mask) entry with an LDS atomic add (integer sums: the same in any
+    // order); a subset sum over the four mask bits across lanes then gives
+    // angle(c) = sum of the entries m within c.
     using TurnT = typename std::conditional<F64, uint64_t, uint32_t>::type;
     __shared__ TurnT angles[PHASES ? kMaxTermBlocks * 32 : 1];
     auto fill_angles = [&]() {
@@ -168,29 +180,16 @@ void k_pass(R *__restrict__ st, const TileArgs a, const PassSub *__restrict__ su
             if (d.nterm == 0 || int(d.pslot % NW) != wave)
                 continue;
             const PassTerm *tm = reinterpret_cast<const PassTerm *>(mats + d.t_off);
-            const uint32_t my_mask = uint32_t(lane & 15), my_back = uint32_t(lane >> 4);
-            TurnT acc = 0;
-            // terms in groups of four, loads first (in flight together)
-            constexpr uint32_t G = 4;
-            for (uint32_t e0 = 0; e0 < d.nterm; e0 += G) {
-                uint64_t om[G], tq[G];
-                uint32_t sm[G], bk[G];
-#pragma unroll
-                for (uint32_t j = 0; j < G; ++j) {
-                    const uint32_t e = e0 + j < d.nterm ? e0 + j : e0;
-                    om[j] = tm[e].omask;
-                    sm[j] = tm[e].smask;
-                    bk[j] = tm[e].back;
-                    tq[j] = tm[e].turn;
-                }
-#pragma unroll
-                for (uint32_t j = 0; j < G; ++j) {
-                    if (e0 + j >= d.nterm || (tbase & om[j]) != om[j])
-                        continue;
-                    if (sm[j] == my_mask && bk[j] == my_back)
-                        acc += TurnT(F64 ? tq[j] : (tq[j] >> 32));
-                }
+            TurnT *row = angles + d.pslot * 32;
+            if (lane < 32)
+                row[lane] = 0;
+            for (uint32_t e = uint32_t(lane); e < d.nterm; e += 64) {
+                const PassTerm t = tm[e];
+                if ((tbase & t.omask) == t.omask)
+                    lds_add(&row[t.back * 16 + t.smask], TurnT(F64 ? t.turn : (t.turn >> 32)));
             }
+            // this wave's LDS operations complete in order: the entries are final
+            TurnT acc = lane < 32 ? row[lane] : TurnT(0);
 #pragma unroll
             for (int bit = 1; bit < 16; bit <<= 1) {
                 const TurnT other = __shfl_xor(acc, bit);
@@ -198,7 +197,7 @@ void k_pass(R *__restrict__ st, const TileArgs a, const PassSub *__restrict__ su
                     acc += other;
             }
             if (lane < 32)
-                angles[d.pslot * 32 + uint32_t(lane)] = acc;
+                row[lane] = acc;
         }
     };
     // U[r][c] * exp(i (front(c) + back(r))) for this lane's fragment of a
