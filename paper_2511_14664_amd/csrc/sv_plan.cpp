@@ -423,12 +423,17 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
                                        const std::vector<uint64_t> *minm, int kmax, int omax,
                                        std::vector<uint64_t> *dep_out)
 {
+    // blocks as linked member lists (head, tail, next[]): moving a free
+    // block into another splices its list in front in constant time
     struct PB {
-        std::vector<int> members;
+        int head = -1, tail = -1, size = 0;
         uint64_t qmask = 0, dep = 0;
         bool alive = true;
     };
+    const int N = int(depm.size());
     std::vector<PB> pb;
+    pb.reserve(size_t(N));
+    std::vector<int> next(size_t(N), -1);
     int last[64];
     std::fill(last, last + 64, -1);
     auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
@@ -440,7 +445,7 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
             x &= x - 1;
         }
     };
-    for (int i = 0; i < int(depm.size()); ++i) {
+    for (int i = 0; i < N; ++i) {
         const uint64_t gm = depm[size_t(i)];
         uint64_t gb = budm[size_t(i)];
         int cand = -1;
@@ -469,27 +474,45 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
                 each_bit(pb[b].dep, [&](int r) { movable = movable && last[r] == b; });
                 if (!movable || !fits(pb[target].qmask | pb[b].qmask | gb, pb[target].dep | pb[b].dep | gm))
                     return;
-                std::vector<int> merged = pb[b].members;
-                merged.insert(merged.end(), pb[target].members.begin(), pb[target].members.end());
-                pb[target].members.swap(merged);
-                pb[target].qmask |= pb[b].qmask;
-                pb[target].dep |= pb[b].dep;
-                pb[b].alive = false;
-                pb[b].members.clear();
-                each_bit(pb[b].dep, [&](int r) { last[r] = target; });
+                // the members of b go before those of target
+                PB &t = pb[target], &f = pb[b];
+                if (f.head >= 0) {
+                    if (t.head >= 0)
+                        next[size_t(f.tail)] = t.head;
+                    else
+                        t.tail = f.tail;
+                    t.head = f.head;
+                    t.size += f.size;
+                }
+                t.qmask |= f.qmask;
+                t.dep |= f.dep;
+                f.alive = false;
+                f.head = f.tail = -1;
+                f.size = 0;
+                each_bit(f.dep, [&](int r) { last[r] = target; });
             });
         }
-        pb[target].members.push_back(i);
-        pb[target].qmask |= gb;
-        pb[target].dep |= gm;
+        PB &t = pb[target];
+        if (t.tail >= 0)
+            next[size_t(t.tail)] = i;
+        else
+            t.head = i;
+        t.tail = i;
+        ++t.size;
+        t.qmask |= gb;
+        t.dep |= gm;
         each_bit(gm, [&](int q) { last[q] = target; });
     }
     std::vector<Group> out;
     std::vector<uint64_t> dep;
     for (const PB &b : pb) {
-        if (!b.alive || b.members.empty())
+        if (!b.alive || b.size == 0)
             continue;
-        out.push_back(Group{b.members, b.qmask});
+        Group g{std::vector<int>(), b.qmask};
+        g.members.reserve(size_t(b.size));
+        for (int x = b.head; x >= 0; x = next[size_t(x)])
+            g.members.push_back(x);
+        out.push_back(std::move(g));
         dep.push_back(b.dep);
     }
     merge_groups(out, dep, kmax, omax);
@@ -580,6 +603,8 @@ static std::vector<std::vector<Group>> pass_partitions(const std::vector<uint64_
     add(order, true);
     // random linear extensions: repeatedly take a random item whose
     // predecessors (earlier items sharing a qubit) are all taken
+    if (trials <= 0)
+        return out;
     uint64_t rng = 0x9E3779B97F4A7C15ull ^ uint64_t(m);
     std::vector<int> npred(static_cast<size_t>(m));
     std::vector<int> ready;
@@ -633,9 +658,9 @@ static void pass_subblocks_from(const std::vector<Block> &gates, const std::vect
             std::vector<int> all;
             for (int i : sg.members)
                 all.push_back(members[size_t(i)]);
-            w.subs.push_back(Group{all, sg.qmask});
-            w.front.push_back({});
-            w.back.push_back({});
+            w.subs.push_back(Group{std::move(all), sg.qmask});
+            w.front.emplace_back();
+            w.back.emplace_back();
             w.vq.push_back(outer);
             continue;
         }
@@ -676,9 +701,9 @@ static void pass_subblocks_from(const std::vector<Block> &gates, const std::vect
         auto flush = [&]() {
             if (reg.empty() && fr.empty() && bk.empty())
                 return;
-            w.subs.push_back(Group{reg, qm});
-            w.front.push_back(fr);
-            w.back.push_back(bk);
+            w.subs.push_back(Group{std::move(reg), qm});
+            w.front.push_back(std::move(fr));
+            w.back.push_back(std::move(bk));
             w.vq.push_back(0);
             reg.clear();
             fr.clear();
@@ -755,39 +780,72 @@ std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates)
 {
     const size_t N = gates.size();
     std::vector<char> used(N, 0);
+    std::vector<uint64_t> qm(N);
+    for (size_t i = 0; i < N; ++i)
+        qm[i] = qubit_mask(gates[i]);
     std::vector<Block> out;
     out.reserve(N);
-    std::vector<const Block *> run;
+    std::vector<size_t> idx;
     for (size_t i = 0; i < N; ++i) {
         if (used[i])
             continue;
         const Block &g = gates[i];
-        const uint64_t pair = qubit_mask(g);
+        const uint64_t pair = qm[i];
         if (g.diag || __builtin_popcountll(pair) != 2) {
             out.push_back(g);
             continue;
         }
         // gates after i on the pair's qubits, up to the first that also
-        // touches another qubit; gates on other qubits commute past the run
-        run.assign(1, &g);
-        std::vector<size_t> idx;
+        // touches another qubit; gates on other qubits commute past the run.
+        // The run's 4x4 product grows one gate at a time (the same products
+        // in the same order as fusing the whole run afresh).
+        int pos[64], tpos[SV_MAX_TARGETS], cpos[SV_MAX_CONTROLS];
+        pos[__builtin_ctzll(pair)] = 0;
+        pos[63 - __builtin_clzll(pair)] = 1;
+        double Mr[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1}, Mi[16] = {};
+        auto mul = [&](const Block &x) {
+            for (int b = 0; b < x.k; ++b)
+                tpos[b] = pos[x.targets[b]];
+            for (int j = 0; j < x.c; ++j)
+                cpos[j] = pos[x.controls[j]];
+            left_multiply(Mr, Mi, 2, x, tpos, cpos);
+        };
+        mul(g);
+        idx.clear();
         bool fused = false;
-        for (size_t j = i + 1; j < N && run.size() < 16; ++j) {
+        for (size_t j = i + 1; j < N && idx.size() < 15; ++j) {
             if (used[j])
                 continue;
-            const uint64_t m = qubit_mask(gates[j]);
+            const uint64_t m = qm[j];
             if ((m & pair) == 0)
                 continue;
             if ((m & ~pair) != 0)
                 break;
-            run.push_back(&gates[j]);
             idx.push_back(j);
-            Block f = fuse(run, pair, true);
-            if (matrix_is_diagonal(f.U, 4)) {
+            mul(gates[j]);
+            bool diag = true;
+            for (int r = 0; r < 4 && diag; ++r)
+                for (int c = 0; c < 4; ++c)
+                    if (r != c && (Mr[r * 4 + c] != 0.0 || Mi[r * 4 + c] != 0.0)) {
+                        diag = false;
+                        break;
+                    }
+            if (diag) {
+                Block f;
+                f.k = 2;
+                f.c = 0;
+                f.targets[0] = __builtin_ctzll(pair);
+                f.targets[1] = 63 - __builtin_clzll(pair);
+                f.U.resize(16);
+                for (int e = 0; e < 16; ++e)
+                    f.U[size_t(e)] = cd(Mr[e], Mi[e]);
                 f.diag = true;
-                out.push_back(std::move(f));
-                for (size_t x : idx)
+                f.ngates = g.ngates;
+                for (size_t x : idx) {
+                    f.ngates += gates[x].ngates;
                     used[x] = 1;
+                }
+                out.push_back(std::move(f));
                 fused = true;
                 break;
             }
