@@ -470,6 +470,12 @@ __global__ __launch_bounds__(kThreads) void k_marg_doubles(const double *__restr
 // segment's non-bin bits.  The probabilities of a segment go to LDS; each
 // bin is summed by G consecutive lanes over interleaved rest indices and
 // combined by a fixed shuffle tree, so the order of every sum is fixed.
+// A thread's loads of one segment differ only in the index bits from kLow
+// up (c64: a 16-byte load holds two amplitudes, bits 0..8 come from the
+// lane; c128: bits 0..7).  When none of those bits is a bin bit (KSUM), each
+// thread sums its loads in registers first and the LDS array shrinks to the
+// 2^kLow low-bit entries (4 or 2 KiB instead of 32), which leaves room for
+// more resident workgroups to keep loads in flight.
 // ---------------------------------------------------------------------------
 constexpr int kSegLog = 12;
 struct FoldArgs {
@@ -478,6 +484,12 @@ struct FoldArgs {
     int lb;             // popcount(binmask)
     int F;              // log2 segments per workgroup
 };
+
+template <typename R>
+constexpr int fold_low_bits()
+{
+    return std::is_same<R, float>::value ? 9 : 8;
+}
 
 // x-th value (ascending) of the integers whose set bits lie in mask.
 __device__ __forceinline__ uint32_t deposit(uint32_t x, uint32_t mask)
@@ -489,16 +501,21 @@ __device__ __forceinline__ uint32_t deposit(uint32_t x, uint32_t mask)
     return r;
 }
 
-template <typename R>
+template <typename R, bool KSUM>
 __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st, double *__restrict__ red,
                                                         const FoldArgs a)
 {
     constexpr int SEG = 1 << kSegLog;
-    constexpr int MAXB = SEG / kThreads;  // bins per thread when every thread owns whole bins
-    __shared__ double pr[SEG];
+    constexpr int LOW = fold_low_bits<R>();
+    constexpr int PR = KSUM ? (1 << LOW) : SEG;  // LDS entries per segment
+    constexpr int MAXB = (PR + kThreads - 1) / kThreads;  // bins per thread when every thread owns whole bins
+    constexpr bool F32 = std::is_same<R, float>::value;
+    constexpr int NLD = F32 ? SEG / (2 * kThreads) : SEG / kThreads;  // loads per thread per segment
+    __shared__ double pr[PR];
     const int tid = threadIdx.x;
+    const uint32_t restmask = KSUM ? (a.restmask & uint32_t(PR - 1)) : a.restmask;
     const int B = 1 << a.lb;
-    const int E = SEG >> a.lb;  // segment indices per bin
+    const int E = PR >> a.lb;  // LDS entries per bin
     const int G = B >= kThreads ? 1 : min(64, kThreads / B);
     const int gi = tid % G;
     const int bin0 = tid / G;
@@ -508,31 +525,50 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
     for (int k = 0; k < MAXB; ++k)
         acc[k] = 0.0;
     // rest enumeration for the group mode: x_r = deposit(r, restmask), r = gi, gi + G, ...
-    const uint32_t x_first = deposit(uint32_t(gi), a.restmask);
-    const uint32_t x_step = deposit(uint32_t(G), a.restmask);
+    const uint32_t x_first = deposit(uint32_t(gi), restmask);
+    const uint32_t x_step = deposit(uint32_t(G), restmask);
     const uint32_t d_bin0 = deposit(uint32_t(bin0), a.binmask);
     for (uint32_t j = 0; j < (1u << a.F); ++j) {
         const uint64_t base = ((uint64_t(blockIdx.x) << a.F) | j) << kSegLog;
-        if constexpr (std::is_same<R, float>::value) {
+        if constexpr (F32) {
             const float4 *v4 = reinterpret_cast<const float4 *>(st) + (base >> 1);
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int k = 0; k < SEG / (2 * kThreads); ++k) {
+            for (int k = 0; k < NLD; ++k) {
                 const float4 q = v4[tid + k * kThreads];
-                const int e = 2 * (tid + k * kThreads);
-                pr[e] = double(q.x) * q.x + double(q.y) * q.y;
-                pr[e + 1] = double(q.z) * q.z + double(q.w) * q.w;
+                const double p0 = double(q.x) * q.x + double(q.y) * q.y;
+                const double p1 = double(q.z) * q.z + double(q.w) * q.w;
+                if constexpr (KSUM) {
+                    s0 += p0;
+                    s1 += p1;
+                } else {
+                    const int e = 2 * (tid + k * kThreads);
+                    pr[e] = p0;
+                    pr[e + 1] = p1;
+                }
+            }
+            if constexpr (KSUM) {
+                pr[2 * tid] = s0;
+                pr[2 * tid + 1] = s1;
             }
         } else {
             const double2 *v2 = reinterpret_cast<const double2 *>(st) + base;
+            double s0 = 0.0;
 #pragma unroll
-            for (int k = 0; k < SEG / kThreads; ++k) {
+            for (int k = 0; k < NLD; ++k) {
                 const double2 q = v2[tid + k * kThreads];
-                pr[tid + k * kThreads] = q.x * q.x + q.y * q.y;
+                const double p0 = q.x * q.x + q.y * q.y;
+                if constexpr (KSUM)
+                    s0 += p0;
+                else
+                    pr[tid + k * kThreads] = p0;
             }
+            if constexpr (KSUM)
+                pr[tid] = s0;
         }
         __syncthreads();
         if (owner_mode) {
-            // bins tid, tid + 256, ...; E <= 16 indices each, ascending
+            // bins tid, tid + 256, ...; E <= 16 entries each, ascending
 #pragma unroll
             for (int k = 0; k < MAXB; ++k) {
                 const int bin = tid + k * kThreads;
@@ -542,7 +578,7 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
                     uint32_t x = 0;
                     for (int r = 0; r < E; ++r) {
                         sacc += pr[db | x];
-                        x = ((x | ~a.restmask) + 1u) & a.restmask;
+                        x = ((x | ~restmask) + 1u) & restmask;
                     }
                     acc[k] += sacc;
                 }
@@ -552,7 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
             uint32_t x = x_first;
             for (int r = gi; r < E; r += G) {
                 sacc += pr[d_bin0 | x];
-                x = ((x | ~a.restmask) + x_step) & a.restmask;
+                x = ((x | ~restmask) + x_step) & restmask;
             }
             for (int off = 1; off < G; off <<= 1)
                 sacc += __shfl_xor(sacc, off, 64);
@@ -737,12 +773,21 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
     }
     if (route.kind == 2) {
         const uint64_t nblk = uint64_t(1) << (n - kSegLog - route.fold.F);
-        if (dtype == SV_C64)
-            hipLaunchKernelGGL(k_marg_fold<float>, dim3(uint32_t(nblk)), dim3(kThreads), 0, s, (const float *)st,
-                               d_scratch, route.fold);
-        else
-            hipLaunchKernelGGL(k_marg_fold<double>, dim3(uint32_t(nblk)), dim3(kThreads), 0, s, (const double *)st,
-                               d_scratch, route.fold);
+        if (dtype == SV_C64) {
+            if ((route.fold.binmask >> fold_low_bits<float>()) == 0)
+                hipLaunchKernelGGL((k_marg_fold<float, true>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
+                                   (const float *)st, d_scratch, route.fold);
+            else
+                hipLaunchKernelGGL((k_marg_fold<float, false>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
+                                   (const float *)st, d_scratch, route.fold);
+        } else {
+            if ((route.fold.binmask >> fold_low_bits<double>()) == 0)
+                hipLaunchKernelGGL((k_marg_fold<double, true>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
+                                   (const double *)st, d_scratch, route.fold);
+            else
+                hipLaunchKernelGGL((k_marg_fold<double, false>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
+                                   (const double *)st, d_scratch, route.fold);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
