@@ -359,6 +359,29 @@ def test_28q_sampled_amplitudes_product_circuit(dtype):
             assert abs(norm - 1) < (1e-12 if dtype == B.SV_C128 else 1e-5)
 
 
+def test_28q_marginal_low_bins_several_segments_per_workgroup():
+    """Nine bin bits 0..8 at 28 qubits (complex64): each thread sums its
+    loads over index bits 9..11 in registers, and the folded array would
+    exceed 2^24 doubles, so each workgroup folds two segments.  The state is
+    a product of two 14-qubit halves, so the marginals are the oracle's
+    14-qubit marginals (times a one-qubit marginal of the upper half)."""
+    n = 28
+    lo, hi, gates = split_layers(n, 20, 91)
+    a_lo = oracle.run(lo, 14)
+    a_hi = oracle.run(hi, 14)
+    with State(n, B.SV_C64) as s:
+        B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES))
+        assert list(B.sv_qubit_map(s.h, n))[:9] == list(range(9))
+        low = list(range(9))
+        say("28q marginal over bits 0..8")
+        got = B.sv_probabilities(s.h, low)
+        assert maxerr(got, oracle.probabilities(a_lo, low)) <= TOL[B.SV_C64]
+        say("28q marginal over bits 0..8 and 27")
+        got = B.sv_probabilities(s.h, low + [27])
+        want = np.outer(oracle.probabilities(a_hi, [13]), oracle.probabilities(a_lo, low)).reshape(-1)
+        assert maxerr(got, want) <= TOL[B.SV_C64]
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_28q_layered_mirror_returns_to_zero(dtype):
     n = 28
