@@ -470,11 +470,12 @@ __global__ __launch_bounds__(kThreads) void k_marg_doubles(const double *__restr
 // segment's non-bin bits.  The probabilities of a segment go to LDS; each
 // bin is summed by G consecutive lanes over interleaved rest indices and
 // combined by a fixed shuffle tree, so the order of every sum is fixed.
-// A thread's loads of one segment differ only in the index bits from kLow
-// up (c64: a 16-byte load holds two amplitudes, bits 0..8 come from the
-// lane; c128: bits 0..7).  When none of those bits is a bin bit (KSUM), each
+// A thread's loads of one segment differ only in the index bits from
+// fold_low_bits() up: 9..11 for c64 (a 16-byte load holds the two amplitudes
+// of bit 0, the lane gives bits 1..8), 8..11 for c128 (the lane gives bits
+// 0..7).  When none of those bits is a bin bit (KSUM), each
 // thread sums its loads in registers first and the LDS array shrinks to the
-// 2^kLow low-bit entries (4 or 2 KiB instead of 32), which leaves room for
+// 2^fold_low_bits() low-bit entries (4 or 2 KiB instead of 32), which leaves room for
 // more resident workgroups to keep loads in flight.
 // ---------------------------------------------------------------------------
 constexpr int kSegLog = 12;
