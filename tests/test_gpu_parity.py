@@ -349,7 +349,7 @@ def test_28q_sampled_amplitudes_product_circuit(dtype):
     idx = rng.integers(0, 1 << n, size=4096)
     idx[:4] = [0, 1, (1 << n) - 1, 1 << 27]
     want = a_lo[idx & ((1 << 14) - 1)] * a_hi[idx >> 14]
-    for mode in (B.SV_PLAN_GREEDY, B.SV_PLAN_PLAIN):
+    for mode in (B.SV_PLAN_PASSES, B.SV_PLAN_GREEDY, B.SV_PLAN_PLAIN):
         say(f"28q product {DNAME[dtype]} mode={mode}")
         with State(n, dtype) as s:
             B.sv_apply_circuit(s.h, gates, B.make_opts(mode, 5))
@@ -386,15 +386,16 @@ def test_28q_marginal_low_bins_several_segments_per_workgroup():
 def test_28q_layered_mirror_returns_to_zero(dtype):
     n = 28
     gates = W.layered_u3_pairing(n, 20, W.circuit_seed(2, 1), "cx_or_cz")
-    say(f"28q mirror {DNAME[dtype]}")
-    with State(n, dtype) as s:
-        B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_GREEDY, 5))
-        B.sv_apply_circuit(s.h, W.inverse(gates), B.make_opts(B.SV_PLAN_GREEDY, 5))
-        a0 = complex(B.sv_copy_to_host(s.h, n, dtype, 0, 1)[0])
-        p = B.sv_probabilities(s.h, [0, 27, 13])
-        tol = TOL[dtype] * 10
-        assert abs(a0 - 1) <= tol, a0
-        assert abs(p[0] - 1) <= tol and np.all(np.abs(p[1:]) <= tol)
+    for mode in (B.SV_PLAN_PASSES, B.SV_PLAN_GREEDY):
+        say(f"28q mirror {DNAME[dtype]} mode={mode}")
+        with State(n, dtype) as s:
+            B.sv_apply_circuit(s.h, gates, B.make_opts(mode, 5))
+            B.sv_apply_circuit(s.h, W.inverse(gates), B.make_opts(mode, 5))
+            a0 = complex(B.sv_copy_to_host(s.h, n, dtype, 0, 1)[0])
+            p = B.sv_probabilities(s.h, [0, 27, 13])
+            tol = TOL[dtype] * 10
+            assert abs(a0 - 1) <= tol, a0
+            assert abs(p[0] - 1) <= tol and np.all(np.abs(p[1:]) <= tol)
 
 
 # ---------------------------------------------------------------------------
