@@ -357,6 +357,36 @@ def test_28q_sampled_amplitudes_product_circuit(dtype):
             assert maxerr(got, want[:512]) <= TOL[dtype]
             norm = B.sv_probabilities(s.h, [])[0]
             assert abs(norm - 1) < (1e-12 if dtype == B.SV_C128 else 1e-5)
+            if mode == B.SV_PLAN_PASSES:
+                check_product_readouts(s.h, dtype, a_lo, a_hi)
+
+
+def check_product_readouts(h, dtype, a_lo, a_hi):
+    """The benchmark's read-outs on a product of two 14-qubit states: Z-string
+    expectations factor into the halves' expectations, and each shot must fall
+    in its cumulative-probability interval, which also factors."""
+    zs = W.hea_z_terms(28)
+    terms = zs[:32] + [zs[28 + 13]]  # the benchmark's 32 strings and Z13 Z14 across the halves
+    got = B.sv_expect_pauli(h, terms)
+    want = np.array([oracle.expect_pauli(a_lo, t[:14]).real * oracle.expect_pauli(a_hi, t[14:]).real
+                     for t in terms])
+    assert maxerr(got, want) <= TOL[dtype]
+    u = W.uniforms(7, 1000)
+    shots = B.sv_sample(h, u)
+    p_lo, p_hi = np.abs(a_lo) ** 2, np.abs(a_hi) ** 2
+    c_lo, c_hi = np.cumsum(p_lo), np.cumsum(p_hi)
+    norm = c_lo[-1] * c_hi[-1]
+
+    def cdf(x):  # probability of the indices <= x
+        hi, lo = x >> 14, x & 0x3FFF
+        return (c_hi[hi - 1] * c_lo[-1] if hi > 0 else 0.0) + p_hi[hi] * c_lo[lo]
+
+    tau = 1e-10 if dtype == B.SV_C128 else 1e-4
+    for s, (x, g) in enumerate(zip(u, shots)):
+        g = int(g)
+        below = cdf(g - 1) if g > 0 else 0.0
+        assert below - tau <= x * norm < cdf(g) + tau, (s, g)
+        assert p_hi[g >> 14] * p_lo[g & 0x3FFF] > 0, (s, g)
 
 
 def test_28q_marginal_low_bins_several_segments_per_workgroup():
