@@ -359,6 +359,15 @@ def test_28q_sampled_amplitudes_product_circuit(dtype):
             assert abs(norm - 1) < (1e-12 if dtype == B.SV_C128 else 1e-5)
             if mode == B.SV_PLAN_PASSES:
                 check_product_readouts(s.h, dtype, a_lo, a_hi)
+                # the benchmark's 6-bit exchange (physical bits 0..5 <-> 22..27)
+                # moves amplitudes without arithmetic and updates the qubit
+                # map: the logical amplitudes read back are bit-identical
+                before = np.array([B.sv_copy_to_host(s.h, n, dtype, int(i), 1)[0] for i in idx[:256]])
+                B.sv_swap_bits(s.h, 0, n - 6, 6)
+                qmap = list(B.sv_qubit_map(s.h, n))
+                assert qmap[:6] == list(range(22, 28)) and qmap[22:] == list(range(6))
+                after = np.array([B.sv_copy_to_host(s.h, n, dtype, int(i), 1)[0] for i in idx[:256]])
+                assert np.array_equal(before.view(np.uint8), after.view(np.uint8))
 
 
 def check_product_readouts(h, dtype, a_lo, a_hi):
