@@ -336,11 +336,15 @@ int pass_tile_log_for(int n, int dtype, int nsub)
 {
     // Passes with few blocks are bound by HBM, and twice the tile (512
     // threads, 64 KiB of LDS) doubles the contiguous runs of a pass whose
-    // qubits are all high (128 -> 256 bytes); with more blocks the matrix
-    // cores bind and the smaller tile, with more workgroups per CU, overlaps
-    // better.  Small states keep the small tile (enough tiles to spread).
+    // qubits are all high; with more blocks the matrix cores bind and the
+    // smaller tile, with more workgroups per CU, overlaps better.  Complex128
+    // takes the larger tile up to three blocks.  Complex64 keeps the 2^12
+    // tile throughout: its runs are already 128 bytes, and on MI355X the
+    // 2^13 tile measured no faster for one or two blocks (whole circuits
+    // 0.2-0.7 % slower with it).  Small states keep the small tile (enough
+    // tiles to spread).
     const int T = pass_tile_log(dtype);
-    const int few = dtype == SV_C64 ? 2 : 3;
+    const int few = dtype == SV_C64 ? 0 : 3;
     return (nsub <= few && n >= T + 1 + 6) ? T + 1 : T;
 }
 
