@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--max-fused", type=int, default=5)
     ap.add_argument("--precision", choices=["native", "bf16x3"], default="native")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (unfused) comparison run")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the FP64 reference run (CPU baseline and the accuracy fields)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of the state size (HBM counter calibration)")
     return ap.parse_args()
@@ -131,6 +131,9 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     gate_apps = len(gates) / (ms_step / 1e3)
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {gate_apps:.1f} gate-apps/s")
+    # the last step's final state, in logical order (the exchange only
+    # relabels index bits), for the accuracy check after the timed region
+    final_state = None if args.no_cpu_baseline else B.sv_copy_to_host(sv.handle, n, dtype)
 
     # per-kernel-class totals from the live HIP-event records
     classes = {}
@@ -171,6 +174,7 @@ def main():
                      "mfma_peak_TFLOP/s": mpeak / 1e12,
                      "blocks_per_launch": round(blocks, 2)}
     plain = None
+    plain_state = None
     if not args.no_plain and args.mode != "plain":
         popts = B.make_opts(B.SV_PLAN_PLAIN)
         B.sv_reset(sv.handle)
@@ -192,6 +196,7 @@ def main():
         plain = {"ms_per_circuit": round(p_ms, 3), "gate_apps_per_s": round(len(gates) / (p_ms / 1e3), 1),
                  "sweeps": pst["sweeps"], "kernel_GB/s": round(p_bytes / (p_kernel_ms / 1e3) / 1e9, 1),
                  "dense_1q_GB/s": round(g1_gbs, 1) if g1_gbs else None}
+        plain_state = None if args.no_cpu_baseline else B.sv_copy_to_host(sv.handle, n, dtype)
         log(f"plain: {plain}")
 
     copy_cal = None
@@ -214,25 +219,26 @@ def main():
         del a, b
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         import oracle
 
-        log("cpu baseline: FP64 reference on the same circuit (bounded sample) ...")
+        log(f"cpu baseline: FP64 reference, the whole {len(gates)}-gate circuit on host cores ...")
         a = oracle.zero_state(n)
         t0 = time.perf_counter()
-        done = 0
         for g in gates:
             oracle.apply_gate(a, g)
-            done += 1
-            if done >= 3 and time.perf_counter() - t0 > args.cpu_seconds:
-                break
         dt = time.perf_counter() - t0
-        cpu = {"value": round(done / dt, 3), "unit": "gate-apps/s", "cores": oracle.num_threads(),
+        cpu = {"value": round(len(gates) / dt, 3), "unit": "gate-apps/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": f"first {done} of the {len(gates)} gates of the same {n}-qubit circuit, "
-                         f"unfused, FP64 complex128, {dt:.1f} s on host cores"}
-        del a
+               "sample": f"the whole {len(gates)}-gate {n}-qubit circuit once, unfused, FP64 complex128, "
+                         f"{dt:.1f} s wall on host cores"}
         log(f"cpu baseline: {cpu}")
+        accuracy = {args.mode: state_error(final_state, a)}
+        if plain_state is not None:
+            accuracy["plain"] = state_error(plain_state, a)
+        log(f"accuracy vs the FP64 reference: {accuracy}")
+        del a, final_state, plain_state
 
     out = {
         "metric": METRIC,
@@ -266,8 +272,32 @@ def main():
         "copy_calibration": copy_cal,
         "cpu_baseline": cpu,
     }
+    if accuracy is not None:
+        # the final state of the timed steps against the FP64 reference
+        out["max_abs_err"] = accuracy[args.mode]["max_abs_err"]
+        out["l2_err"] = accuracy[args.mode]["l2_err"]
+        out["accuracy_vs_fp64_oracle"] = accuracy
     print(json.dumps(out), flush=True)
     sv.close()
+
+
+def state_error(got, want, chunk=1 << 24):
+    """max |d a|, ||d psi||_2 and the largest |d a| / |a| over amplitudes of
+    modulus >= 2^-15, FP64, in chunks."""
+    import numpy as np
+
+    mx, l2, rel = 0.0, 0.0, 0.0
+    for i in range(0, want.size, chunk):
+        w = want[i:i + chunk]
+        d = np.abs(np.asarray(got[i:i + chunk], dtype=np.complex128) - w)
+        mx = max(mx, float(d.max()))
+        l2 += float(np.dot(d, d))
+        aw = np.abs(w)
+        sel = aw >= 2.0 ** -15
+        if np.any(sel):
+            rel = max(rel, float(np.max(d[sel] / aw[sel])))
+    return {"max_abs_err": float(f"{mx:.4g}"), "l2_err": float(f"{l2 ** 0.5:.4g}"),
+            "max_rel_err_amps_ge_2^-15": float(f"{rel:.4g}")}
 
 
 def counter_traffic(dom_key, n, dtype, args):

@@ -146,9 +146,12 @@ const char *sv_last_error(void);
 int sv_state_bytes(int n, int dtype, uint64_t *bytes);
 
 /* Allocate a state of n qubits (1..SV_MAX_QUBITS) on the current HIP device
- * and set it to |0...0>.  The library owns the memory; sv_destroy frees it.
- * SV_ENOMEM if the state does not fit in free device memory (or exceeds the
- * SV_MAX_DEVICE_BYTES environment limit, checked on the host first). */
+ * and set it to |0...0>: the complex vector of dimension 2^n of the paper's
+ * state-vector representation (Sec. 2.1 "State-Vector Simulation"), 2^(n-27)
+ * GiB in complex64 (Sec. 1).  Amplitude 0 is 1, all others 0.  The library
+ * owns the memory; sv_destroy frees it.  SV_ENOMEM if the state does not
+ * fit in free device memory (or exceeds the SV_MAX_DEVICE_BYTES environment
+ * limit, checked on the host first). */
 int sv_create(int n, int dtype, sv_handle *out);
 
 /* Wrap caller-owned device memory (e.g. a torch tensor) of `bytes` >=
@@ -191,11 +194,18 @@ int sv_qubit_map(sv_handle h, int *map);
 
 /* Marginal distribution over logical qubits Q[0..m) (0 <= m <= min(n, 30)):
  * out[x] = sum of |a_i|^2 over i whose qubit Q[b] equals bit b of x; 2^m
- * doubles.  m = 0 gives the squared norm.  FP64 accumulation for both
+ * doubles.  These are the probabilities with which a measurement of the
+ * qubits Q returns the bitstring x (Sec. 2.1 "Measurement and Sampling":
+ * the amplitudes determine the outcome distribution; the squared moduli of
+ * a qubit's amplitudes are its outcome probabilities, Sec. 2.1 "Classical
+ * Bits and Qubits").  m = 0 gives the squared norm.  FP64 accumulation for both
  * dtypes.  Synchronises. */
 int sv_probabilities(sv_handle h, const int *qubits, int m, double *out);
 
-/* Expectation values <psi|P|psi> of Pauli strings.  terms[t] is a string of
+/* Expectation values <psi|P|psi> of Pauli strings, the quantities shots are
+ * repeated to estimate (Sec. 2.1 "Measurement and Sampling") and that the
+ * simulator's read-out functions return for each task (Sec. 2.5); here they
+ * are computed exactly from the amplitudes.  terms[t] is a string of
  * n characters from "IXYZ" (lower case accepted), character q acting on
  * logical qubit q.  out[t] receives the real part (the imaginary part of a
  * Hermitian expectation is zero up to rounding).  FP64 accumulation.
@@ -209,8 +219,27 @@ int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *o
  * out[s] is the logical bitstring (bit q = qubit q).  Synchronises. */
 int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out);
 
+/* Draw `shots` outcomes as sv_sample does, with the uniforms taken from the
+ * library's own seeded stream: u_s = sv_uniforms(seed, s) for s = 0..shots-1
+ * (the paper's benchmarks sample 1000 shots per circuit, Sec. 2.2).  The same
+ * seed gives the same outcomes on every call and device.  out: `shots`
+ * int64 host values.  Synchronises. */
+int sv_sample_seeded(sv_handle h, int shots, uint64_t seed, int64_t *out);
+
+/* The library's uniform stream, host only (no device work): out[j] = u_{first+j}
+ * for j < count, where u_s is the s-th output of SplitMix64 (Steele, Lea, Flood,
+ * OOPSLA 2014) started from state `seed`:
+ *     z = seed + (s + 1) * 0x9E3779B97F4A7C15 (mod 2^64),
+ *     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9, z = (z ^ (z >> 27)) * 0x94D049BB133111EB,
+ *     z = z ^ (z >> 31),  u_s = (z >> 11) * 2^-53  in [0, 1).
+ * SV_EINVAL if count < 0 or out is NULL with count > 0. */
+int sv_uniforms(uint64_t seed, uint64_t first, int count, double *out);
+
 /* Copy amplitudes [first, first+count) in LOGICAL index order to host memory
- * (count * bytes-per-amplitude bytes, dtype layout).  Synchronises. */
+ * (count * bytes-per-amplitude bytes, dtype layout): the state vector itself,
+ * the result of state-vector simulation (Sec. 2.1 "State-Vector Simulation").
+ * `dst` is caller-owned host memory; SV_EINVAL for a range outside [0, 2^n).
+ * Synchronises. */
 int sv_copy_to_host(sv_handle h, void *dst, uint64_t first, uint64_t count);
 
 /* Overwrite amplitudes [first, first+count) (logical order) from host memory.

@@ -81,6 +81,9 @@ class StateVector:
     def sample(self, uniforms) -> np.ndarray:
         return _b.sv_sample(self.handle, uniforms)
 
+    def sample_seeded(self, shots: int, seed: int) -> np.ndarray:
+        return _b.sv_sample_seeded(self.handle, shots, seed)
+
     def to_host(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         return _b.sv_copy_to_host(self.handle, self.n, self.dtype, first, count)
 

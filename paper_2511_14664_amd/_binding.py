@@ -83,6 +83,8 @@ def _load():
         "sv_probabilities": ([P, P, I, P], I),
         "sv_expect_pauli": ([P, ctypes.POINTER(ctypes.c_char_p), I, P], I),
         "sv_sample": ([P, P, I, P], I),
+        "sv_sample_seeded": ([P, I, U64, P], I),
+        "sv_uniforms": ([U64, U64, I, P], I),
         "sv_copy_to_host": ([P, P, U64, U64], I),
         "sv_copy_from_host": ([P, P, U64, U64], I),
         "sv_plan_create": ([I, I, ctypes.POINTER(sv_gate), I, ctypes.POINTER(sv_plan_opts),
@@ -238,6 +240,18 @@ def sv_sample(h: int, uniforms) -> np.ndarray:
     out = np.empty(max(1, u.size), dtype=np.int64)
     _check(_lib.sv_sample(ctypes.c_void_p(h), u.ctypes.data, u.size, out.ctypes.data), "sv_sample")
     return out[:u.size]
+
+
+def sv_sample_seeded(h: int, shots: int, seed: int) -> np.ndarray:
+    out = np.empty(max(1, shots), dtype=np.int64)
+    _check(_lib.sv_sample_seeded(ctypes.c_void_p(h), shots, seed, out.ctypes.data), "sv_sample_seeded")
+    return out[:shots]
+
+
+def sv_uniforms(seed: int, count: int, first: int = 0) -> np.ndarray:
+    out = np.empty(max(1, count), dtype=np.float64)
+    _check(_lib.sv_uniforms(seed, first, count, out.ctypes.data), "sv_uniforms")
+    return out[:count]
 
 
 def sv_copy_to_host(h: int, n: int, dtype: int, first: int = 0, count: Optional[int] = None) -> np.ndarray:

@@ -1483,6 +1483,48 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
     return SV_OK;
 }
 
+// Uniform s of the shot stream of `seed`: the s-th output of SplitMix64
+// (Steele, Lea, Flood, OOPSLA 2014) started from state `seed`, i.e. the mix
+// function applied to seed + (s + 1) * 0x9E3779B97F4A7C15, whose top 53 bits
+// scaled by 2^-53 give a double in [0, 1).  A pure function of (seed, s), so
+// any range of the stream can be produced on its own.
+static double shot_uniform(uint64_t seed, uint64_t s)
+{
+    uint64_t z = seed + (s + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return double(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+int sv_uniforms(uint64_t seed, uint64_t first, int count, double *out)
+{
+    clear_error();
+    if (count < 0 || (count > 0 && !out)) {
+        set_error("bad uniform-stream arguments");
+        return SV_EINVAL;
+    }
+    for (int s = 0; s < count; ++s)
+        out[s] = shot_uniform(seed, first + uint64_t(s));
+    return SV_OK;
+}
+
+int sv_sample_seeded(sv_handle h, int shots, uint64_t seed, int64_t *out)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (shots < 0 || (shots > 0 && !out)) {
+        set_error("bad sampling arguments");
+        return SV_EINVAL;
+    }
+    std::vector<double> u(size_t(shots) + 1);
+    for (int s = 0; s < shots; ++s)
+        u[s] = shot_uniform(seed, uint64_t(s));
+    return sv_sample(h, u.data(), shots, out);
+}
+
 int sv_copy_to_host(sv_handle h, void *dst, uint64_t first, uint64_t count)
 {
     clear_error();

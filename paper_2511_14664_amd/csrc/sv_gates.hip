@@ -643,14 +643,10 @@ hipError_t launch_tile_k(void *st, int n, const void *d_U, int k, const int *tgt
 
 int dense_path(int n, int dtype, int k, int c, int precision)
 {
-    static const bool no_mfma = [] {
-        const char *e = getenv("SV_NO_MFMA");
-        return e && *e && *e != '0';
-    }();
-    if (!no_mfma && precision == SV_PREC_BF16X3 && dtype == SV_C64 && (k == 5 || k == 6) && n - c >= 12)
+    if (precision == SV_PREC_BF16X3 && dtype == SV_C64 && (k == 5 || k == 6) && n - c >= 12)
         return SV_SWEEP_DENSE_BF16X3;
     const int tl = mfma_tile_log(dtype, k);
-    if (!no_mfma && tl > 0 && n - c >= tl)
+    if (tl > 0 && n - c >= tl)
         return SV_SWEEP_DENSE_MFMA;
     const int m = (k <= 5) ? 11 - k : 6;
     return (n - c - k < m) ? SV_SWEEP_GROUP : SV_SWEEP_DENSE;

@@ -529,9 +529,19 @@ std::vector<Group> group_greedy(const std::vector<Block> &gates, int kmax)
     return greedy_masks(m, m, nullptr, kmax, 64, nullptr);
 }
 
+// A diagonal gate whose entries all have modulus 1 (to rounding) is a pure
+// phase on each basis state, so a pass may fold it in as angles; a diagonal
+// with other moduli (not unitary) keeps its magnitudes by taking the
+// ordinary block path.
 bool is_phase_gate(const Block &b)
 {
-    return b.diag && b.k + b.c <= kMaxPhaseQubits;
+    if (!b.diag || b.k + b.c > kMaxPhaseQubits)
+        return false;
+    const int d = 1 << b.k;
+    for (int x = 0; x < d; ++x)
+        if (std::fabs(std::norm(b.U[size_t(x) * d + x]) - 1.0) > 1e-10)
+            return false;
+    return true;
 }
 
 uint64_t outer_capable(const Block &b)

@@ -247,3 +247,45 @@ def test_pass_plan_info_rejects_bad_input():
         B.sv_pass_plan_info(12, B.SV_C64, [Gate("h", (12,))])
     with pytest.raises(B.SvError):
         B.sv_pass_plan_info(0, B.SV_C64, g)
+
+
+# ---------------------------------------------------------------------------
+# The seeded shot stream (sv_uniforms / sv_sample_seeded), host only
+# ---------------------------------------------------------------------------
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64(seed, s):
+    """s-th output of SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) from state
+    `seed`: the state advances by the golden-ratio increment and each output
+    is the published 64-bit finaliser of the new state."""
+    z = (seed + (s + 1) * 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_reference_outputs():
+    # the first outputs of the reference SplitMix64 generator from state 0
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "splitmix64_seed0.json")))
+    assert [_splitmix64(0, s) for s in range(len(gold["outputs"]))] == [int(x, 16) for x in gold["outputs"]]
+
+
+def test_uniform_stream_is_splitmix64():
+    for seed in (0, 7, 2 ** 64 - 1, 0x0123456789ABCDEF):
+        got = B.sv_uniforms(seed, 300)
+        want = np.array([(_splitmix64(seed, s) >> 11) * 2.0 ** -53 for s in range(300)])
+        assert np.array_equal(got, want)
+        assert np.all((got >= 0) & (got < 1))
+        # any window of the stream can be produced on its own
+        assert np.array_equal(B.sv_uniforms(seed, 17, first=250), got[250:267])
+    assert B.sv_uniforms(3, 0).size == 0
+    with pytest.raises(B.SvError) as e:
+        B.sv_uniforms(3, -1)
+    assert e.value.code == B.SV_EINVAL
+
+
+def test_sample_seeded_rejects_before_touching_the_device():
+    with pytest.raises(B.SvError) as e:
+        B.sv_sample_seeded(0, 10, 1)
+    assert e.value.code == B.SV_EINVAL
