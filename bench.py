@@ -23,6 +23,8 @@ if ROOT not in sys.path:
 
 METRIC = "gate-apps/s & achieved HBM GB/s at 28–34 qubits, fused vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+PREC_LABEL = {"native": "products in the state precision", "bf16x3": "three-term BF16 split",
+              "bf16x6": "FP32-accurate six-product split-BF16 products"}
 
 
 def parse():
@@ -42,7 +44,10 @@ def parse():
     ap.add_argument("--mode", choices=["plain", "greedy", "learned", "passes"], default="passes")
     ap.add_argument("--pass-qubits", type=int, default=8, help="qubits per LDS pass (--mode passes)")
     ap.add_argument("--max-fused", type=int, default=5)
-    ap.add_argument("--precision", choices=["native", "bf16x3"], default="native")
+    ap.add_argument("--precision", choices=["native", "bf16x3", "bf16x6"], default="native",
+                    help="native: FP32 (complex64) / FP64 (complex128) arithmetic; bf16x3: three-term BF16 "
+                         "split for complex64 5-6-qubit greedy blocks; bf16x6: FP32-accurate six-product split "
+                         "BF16 for complex64 pass blocks")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (unfused) comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 reference run (CPU baseline and the accuracy fields)")
@@ -89,7 +94,7 @@ def main():
     circ = B.Circuit(gates)
     mode = {"plain": B.SV_PLAN_PLAIN, "greedy": B.SV_PLAN_GREEDY, "learned": B.SV_PLAN_LEARNED,
             "passes": B.SV_PLAN_PASSES}[args.mode]
-    prec = B.SV_PREC_BF16X3 if args.precision == "bf16x3" else B.SV_PREC_NATIVE
+    prec = {"native": B.SV_PREC_NATIVE, "bf16x3": B.SV_PREC_BF16X3, "bf16x6": B.SV_PREC_BF16X6}[args.precision]
     opts = B.make_opts(mode, args.max_fused, prec, args.pass_qubits if args.mode == "passes" else 0)
     marg_q = list(range(n - 10, n))
     terms = W.hea_z_terms(n)[: 2 * 16]
@@ -160,18 +165,22 @@ def main():
                  for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms"])}
 
     traffic = counter_traffic(dom_key, n, dtype, args)
-    # A pass launch also runs its blocks on the matrix cores: a d x d complex
-    # block costs 8 d - 2 algorithmic flops per amplitude and three real
-    # d x d products (6 d flops per amplitude) on the matrix cores, so the
-    # two totals also give the number of blocks.
+    # A pass launch also runs its blocks on the matrix cores.  Each block is a
+    # dense 16 x 16 complex matrix (8 * 16 - 2 = 126 algorithmic flops per
+    # amplitude); the matrix cores execute three real 16 x 16 products (96
+    # flops per amplitude, FP32 / FP64) or, with split BF16 operands, two
+    # real output rows x 32 terms x six part products (768 BF16 flops per
+    # amplitude).  The records carry both totals.
     mfma_side = {}
-    if dom_key[0] == "pass" and args.precision == "native":
-        mpeak = 157.3e12 if dtype == B.SV_C64 else 78.6e12
+    if dom_key[0] == "pass" and args.precision in ("native", "bf16x6"):
+        split = args.precision == "bf16x6" and dtype == B.SV_C64
+        mpeak = 2500e12 if split else (157.3e12 if dtype == B.SV_C64 else 78.6e12)
         mflops = dom["mfma_flops"] / dom["launches"]
-        blocks = (dom["mfma_flops"] * 8.0 / 6.0 - dom["flops"]) / (2.0 * 2.0 ** n) / dom["launches"]
+        blocks = dom["flops"] / (126.0 * 2.0 ** n) / dom["launches"]
         mfma_side = {"mfma_flops_per_launch": mflops,
                      "mfma_frac": round(mflops / (avg_ms / 1e3) / mpeak, 4),
                      "mfma_peak_TFLOP/s": mpeak / 1e12,
+                     "mfma_dtype": "bf16 (split FP32 operands)" if split else ("fp32" if dtype == B.SV_C64 else "fp64"),
                      "blocks_per_launch": round(blocks, 2)}
     plain = None
     plain_state = None
@@ -256,7 +265,8 @@ def main():
         "config": {"workload": f"{n}-qubit random layered circuit (U3 on every qubit + CNOT/CZ on a random "
                                f"matching, depth 20, {len(gates)} gates), {args.dtype}, "
                                + (f"LDS passes of <= {args.pass_qubits} qubits (fused 4-qubit blocks on the matrix "
-                                  f"cores)" if args.mode == "passes" else f"{args.mode} fusion <= {args.max_fused} qubits")
+                                  f"cores, {PREC_LABEL[args.precision]})" if args.mode == "passes"
+                                  else f"{args.mode} fusion <= {args.max_fused} qubits")
                                + f", + 6-bit index exchange, 10-qubit marginal, "
                                f"{len(terms)} Z-string expectations, 1000 shots",
                    "qubits": n, "state_bytes": S << n, "gates": len(gates),

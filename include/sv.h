@@ -108,10 +108,16 @@ typedef enum sv_plan_mode {
 
 typedef enum sv_precision {
     SV_PREC_NATIVE = 0,   /* complex64: FP32 arithmetic; complex128: FP64 */
-    SV_PREC_BF16X3 = 1    /* complex64 fused blocks of 5-6 qubits: three-term BF16 split
+    SV_PREC_BF16X3 = 1,   /* complex64 fused blocks of 5-6 qubits: three-term BF16 split
                              products on the matrix cores, FP32 accumulation (relative
                              error ~2^-16 per product); other blocks and complex128
                              run as SV_PREC_NATIVE */
+    SV_PREC_BF16X6 = 2    /* complex64 LDS-pass blocks (SV_PLAN_PASSES): every FP32 operand
+                             split exactly into three BF16 parts, each real product taken
+                             as the six largest of the nine part products on the BF16
+                             matrix cores with FP32 accumulation (dropped terms below
+                             2^-23 relative per product: FP32-accurate); other sweeps and
+                             complex128 run as SV_PREC_NATIVE */
 } sv_precision;
 
 typedef struct sv_plan_opts {
@@ -272,7 +278,7 @@ typedef struct sv_sweep_record {
     double bytes;            /* algorithmic HBM bytes */
     double flops;            /* algorithmic: 8 d - 2 per amplitude per dense d x d complex block */
     float ms;                /* HIP-event duration on the handle's stream */
-    int32_t reserved;
+    int32_t precision;       /* sv_precision of the sweep's arithmetic */
     double mfma_flops;       /* real flops a pass executes on the matrix cores (0: other sweeps) */
 } sv_sweep_record;
 

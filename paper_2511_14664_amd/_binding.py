@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4
 SV_C64, SV_C128 = 0, 1
 SV_PLAN_PLAIN, SV_PLAN_GREEDY, SV_PLAN_LEARNED, SV_PLAN_PASSES = 0, 1, 2, 3
-SV_PREC_NATIVE, SV_PREC_BF16X3 = 0, 1
+SV_PREC_NATIVE, SV_PREC_BF16X3, SV_PREC_BF16X6 = 0, 1, 2
 SV_MAX_TARGETS, SV_MAX_CONTROLS = 6, 8
 
 GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
@@ -323,7 +323,7 @@ class sv_sweep_record(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("c", ctypes.c_int32),
                 ("lowest_target", ctypes.c_int32), ("highest_target", ctypes.c_int32),
                 ("num_gates", ctypes.c_int32), ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32), ("mfma_flops", ctypes.c_double)]
+                ("ms", ctypes.c_float), ("precision", ctypes.c_int32), ("mfma_flops", ctypes.c_double)]
 
 
 SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap",
@@ -347,7 +347,7 @@ def sv_profile_read(h: int, max_records: int = 1 << 16) -> List[dict]:
     out = []
     for i in range(min(cnt.value, max_records)):
         r = buf[i]
-        d = {f: getattr(r, f) for f, _ in r._fields_ if f != "reserved"}
+        d = {f: getattr(r, f) for f, _ in r._fields_}
         d["kind_name"] = SWEEP_KIND.get(r.kind, str(r.kind))
         out.append(d)
     return out

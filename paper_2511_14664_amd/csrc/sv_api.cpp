@@ -476,6 +476,7 @@ struct PassWork {
     uint64_t bytes = 0;
     uint64_t nterm_max = 0;  // bound on the pass's phase terms
     int ngates = 0;
+    bool split = false;      // complex64 blocks as split BF16 products (SV_PREC_BF16X6)
 };
 
 // Monomials of a phase gate's angle: a diagonal gate on qubits Q (targets,
@@ -776,9 +777,11 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     pr.rec.bytes = 2.0 * double(h->bytes);
     // every block a dense 16 x 16 complex matrix: 8 * 16 - 2 flops per
     // amplitude; on the matrix cores three real products of 2 * 16 flops
-    // per amplitude each
+    // per amplitude each (FP32 / FP64), or with split BF16 operands two
+    // real output rows x 32 terms x six part products x 2 flops (BF16)
     pr.rec.flops = double(nsub) * (8.0 * 16.0 - 2.0) * std::ldexp(1.0, h->n);
-    pr.rec.mfma_flops = double(nsub) * 6.0 * 16.0 * std::ldexp(1.0, h->n);
+    pr.rec.mfma_flops = double(nsub) * (w.split ? 768.0 : 96.0) * std::ldexp(1.0, h->n);
+    pr.rec.precision = w.split ? SV_PREC_BF16X6 : SV_PREC_NATIVE;
     int rc = prof_begin(h, pr);
     if (rc != SV_OK)
         return rc;
@@ -786,7 +789,8 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     bool phases = false;
     for (size_t i = 0; i < nsub; ++i)
         phases = phases || !w.front[i].empty() || !w.back[i].empty();
-    hipError_t e = launch_pass(h->d_state, h->n, h->dtype, T, tb, base + w.off, int(nsub), base, phases, h->stream);
+    hipError_t e =
+        launch_pass(h->d_state, h->n, h->dtype, T, tb, base + w.off, int(nsub), base, phases, w.split, h->stream);
     if (e != hipSuccess) {
         set_error("pass %zu launch failed: %s", index, hipGetErrorString(e));
         return SV_EDEVICE;
@@ -824,6 +828,7 @@ int run_passes(sv_state *h, const std::vector<Block> &circuit, int pass_qubits, 
         w.back = pg[i].back;
         w.vq = pg[i].vq;
         w.ngates = pg[i].ngates;
+        w.split = precision == SV_PREC_BF16X6 && h->dtype == SV_C64;
         w.off = total;
         if (w.kernel) {
             uint64_t nmat = 0;

@@ -210,9 +210,10 @@ int pass_tile_log_for(int n, int dtype, int nsub);
 // lowest free bits outside phys_avoid); returns T, or -1 if the pass does not
 // fit.
 int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *tile_bits);
-// phases: some block carries phase terms (selects the kernel that reads them).
+// phases: some block carries phase terms (selects the kernel that reads them);
+// split: complex64 blocks as FP32-accurate split BF16 products (T = 12 only).
 hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
-                       const void *d_mats, bool phases, hipStream_t s);
+                       const void *d_mats, bool phases, bool split, hipStream_t s);
 
 // Z strings per launch_expect_z call.
 int expect_z_batch();

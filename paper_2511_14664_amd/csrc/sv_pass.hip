@@ -305,6 +305,218 @@ void k_pass(R *__restrict__ st, const TileArgs a, const PassSub *__restrict__ su
     });
 }
 
+// ---------------------------------------------------------------------------
+// Complex64 passes with FP32-accurate split BF16 products.
+//
+// Each FP32 value x is split exactly into three BF16 parts, x = h + m + l
+// (h = bf16(x), m = bf16(x - h), l = x - h - m, rounding to nearest: x - h
+// and x - h - m are exact FP32 differences and the last has at most 8
+// significant bits, so l is exact as well; |m| <= 2^-8 |x|, |l| <= 2^-16 |x|).
+// A real product X Y is then the six BF16 products Xh Yh + Xh Ym + Xm Yh +
+// Xh Yl + Xm Ym + Xl Yh; the three dropped ones (Xm Yl, Xl Ym, Xl Yl) are
+// below 2^-23 |X||Y| together, and the BF16 products are exact in the FP32
+// accumulator.  The block runs as one real contraction of the complex
+// product: [Yr; Yi] = [[Ur, -Ui], [Ui, Ur]] [Vr; Vi], K = 32 real terms, on
+// v_mfma_f32_16x16x32_bf16 (BF16 matrix rate, 16x that of FP32): two 16-row
+// output tiles (real and imaginary rows) x six products per group set.
+//
+// The K index is ordered so that lane l (q = l / 16, j = l % 16) supplies
+// B[8 q + 2 r + c][j] = component c of amplitude row 4 q + r of group j, and
+// receives D[4 q + r][j]: each lane reads and writes the same four
+// amplitudes of a group, so a block needs no barrier between group sets.
+// Its A fragment A[j][8 q + 2 r + c] holds U entries of row j, column
+// 4 q + r.  Products are accumulated smallest first.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// (a, b) as two BF16 values in one register, a in the low half.  The empty
+// asm keeps the compiler from re-deriving either half by a separate
+// conversion.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    const bf16x2_t p = {__bf16(a), __bf16(b)};
+    uint32_t r = __builtin_bit_cast(uint32_t, p);
+    asm("" : "+v"(r));
+    return r;
+}
+
+// Exact three-part split of the pair (a, b): parts packed as by pack_bf16.
+__device__ __forceinline__ void split3(float a, float b, uint32_t &h, uint32_t &m, uint32_t &l)
+{
+    h = pack_bf16(a, b);
+    const float ra = a - __builtin_bit_cast(float, h << 16);
+    const float rb = b - __builtin_bit_cast(float, h & 0xffff0000u);
+    m = pack_bf16(ra, rb);
+    const float sa = ra - __builtin_bit_cast(float, m << 16);
+    const float sb = rb - __builtin_bit_cast(float, m & 0xffff0000u);
+    l = pack_bf16(sa, sb);
+}
+
+__device__ __forceinline__ bf16x8_t as_bf16x8(const uint32_t *w)
+{
+    const u32x4_t v = {w[0], w[1], w[2], w[3]};
+    return __builtin_bit_cast(bf16x8_t, v);
+}
+
+// acc + (Ah + Am + Al)(Bh + Bm + Bl) without the three smallest products,
+// smallest first
+__device__ __forceinline__ floatx4 mma_split6(const uint32_t *ah, const uint32_t *am, const uint32_t *al,
+                                              const bf16x8_t &bh, const bf16x8_t &bm, const bf16x8_t &bl)
+{
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(am), bm, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(am), bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), bm, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), bh, acc, 0, 0, 0);
+    return acc;
+}
+
+template <bool PHASES>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASES ? 4 : 5)))
+void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__restrict__ subs, int nsub,
+                  const char *__restrict__ mats)
+{
+    using C = float2;
+    constexpr int TA_LOG = 12;
+    constexpr int D = 16, NT = 16;
+    constexpr int NGS = (1 << (TA_LOG - 4)) / NT;  // group sets of 16 groups
+    constexpr int NW = kThreads / 64;
+    constexpr int PER_WAVE = NGS / NW;
+    static_assert(PER_WAVE >= 1 && NGS % NW == 0, "tile shape");
+
+    __shared__ __align__(16) C tile[1 << TA_LOG];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int q = lane / 16, j16 = lane % 16;
+
+    const uint64_t tbase = insert_zeros(uint64_t(blockIdx.y) * gridDim.x + blockIdx.x, a.outer);
+    // this lane's FP32 fragment of block sb: U[j16][4 q + r], r < 4
+    auto load_u = [&](int sb, float *ur, float *ui) {
+        const PassSub &d = subs[sb];
+        uint32_t var = 0;
+        for (uint32_t v = 0; v < d.nvar; ++v)
+            var |= uint32_t((tbase >> d.vpos[v]) & 1) << v;
+        const float4 *U = reinterpret_cast<const float4 *>(reinterpret_cast<const C *>(mats + d.u_off) +
+                                                           size_t(var) * (D * D) + j16 * D + 4 * q);
+        const float4 u0 = U[0], u1 = U[1];
+        ur[0] = u0.x;
+        ui[0] = u0.y;
+        ur[1] = u0.z;
+        ui[1] = u0.w;
+        ur[2] = u1.x;
+        ui[2] = u1.y;
+        ur[3] = u1.z;
+        ui[3] = u1.w;
+    };
+    float ur[4], ui[4];
+    load_u(0, ur, ui);  // in flight with the tile's loads
+
+    // per-tile phase angles, as in k_pass (fixed-point turns, 32 bits)
+    __shared__ uint32_t angles[PHASES ? kMaxTermBlocks * 32 : 1];
+    auto fill_angles = [&]() {
+        for (int sb = 0; sb < nsub; ++sb) {
+            const PassSub &d = subs[sb];
+            if (d.nterm == 0 || int(d.pslot % NW) != wave)
+                continue;
+            const PassTerm *tm = reinterpret_cast<const PassTerm *>(mats + d.t_off);
+            uint32_t *row = angles + d.pslot * 32;
+            if (lane < 32)
+                row[lane] = 0;
+            for (uint32_t e = uint32_t(lane); e < d.nterm; e += 64) {
+                const PassTerm t = tm[e];
+                if ((tbase & t.omask) == t.omask)
+                    lds_add(&row[t.back * 16 + t.smask], uint32_t(t.turn >> 32));
+            }
+            uint32_t acc = lane < 32 ? row[lane] : 0u;
+#pragma unroll
+            for (int bit = 1; bit < 16; bit <<= 1) {
+                const uint32_t other = __shfl_xor(acc, bit);
+                if (lane & bit)
+                    acc += other;
+            }
+            if (lane < 32)
+                row[lane] = acc;
+        }
+    };
+
+    tile_sweep<float, TA_LOG, true, kThreads, true, true>(st, a, tile, [&](C *t) {
+        if (PHASES) {
+            fill_angles();
+            __syncthreads();
+        }
+        for (int sb = 0; sb < nsub; ++sb) {
+            const PassSub &d = subs[sb];
+            if (PHASES && d.nterm > 0) {
+                // U[r][c] exp(i (front(c) + back(r))), r = j16, c = 4 q + k
+                const uint32_t *row = angles + d.pslot * 32;
+                const uint32_t tb = row[16 + j16];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float sn, cs;
+                    turn_sincos(uint32_t(row[4 * q + k] + tb), sn, cs);
+                    const float r0 = ur[k], i0 = ui[k];
+                    ur[k] = r0 * cs - i0 * sn;
+                    ui[k] = r0 * sn + i0 * cs;
+                }
+            }
+            // A operands: real rows [Ur, -Ui], imaginary rows [Ui, Ur], split
+            uint32_t arh[4], arm[4], arl[4], aih[4], aim[4], ail[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                split3(ur[k], -ui[k], arh[k], arm[k], arl[k]);
+                split3(ui[k], ur[k], aih[k], aim[k], ail[k]);
+            }
+            if (sb + 1 < nsub)
+                load_u(sb + 1, ur, ui);
+            // LDS byte offsets (XOR-linear parts, as in k_pass): lane part
+            // from (q, j16), register part from the row r, wave-uniform part
+            // from the group set
+            const uint32_t x4 = d.xc[4], x8 = d.xc[8];
+            auto deposit = [&](uint32_t g) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t lo = d.tslot_m[b];
+                    g = (g & lo) | ((g & ~lo) << 1);
+                }
+                return g;
+            };
+            const uint32_t lane_off = swz_p(((q & 1) ? x4 : 0u) | ((q & 2) ? x8 : 0u) | deposit(uint32_t(j16))) << 3;
+            uint32_t roff[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                roff[r] = swz_p(d.xc[r]) << 3;
+            char *tb = reinterpret_cast<char *>(t);
+#pragma unroll
+            for (int g = 0; g < PER_WAVE; ++g) {
+                const uint32_t hoff = swz_p(deposit(uint32_t(wave + NW * g) * NT)) << 3;
+                float v[8];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const C x = *reinterpret_cast<const C *>(tb + (lane_off ^ (roff[r] ^ hoff)));
+                    v[2 * r] = x.x;
+                    v[2 * r + 1] = x.y;
+                }
+                uint32_t bh[4], bm[4], bl[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    split3(v[2 * r], v[2 * r + 1], bh[r], bm[r], bl[r]);
+                const bf16x8_t Bh = as_bf16x8(bh), Bm = as_bf16x8(bm), Bl = as_bf16x8(bl);
+                const floatx4 yr = mma_split6(arh, arm, arl, Bh, Bm, Bl);
+                const floatx4 yi = mma_split6(aih, aim, ail, Bh, Bm, Bl);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    *reinterpret_cast<C *>(tb + (lane_off ^ (roff[r] ^ hoff))) = make_float2(yr[r], yi[r]);
+            }
+            __syncthreads();
+        }
+    });
+}
+
 template <typename R, int TA_LOG, int NTH>
 hipError_t launch_pass_t(void *st, const TileArgs &a, const void *subs, int nsub, const void *mats, bool phases,
                          hipStream_t s)
@@ -368,10 +580,12 @@ int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *
 }
 
 hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
-                       const void *d_mats, bool phases, hipStream_t s)
+                       const void *d_mats, bool phases, bool split, hipStream_t s)
 {
     const int T0 = pass_tile_log(dtype);
     if (nsub < 1 || (T != T0 && T != T0 + 1) || n < T)
+        return hipErrorInvalidValue;
+    if (split && (dtype != SV_C64 || T != 12))
         return hipErrorInvalidValue;
     TileArgs a{};
     std::vector<int> bits(tile_bits, tile_bits + T);
@@ -379,6 +593,19 @@ hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, 
         a.dep[b] = uint64_t(1) << bits[b];
     a.outer = make_insert_masks(bits);
     a.ntiles = uint64_t(1) << (n - T);
+    if (split) {
+        if (a.dep[0] != 1)
+            return hipErrorInvalidValue;
+        const PassSub *ps = static_cast<const PassSub *>(d_subs);
+        const char *m = static_cast<const char *>(d_mats);
+        if (phases)
+            hipLaunchKernelGGL(k_pass_split<true>, tile_grid(a.ntiles), dim3(kThreads), 0, s, (float *)st, a, ps,
+                               nsub, m);
+        else
+            hipLaunchKernelGGL(k_pass_split<false>, tile_grid(a.ntiles), dim3(kThreads), 0, s, (float *)st, a, ps,
+                               nsub, m);
+        return hipGetLastError();
+    }
     if (dtype == SV_C64)
         return T == 12 ? launch_pass_t<float, 12, kThreads>(st, a, d_subs, nsub, d_mats, phases, s)
                        : launch_pass_t<float, 13, 512>(st, a, d_subs, nsub, d_mats, phases, s);

@@ -1113,7 +1113,7 @@ int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_pl
         set_error("max_fused %d outside 1..%d", o.max_fused, SV_MAX_TARGETS);
         return SV_EINVAL;
     }
-    if (o.precision != SV_PREC_NATIVE && o.precision != SV_PREC_BF16X3) {
+    if (o.precision != SV_PREC_NATIVE && o.precision != SV_PREC_BF16X3 && o.precision != SV_PREC_BF16X6) {
         set_error("unknown precision mode %d", o.precision);
         return SV_EINVAL;
     }

@@ -14,13 +14,23 @@ sum (|A_ij| + |B_ij|)^2 <= 2 ||U||_F^2 = 2 d for a unitary U.
 
 * Three-product form on the matrix cores (pass blocks, dense blocks of k >= 3,
   d = max(16, 2^k)): P1 = A x, P2 = B z, P3 = fl(A + B) fl(x + z), each a
-  d-term FP32 dot product (error <= d u sum |a_k b_k|, any summation order),
-  Re = fl(P1 - P2), Im = fl(fl(P3 - P1) - P2).  With matrix entries carrying
+  d-term dot product accumulated in the matrix core; Re = fl(P1 - P2),
+  Im = fl(fl(P3 - P1) - P2) on the vector unit.  The matrix core's
+  accumulation is charged 2 u per addition (covering truncating as well as
+  round-to-nearest adders), the vector unit u.  With matrix entries carrying
   a relative error of at most m u (m = 1 for rounding to FP32; m = 8 once a
   pass rotates an entry by per-tile phases: FP32 sin/cos, two products and a
-  sum), to first order |dRe| <= (d + m + 1) u T_i and
-  |dIm| <= (2 d + 2 m + 5) u T_i, so
-      eps_3M(d) = 2 sqrt(d) u sqrt((d + 9)^2 + (2 d + 21)^2)     (m = 8).
+  sum), to first order |dRe| <= (2 d + m + 1) u T_i and
+  |dIm| <= (4 d + 2 m + 5) u T_i, so
+      eps_3M(d) = 2 sqrt(d) u sqrt((2 d + 9)^2 + (4 d + 21)^2)     (m = 8).
+* Split BF16 form (SV_PREC_BF16X6 pass blocks, d = 16): both operands split
+  exactly into three BF16 parts, each output row a sum of K = 2 d real
+  products [Ur, -Ui] [x; z] or [Ui, Ur] [x; z] taken as six part products
+  (the three dropped ones are below 2 u |a b| per product), accumulated in
+  six matrix-core steps of K + 1 terms smallest first, so the last step (the
+  products of the high parts) dominates: |dRe|, |dIm| <= (2 (2 d + 2) + 2 + m)
+  u T_i, and
+      eps_split(d) = 2 sqrt(d) u sqrt(2) (4 d + 14).
 * Four-product form on the vector units (one-qubit sweeps, small-tile
   blocks, per-group blocks): each real output is a 2d-term dot product plus
   the matrix rounding, |dRe|, |dIm| <= (2 d + 2) u T_i, so
@@ -58,7 +68,10 @@ def _d_of(rec):
 def _eps(kind, d, probabilistic, u):
     """Bound on ||d y||_2 / ||v||_2 for one block of one sweep."""
     if kind == "3m":
-        cr, ci = d + 9, 2 * d + 21
+        cr, ci = 2 * d + 9, 4 * d + 21
+        scale = 2 * math.sqrt(d) * u
+    elif kind == "split":
+        cr = ci = 4 * d + 14
         scale = 2 * math.sqrt(d) * u
     elif kind == "4m":
         cr = ci = 2 * d + 2
@@ -77,7 +90,7 @@ def sweep_terms(rec, n):
     name = rec["kind_name"]
     if name == "pass":
         blocks = int(round(rec["flops"] / (126.0 * 2.0 ** n)))
-        return "3m", 16, blocks
+        return ("split" if rec.get("precision") == 2 else "3m"), 16, blocks
     if name in ("dense_mfma",):
         return "3m", max(16, _d_of(rec)), 1
     if name in ("dense_tile", "dense_group"):

@@ -5,7 +5,8 @@ The circuit is the benchmark's: 20 layers of U3 on every qubit then CNOT or CZ
 (fair coin) on a random perfect matching, 840 gates, seed 2001.  The oracle
 runs it once (FP64, unfused, ~4 GiB of host memory) and its state serves every
 case.  For complex128 and complex64 and the plain, greedy (<= 5-qubit blocks)
-and LDS-pass plans, all 2^28 amplitudes copied back from the GPU are compared:
+and LDS-pass plans (complex64 passes also with split BF16 block products),
+all 2^28 amplitudes copied back from the GPU are compared:
 
 * max |d amp| <= 1e-12 (complex128) / 2e-5 (complex64);
 * ||d psi||_2 within the rounding bounds of ``tests/error_bounds.py``
@@ -36,7 +37,8 @@ pytestmark = pytest.mark.gpu
 N = 28
 TOL = {B.SV_C128: 1e-12, B.SV_C64: 2e-5}
 DNAME = {B.SV_C128: "c128", B.SV_C64: "c64"}
-MODES = {"passes": B.SV_PLAN_PASSES, "greedy": B.SV_PLAN_GREEDY, "plain": B.SV_PLAN_PLAIN}
+MODES = {"passes": (B.SV_PLAN_PASSES, B.SV_PREC_NATIVE), "passes_bf16x6": (B.SV_PLAN_PASSES, B.SV_PREC_BF16X6),
+         "greedy": (B.SV_PLAN_GREEDY, B.SV_PREC_NATIVE), "plain": (B.SV_PLAN_PLAIN, B.SV_PREC_NATIVE)}
 CHUNK = 1 << 24
 
 
@@ -103,15 +105,19 @@ def splitmix_uniforms(seed, count):
     return out
 
 
-@pytest.mark.parametrize("mode", list(MODES))
-@pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64], ids=DNAME.get)
+CASES = [(B.SV_C128, "passes"), (B.SV_C128, "greedy"), (B.SV_C128, "plain"),
+         (B.SV_C64, "passes"), (B.SV_C64, "passes_bf16x6"), (B.SV_C64, "greedy"), (B.SV_C64, "plain")]
+
+
+@pytest.mark.parametrize("dtype,mode", CASES, ids=[f"{DNAME[d]}-{m}" for d, m in CASES])
 def test_headline_circuit_full_state(headline, dtype, mode):
     gates, want = headline
     say(f"28q headline {DNAME[dtype]} mode={mode}: run")
     h = B.sv_create(N, dtype)
     try:
         B.sv_profile_enable(h, True)
-        st = B.sv_apply_circuit(h, gates, B.make_opts(MODES[mode], 5))
+        plan, prec = MODES[mode]
+        st = B.sv_apply_circuit(h, gates, B.make_opts(plan, 5, prec))
         recs = B.sv_profile_read(h, 1 << 12)
         B.sv_profile_enable(h, False)
         assert st["gates"] == 840 and len(recs) == st["sweeps"]
@@ -128,7 +134,7 @@ def test_headline_circuit_full_state(headline, dtype, mode):
         assert mx <= TOL[dtype]
         assert l2 <= prob <= det
         assert rel <= rel_bound
-        if mode != "passes":
+        if not mode.startswith("passes"):
             return
         check_readouts(h, dtype, got)
     finally:

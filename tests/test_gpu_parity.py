@@ -752,6 +752,41 @@ def test_pass_plan_gate_order_search_matches_oracle(dtype, kind, n):
             run_checked(s, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, orders), want)
 
 
+@pytest.mark.parametrize("kind", ["mixed", "phases", "controls", "terms", "layered"])
+@pytest.mark.parametrize("n", [13, 20, 23])
+def test_pass_plan_bf16x6_matches_oracle(kind, n):
+    """Complex64 passes with FP32-accurate split BF16 block products
+    (SV_PREC_BF16X6): every kind of pass block (plain, matrix variants,
+    per-tile phase terms), checked to the complex64 tolerance and the
+    split form's rounding bound; the records show the split kernel ran."""
+    if kind == "mixed":
+        gates = pass_circuit(n, 110 + n)
+    elif kind == "phases":
+        gates = phase_circuit(n, 111 + n, 4)
+    elif kind == "controls":
+        gates = control_circuit(n, 112 + n, 4)
+    elif kind == "terms":
+        gates = term_heavy_circuit(n, 6, 113 + n)
+    else:
+        gates = W.layered_u3_pairing(n, 10, W.circuit_seed(2, n), "cx_or_cz")
+    want = oracle.run(gates, n)
+    say(f"bf16x6 passes n={n} {kind}")
+    with State(n, B.SV_C64) as s:
+        _, recs = run_checked(s, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_BF16X6, 8), want,
+                              random_circuit=kind == "layered")
+    passes = [r for r in recs if r["kind_name"] == "pass"]
+    assert passes and all(r["precision"] == B.SV_PREC_BF16X6 for r in passes)
+
+
+def test_pass_plan_bf16x6_complex128_runs_native():
+    n = 14
+    gates = pass_circuit(n, 7)
+    want = oracle.run(gates, n)
+    with State(n, B.SV_C128) as s:
+        _, recs = run_checked(s, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_BF16X6, 8), want)
+    assert all(r["precision"] == B.SV_PREC_NATIVE for r in recs)
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_pass_plan_phase_gates_after_relayout(dtype):
     n = 18
