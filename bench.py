@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--mode", choices=["plain", "greedy", "learned", "passes"], default="passes")
     ap.add_argument("--pass-qubits", type=int, default=8, help="qubits per LDS pass (--mode passes)")
     ap.add_argument("--max-fused", type=int, default=5)
-    ap.add_argument("--precision", choices=["native", "bf16x3", "bf16x6"], default="native",
+    ap.add_argument("--precision", choices=["native", "bf16x3", "bf16x6"], default="bf16x6",
                     help="native: FP32 (complex64) / FP64 (complex128) arithmetic; bf16x3: three-term BF16 "
                          "split for complex64 5-6-qubit greedy blocks; bf16x6: FP32-accurate six-product split "
                          "BF16 for complex64 pass blocks")
@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of the state size (HBM counter calibration)")
     return ap.parse_args()
+
+
+def precision_of(args, B):
+    return {"native": B.SV_PREC_NATIVE, "bf16x3": B.SV_PREC_BF16X3, "bf16x6": B.SV_PREC_BF16X6}[args.precision]
 
 
 def log(*a):
@@ -94,7 +98,7 @@ def main():
     circ = B.Circuit(gates)
     mode = {"plain": B.SV_PLAN_PLAIN, "greedy": B.SV_PLAN_GREEDY, "learned": B.SV_PLAN_LEARNED,
             "passes": B.SV_PLAN_PASSES}[args.mode]
-    prec = {"native": B.SV_PREC_NATIVE, "bf16x3": B.SV_PREC_BF16X3, "bf16x6": B.SV_PREC_BF16X6}[args.precision]
+    prec = precision_of(args, B)
     opts = B.make_opts(mode, args.max_fused, prec, args.pass_qubits if args.mode == "passes" else 0)
     marg_q = list(range(n - 10, n))
     terms = W.hea_z_terms(n)[: 2 * 16]
@@ -378,7 +382,7 @@ def bench_su4(args):
     from paper_2511_14664_amd import _binding as B
 
     n = 30
-    prec = B.SV_PREC_BF16X3 if args.precision == "bf16x3" else B.SV_PREC_NATIVE
+    prec = precision_of(args, B)
     gates = W.u3_su4_layers(n, 40, W.circuit_seed(5, 1))
     circ = B.Circuit(gates)
     model = train_cost_model(B, W)
@@ -452,7 +456,7 @@ def bench_paper33(args):
     torch.cuda.empty_cache()
     h = B.sv_create(n, B.SV_C64)
     res = {}
-    plans = (("passes", B.make_opts(B.SV_PLAN_PASSES, args.max_fused, B.SV_PREC_NATIVE, args.pass_qubits)),
+    plans = (("passes", B.make_opts(B.SV_PLAN_PASSES, args.max_fused, precision_of(args, B), args.pass_qubits)),
              ("greedy", B.make_opts(B.SV_PLAN_GREEDY, args.max_fused)))
     for name, opts in plans:
         def run():
@@ -519,7 +523,7 @@ def bench_share(args):
     if seg:
         segs.append((B.Circuit(seg), None))
     mode = {"plain": B.SV_PLAN_PLAIN, "passes": B.SV_PLAN_PASSES}.get(args.mode, B.SV_PLAN_GREEDY)
-    opts = B.make_opts(mode, args.max_fused, B.SV_PREC_NATIVE, args.pass_qubits if args.mode == "passes" else 0)
+    opts = B.make_opts(mode, args.max_fused, precision_of(args, B), args.pass_qubits if args.mode == "passes" else 0)
     torch.cuda.empty_cache()
     h = B.sv_create(n, dtype)
     ngates = W.gate_count(ops)

@@ -165,3 +165,23 @@ def check_readouts(h, dtype, got):
     after = B.sv_copy_to_host(h, N, dtype)
     assert np.array_equal(after.view(np.uint8), got.view(np.uint8))
     say("  read-outs and exchange agree")
+
+
+def test_headline_split_products_are_fp32_accurate(headline):
+    """The split-BF16 pass path is at least as accurate as complex64 applied
+    one gate at a time in FP32 on the vector units: its ||d psi||_2 and its
+    largest relative error do not exceed the plain path's."""
+    gates, want = headline
+    err = {}
+    for mode in ("plain", "passes_bf16x6"):
+        plan, prec = MODES[mode]
+        h = B.sv_create(N, B.SV_C64)
+        try:
+            B.sv_apply_circuit(h, gates, B.make_opts(plan, 5, prec))
+            err[mode] = state_errors(B.sv_copy_to_host(h, N, B.SV_C64), want)
+        finally:
+            B.sv_destroy(h)
+    say(f"c64 plain: ||d psi||_2 {err['plain'][1]:.3e}, rel {err['plain'][2]:.3e}; "
+        f"split passes: ||d psi||_2 {err['passes_bf16x6'][1]:.3e}, rel {err['passes_bf16x6'][2]:.3e}")
+    assert err["passes_bf16x6"][1] <= err["plain"][1]
+    assert err["passes_bf16x6"][2] <= err["plain"][2]
