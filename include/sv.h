@@ -218,6 +218,24 @@ int sv_probabilities(sv_handle h, const int *qubits, int m, double *out);
  * Z-only strings are evaluated together in one read sweep.  Synchronises. */
 int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *out);
 
+/* Largest nterms of sv_expect_pauli_noalloc. */
+#define SV_NOALLOC_MAX_TERMS 256
+
+/* sv_expect_pauli for callers that cannot allocate memory during the call
+ * (serving loops that evaluate expectation values of one state again and
+ * again, code that must not call hipMalloc): the same kernels and the same
+ * results, but the partial sums live in a fixed device array of the library
+ * (1 MiB + 4 KiB on every GPU it runs on, held until the process ends) and
+ * the results come back through a host copy straight into `out`: no
+ * hipMalloc, hipFree, pinned or heap allocation on the success path.
+ * nterms: 0..SV_NOALLOC_MAX_TERMS, SV_EINVAL beyond (and for the argument
+ * errors of sv_expect_pauli).  All calls on one GPU share that array, so
+ * calls that overlap in time on one GPU (other threads, other handles on
+ * the same device) race and must be serialised by the caller; one thread's
+ * calls cannot overlap, since each synchronises before returning.  No slot
+ * of the array has to start at zero: each call writes every slot it reads. */
+int sv_expect_pauli_noalloc(sv_handle h, const char *const *terms, int nterms, double *out);
+
 /* Draw `shots` outcomes (paper Sec. 2.1 "Measurement and Sampling"): for
  * uniform u_s in [0, 1) (caller-drawn), the outcome is the smallest logical
  * basis index x with CDF(x) > u_s * norm, CDF accumulated in FP64 over

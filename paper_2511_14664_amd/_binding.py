@@ -20,6 +20,7 @@ SV_C64, SV_C128 = 0, 1
 SV_PLAN_PLAIN, SV_PLAN_GREEDY, SV_PLAN_LEARNED, SV_PLAN_PASSES = 0, 1, 2, 3
 SV_PREC_NATIVE, SV_PREC_BF16X3, SV_PREC_BF16X6 = 0, 1, 2
 SV_MAX_TARGETS, SV_MAX_CONTROLS = 6, 8
+SV_NOALLOC_MAX_TERMS = 256
 
 GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
              "p": 9, "u3": 10, "matrix": 11}
@@ -82,6 +83,7 @@ def _load():
         "sv_qubit_map": ([P, P], I),
         "sv_probabilities": ([P, P, I, P], I),
         "sv_expect_pauli": ([P, ctypes.POINTER(ctypes.c_char_p), I, P], I),
+        "sv_expect_pauli_noalloc": ([P, ctypes.POINTER(ctypes.c_char_p), I, P], I),
         "sv_sample": ([P, P, I, P], I),
         "sv_sample_seeded": ([P, I, U64, P], I),
         "sv_uniforms": ([U64, U64, I, P], I),
@@ -232,6 +234,14 @@ def sv_expect_pauli(h: int, terms: Sequence[str]) -> np.ndarray:
     arr = (ctypes.c_char_p * max(1, len(terms)))(*[t.encode() for t in terms])
     out = np.empty(max(1, len(terms)), dtype=np.float64)
     _check(_lib.sv_expect_pauli(ctypes.c_void_p(h), arr, len(terms), out.ctypes.data), "sv_expect_pauli")
+    return out[:len(terms)]
+
+
+def sv_expect_pauli_noalloc(h: int, terms: Sequence[str]) -> np.ndarray:
+    arr = (ctypes.c_char_p * max(1, len(terms)))(*[t.encode() for t in terms])
+    out = np.empty(max(1, len(terms)), dtype=np.float64)
+    _check(_lib.sv_expect_pauli_noalloc(ctypes.c_void_p(h), arr, len(terms), out.ctypes.data),
+           "sv_expect_pauli_noalloc")
     return out[:len(terms)]
 
 

@@ -1325,6 +1325,61 @@ int sv_probabilities(sv_handle h, const int *qubits, int m, double *out)
     return SV_OK;
 }
 
+// Expectation values of parsed Pauli strings (x mask, y|z mask, number of
+// Y) on the handle's stream: d_part holds the launches' partial sums
+// (expect_scratch_doubles), d_res 2 * nterms result doubles, h_res as many
+// host doubles (pinned or not), order[nterms] an index buffer.  Device
+// results: the Z-only strings first (one double each, in order of
+// appearance), then (Re, Im) of each general string.  Every launch is
+// queued, then one copy and one wait.
+static int expect_core(sv_state *h, int nterms, const uint64_t *xs, const uint64_t *yzs, const int *nys,
+                       double *d_part, double *d_res, double *h_res, int *order, double *out)
+{
+    int nz = 0;
+    for (int t = 0; t < nterms; ++t)
+        if (xs[t] == 0)
+            order[nz++] = t;
+    int nxy = 0;
+    for (int t = 0; t < nterms; ++t)
+        if (xs[t] != 0)
+            order[nz + nxy++] = t;
+    constexpr int kZ = 64;
+    const int zb = std::min(expect_z_batch(), kZ);
+    for (int s = 0; s < nz; s += zb) {
+        const int nb = std::min(zb, nz - s);
+        uint64_t z[kZ];
+        for (int j = 0; j < nb; ++j)
+            z[j] = yzs[order[s + j]];
+        hipError_t e = launch_expect_z(h->d_state, h->n, h->dtype, z, nb, d_part, d_res + s, h->stream);
+        if (e != hipSuccess) {
+            set_error("Z expectation launch failed: %s", hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+    }
+    for (int q = 0; q < nxy; ++q) {
+        const int t = order[nz + q];
+        hipError_t e = launch_expect_xy(h->d_state, h->n, h->dtype, xs[t], yzs[t], d_part, d_res + nz + 2 * q,
+                                        h->stream);
+        if (e != hipSuccess) {
+            set_error("Pauli expectation launch failed: %s", hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+    }
+    const size_t nres = size_t(nz) + 2 * size_t(nxy);
+    HIP_TRY(hipMemcpyAsync(h_res, d_res, nres * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int j = 0; j < nz; ++j)
+        out[order[j]] = h_res[j];
+    static const cd ipow[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    for (int q = 0; q < nxy; ++q) {
+        const int t = order[nz + q];
+        const cd S(h_res[nz + 2 * q], h_res[nz + 2 * q + 1]);
+        // multiply by i^(number of Y)
+        out[t] = (ipow[nys[t] & 3] * S).real();
+    }
+    return SV_OK;
+}
+
 int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *out)
 {
     clear_error();
@@ -1336,7 +1391,7 @@ int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *o
         return SV_EINVAL;
     }
     std::vector<uint64_t> xs(nterms), yzs(nterms);
-    std::vector<int> nys(nterms);
+    std::vector<int> nys(nterms), order(nterms);
     for (int t = 0; t < nterms; ++t) {
         rc = parse_pauli(h, terms[t], xs[t], yzs[t], nys[t]);
         if (rc != SV_OK)
@@ -1353,49 +1408,43 @@ int sv_expect_pauli(sv_handle h, const char *const *terms, int nterms, double *o
     rc = ensure_pinned(h, 2 * uint64_t(nterms) * sizeof(double));
     if (rc != SV_OK)
         return rc;
-    double *d_res = h->d_scratch + part;
-    // Device results: the Z-only strings' values first (one double each, in
-    // order of appearance), then (Re, Im) of each general string.  Every
-    // launch is queued, then one copy and one wait.
-    std::vector<int> zterms, xyterms;
-    for (int t = 0; t < nterms; ++t)
-        (xs[t] == 0 ? zterms : xyterms).push_back(t);
-    const int zb = expect_z_batch();
-    for (size_t s = 0; s < zterms.size(); s += size_t(zb)) {
-        const int nb = int(std::min<size_t>(size_t(zb), zterms.size() - s));
-        std::vector<uint64_t> z(static_cast<size_t>(nb));
-        for (int j = 0; j < nb; ++j)
-            z[j] = yzs[zterms[s + j]];
-        hipError_t e = launch_expect_z(h->d_state, h->n, h->dtype, z.data(), nb, h->d_scratch, d_res + s, h->stream);
-        if (e != hipSuccess) {
-            set_error("Z expectation launch failed: %s", hipGetErrorString(e));
-            return SV_EDEVICE;
-        }
+    return expect_core(h, nterms, xs.data(), yzs.data(), nys.data(), h->d_scratch, h->d_scratch + part,
+                       static_cast<double *>(h->h_pinned), order.data(), out);
+}
+
+int sv_expect_pauli_noalloc(sv_handle h, const char *const *terms, int nterms, double *out)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (nterms < 0 || nterms > SV_NOALLOC_MAX_TERMS || (nterms > 0 && (!terms || !out))) {
+        set_error("bad term list (nterms %d, at most %d without allocation)", nterms, SV_NOALLOC_MAX_TERMS);
+        return SV_EINVAL;
     }
-    const size_t nz = zterms.size();
-    for (size_t q = 0; q < xyterms.size(); ++q) {
-        const int t = xyterms[q];
-        hipError_t e = launch_expect_xy(h->d_state, h->n, h->dtype, xs[t], yzs[t], h->d_scratch, d_res + nz + 2 * q,
-                                        h->stream);
-        if (e != hipSuccess) {
-            set_error("Pauli expectation launch failed: %s", hipGetErrorString(e));
-            return SV_EDEVICE;
-        }
+    // fixed-size host workspace: nothing is allocated on the success path
+    uint64_t xs[SV_NOALLOC_MAX_TERMS], yzs[SV_NOALLOC_MAX_TERMS];
+    int nys[SV_NOALLOC_MAX_TERMS], order[SV_NOALLOC_MAX_TERMS];
+    double h_res[2 * SV_NOALLOC_MAX_TERMS];
+    for (int t = 0; t < nterms; ++t) {
+        rc = parse_pauli(h, terms[t], xs[t], yzs[t], nys[t]);
+        if (rc != SV_OK)
+            return rc;
     }
-    const size_t nres = nz + 2 * xyterms.size();
-    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_res, nres * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    const double *pv = static_cast<const double *>(h->h_pinned);
-    for (size_t j = 0; j < nz; ++j)
-        out[zterms[j]] = pv[j];
-    static const cd ipow[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
-    for (size_t q = 0; q < xyterms.size(); ++q) {
-        const int t = xyterms[q];
-        const cd S(pv[nz + 2 * q], pv[nz + 2 * q + 1]);
-        // multiply by i^(number of Y)
-        out[t] = (ipow[nys[t] & 3] * S).real();
+    if (nterms == 0)
+        return SV_OK;
+    DeviceGuard dg(h->device);
+    double *d_scr = nullptr;
+    uint64_t have = 0;
+    rc = noalloc_scratch(h->device, &d_scr, &have);
+    if (rc != SV_OK)
+        return rc;
+    const uint64_t part = expect_scratch_doubles(h->n);
+    if (part + 2 * uint64_t(nterms) > have) {
+        set_error("fixed scratch of %llu doubles is too small", (unsigned long long)have);
+        return SV_EUNSUPPORTED;
     }
-    return SV_OK;
+    return expect_core(h, nterms, xs, yzs, nys, d_scr, d_scr + part, h_res, order, out);
 }
 
 int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)

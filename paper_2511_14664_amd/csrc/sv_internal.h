@@ -215,6 +215,9 @@ int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *
 hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, const void *d_subs, int nsub,
                        const void *d_mats, bool phases, bool split, hipStream_t s);
 
+// Device address and size (in doubles) of the fixed scratch array of the
+// allocation-free read-out on `device`, which must be the current device.
+int noalloc_scratch(int device, double **ptr, uint64_t *doubles);
 // Z strings per launch_expect_z call.
 int expect_z_batch();
 hipError_t launch_expect_z(const void *st, int n, int dtype, const uint64_t *zmasks, int nt,

@@ -4,6 +4,7 @@
 // amplitude precision, with a fixed reduction order (no atomics), so results
 // are reproducible run to run.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "sv_internal.h"
@@ -853,6 +854,48 @@ uint32_t exp_grid(int n)
     return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(kExpGrid, need)));
 }
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free expectation entry point
+// (sv_expect_pauli_noalloc): the per-workgroup partial sums of one batch of
+// strings, then two result doubles per string.  Every device the library
+// runs on holds its own copy until the process ends.  In host code the
+// name `scratch` is a host-side stand-in, not a device address: the address
+// comes from hipGetSymbolAddress, looked up once per device with that device
+// current, and only that address is handed to kernels and copies.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kNoAllocDoubles = uint64_t(kMaxZ) * kExpGrid + 2 * uint64_t(SV_NOALLOC_MAX_TERMS);
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+int noalloc_scratch(int device, double **ptr, uint64_t *doubles)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("device %d outside 0..%d", device, kMaxDevices - 1);
+        return SV_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[device] == nullptr) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess || cur != device) {
+            set_error("scratch lookup needs device %d current (current %d)", device, cur);
+            return SV_EDEVICE;
+        }
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return SV_EDEVICE;
+        }
+        addr[device] = static_cast<double *>(p);
+    }
+    *ptr = addr[device];
+    *doubles = kNoAllocDoubles;
+    return SV_OK;
+}
 
 uint64_t expect_scratch_doubles(int n)
 {
