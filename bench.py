@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -341,40 +343,59 @@ def counter_traffic(dom_key, n, dtype, args):
     return None
 
 
+def training_sweeps(B, W, n, dtype, gates, k_max=6):
+    """Sweep timings the library records itself (HIP events) for one circuit:
+    greedy plans of widths 1..k_max, the plain plan, and LDS pass plans of 5..8
+    pass qubits with and without the gate-order search, in each block
+    arithmetic and tile width the pass kernels have.  Returns feature rows and
+    ln(ms per GB) targets."""
+    circ = B.Circuit(gates)
+    h = B.sv_create(n, dtype)
+    try:
+        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_GREEDY, 3))  # warm-up: code objects loaded
+        B.sv_profile_read(h)
+        B.sv_profile_enable(h, True)
+        runs = [B.make_opts(B.SV_PLAN_GREEDY, k) for k in range(1, k_max + 1)] + [B.make_opts(B.SV_PLAN_PLAIN)]
+        T0 = 12 if dtype == B.SV_C64 else 11
+        precs = (B.SV_PREC_NATIVE, B.SV_PREC_BF16X6) if dtype == B.SV_C64 else (B.SV_PREC_NATIVE,)
+        for pq in (5, 6, 7, 8):
+            for orders in (-1, 8):
+                for prec in precs:
+                    tiles = (T0,) if prec == B.SV_PREC_BF16X6 or n < T0 + 7 else (T0, T0 + 1)
+                    for tile in tiles:
+                        runs.append(B.make_opts(B.SV_PLAN_PASSES, 5, prec, pq, orders, tile))
+        X, y = [], []
+        for o in runs:
+            B.sv_reset(h)
+            B.sv_apply_circuit(h, circ, o)
+            recs, cnt = B.sv_profile_read_raw(h, 1 << 14)
+            X.append(B.sv_sweep_features(n, dtype, recs, cnt))
+            y.append(B.sv_sweep_targets(recs, cnt))
+        return np.concatenate(X), np.concatenate(y)
+    finally:
+        B.sv_destroy(h)
+
+
 def train_cost_model(B, W):
     """Cost model trained on sweep timings the library records on the
     12-qubit complex128 and 28-qubit complex64/complex128 layered workloads
-    (greedy widths 1..6, plain and LDS passes); untimed set-up."""
-    import numpy as np
-
+    (greedy widths 1..6, plain, and pass plans of 5..8 qubits in every block
+    arithmetic and tile width); untimed set-up."""
     Xs, ys = [], []
     for n, dt, ent, cfg in ((12, B.SV_C128, "cx", 1), (28, B.SV_C64, "cx_or_cz", 2), (28, B.SV_C128, "cx_or_cz", 2)):
-        circ = B.Circuit(W.layered_u3_pairing(n, 20, W.circuit_seed(cfg, 1), ent))
-        h = B.sv_create(n, dt)
-        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_GREEDY, 3))
-        B.sv_profile_read(h)
-        B.sv_profile_enable(h, True)
-        for k in range(1, 7):
-            B.sv_reset(h)
-            B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_GREEDY, k))
-        B.sv_reset(h)
-        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PLAIN))
-        B.sv_reset(h)
-        B.sv_apply_circuit(h, circ, B.make_opts(B.SV_PLAN_PASSES))
-        recs, cnt = B.sv_profile_read_raw(h)
-        Xs.append(B.sv_sweep_features(n, dt, recs, cnt))
-        ys.append(B.sv_sweep_targets(recs, cnt))
-        B.sv_destroy(h)
+        X, y = training_sweeps(B, W, n, dt, W.layered_u3_pairing(n, 20, W.circuit_seed(cfg, 1), ent))
+        Xs.append(X)
+        ys.append(y)
     m = B.sv_costmodel_create(16)
-    loss = B.sv_costmodel_train(m, np.concatenate(Xs), np.concatenate(ys), 3000, 3e-3)
+    loss = B.sv_costmodel_train(m, np.concatenate(Xs), np.concatenate(ys), 4000, 3e-3)
     log(f"cost model trained on {sum(len(y) for y in ys)} sweeps, loss {loss:.4f}")
     return m
 
 
 def bench_su4(args):
     """30-qubit complex64 U3 + Haar SU(4) circuit (depth 40, 1800 gates): wall
-    time per circuit of the greedy plan and of the learned plan at equal
-    accuracy, and the cost model's prediction error."""
+    time per circuit of the greedy plan, the heuristic LDS pass plan and the
+    learned plan at equal accuracy, and the ranking the model predicts."""
     import numpy as np
     import torch
 
@@ -389,6 +410,7 @@ def bench_su4(args):
     k, pred = B.sv_costmodel_rank(model, n, B.SV_C64, circ, 6)
     res = {}
     for name, opts in (("greedy", B.make_opts(B.SV_PLAN_GREEDY, args.max_fused, prec)),
+                       ("passes", B.make_opts(B.SV_PLAN_PASSES, args.max_fused, prec)),
                        ("learned", B.make_opts(B.SV_PLAN_LEARNED, 6, prec))):
         h = B.sv_create(n, B.SV_C64)
         B.sv_set_costmodel(h, model)
@@ -412,8 +434,10 @@ def bench_su4(args):
            "predicted_ms_by_plan": {**{f"greedy_k{w}": round(float(pred[w - 1]), 1) for w in range(1, 7)},
                                     "passes": round(float(pred[6]), 1)},
            "greedy_ms": res["greedy"]["ms_per_circuit"], "greedy_sweeps": res["greedy"]["sweeps"],
+           "passes_ms": res["passes"]["ms_per_circuit"], "passes_sweeps": res["passes"]["sweeps"],
            "learned_ms": res["learned"]["ms_per_circuit"], "learned_sweeps": res["learned"]["sweeps"],
-           "gain": round(res["greedy"]["ms_per_circuit"] / res["learned"]["ms_per_circuit"], 3),
+           "gain_vs_greedy": round(res["greedy"]["ms_per_circuit"] / res["learned"]["ms_per_circuit"], 3),
+           "gain_vs_passes": round(res["passes"]["ms_per_circuit"] / res["learned"]["ms_per_circuit"], 3),
            "max_abs_diff_first_4096_amps": float(np.max(np.abs(res["greedy"]["amp"] - res["learned"]["amp"])))}
     print(json.dumps(out), flush=True)
 

@@ -95,9 +95,13 @@ typedef struct sv_gate {
 typedef enum sv_plan_mode {
     SV_PLAN_PLAIN = 0,    /* one sweep per gate */
     SV_PLAN_GREEDY = 1,   /* greedy dependency-aware fusion into <= max_fused-qubit blocks */
-    SV_PLAN_LEARNED = 2,  /* candidate plans (greedy widths 1..max_fused and the pass plan)
-                             ranked by the attached cost model; falls back to
-                             SV_PLAN_GREEDY without a usable model */
+    SV_PLAN_LEARNED = 2,  /* candidate plans ranked by the attached cost model: greedy widths
+                             1..max_fused, and LDS pass plans (as SV_PLAN_PASSES) of 6, 7 and 8
+                             pass qubits over several gate orders, each kernel pass with the
+                             tile width the model predicts fastest.  The winner is kept on the
+                             handle per circuit structure (and model version), so a circuit
+                             applied again is not ranked again.  Falls back to SV_PLAN_GREEDY
+                             without a usable model */
     SV_PLAN_PASSES = 3    /* greedy dependency-aware grouping into passes of <= pass_qubits
                              qubits; a pass moves the state through LDS once and applies
                              its gates there as a sequence of fused 4-qubit blocks on the
@@ -130,6 +134,9 @@ typedef struct sv_plan_opts {
                              its reverse, and for re-planning the whole circuit; the cheapest result in the
                              pass cost model is kept.  0: by state size (16 from 32 qubits, else none), -1:
                              none, 1..64; else must be 0 */
+    int32_t pass_tile;    /* SV_PLAN_PASSES: log2 amplitudes of every kernel pass's LDS tile: 0 = by the
+                             pass's blocks; else the smallest tile (12 complex64, 11 complex128) or twice
+                             it (complex128, and complex64 with SV_PREC_NATIVE); else must be 0 */
 } sv_plan_opts;
 
 /* Counters filled by sv_apply_circuit / sv_apply_plan (may be NULL). */
@@ -298,6 +305,11 @@ typedef struct sv_sweep_record {
     float ms;                /* HIP-event duration on the handle's stream */
     int32_t precision;       /* sv_precision of the sweep's arithmetic */
     double mfma_flops;       /* real flops a pass executes on the matrix cores (0: other sweeps) */
+    int32_t blocks;          /* SV_SWEEP_PASS: fused blocks applied in LDS (0: other sweeps) */
+    int32_t term_blocks;     /* SV_SWEEP_PASS: blocks carrying per-tile phase terms */
+    int32_t variant_blocks;  /* SV_SWEEP_PASS: blocks staged as per-tile matrix variants */
+    int32_t tile_log;        /* SV_SWEEP_PASS: log2 amplitudes of the LDS tile */
+    uint64_t tile_mask;      /* SV_SWEEP_PASS: physical index bits of the tile */
 } sv_sweep_record;
 
 /* enable != 0: bracket every subsequent sweep of this handle with a pair of
@@ -365,12 +377,12 @@ int sv_batch_destroy(sv_batch_handle b);
  * W1 [H x F row-major], b1 [H], W2 [H x H], b2 [H], w3 [H], b3 [1].
  * Training (full-batch Adam on the mean squared error) and gradients run in
  * FP32 on the GPU; prediction runs in FP16 with FP32 accumulation. */
-#define SV_CM_FEATURES 10
+#define SV_CM_FEATURES 16
 #define SV_CM_HIDDEN 64
 
 typedef struct sv_costmodel *sv_costmodel_handle;
 
-/* Number of parameters (4929). */
+/* Number of parameters (5313). */
 int sv_costmodel_num_params(int *count);
 /* New model with He-uniform weights drawn from `seed`, zero biases. */
 int sv_costmodel_create(uint64_t seed, sv_costmodel_handle *out);
@@ -388,7 +400,12 @@ int sv_costmodel_predict(sv_costmodel_handle m, const float *x, int n, float *ou
 int sv_costmodel_destroy(sv_costmodel_handle m);
 
 /* Feature rows (count x SV_CM_FEATURES) of recorded sweeps on an n-qubit
- * state of dtype. */
+ * state of dtype: the sweep's width (targets or pass qubits), controls,
+ * gates, lowest and highest target bit, tile bits among the top 8 index
+ * bits, dtype, whether it is a pass, its kind, algorithmic bytes, blocks,
+ * phase-term and variant blocks, tile width above the smallest, block
+ * arithmetic, and the contiguous low tile bits (the length of the runs a
+ * pass tile reads), each scaled to about [0, 1]. */
 int sv_sweep_features(int n, int dtype, const sv_sweep_record *recs, int count, float *out);
 
 /* Training targets of recorded sweeps: out[i] = ln(ms_i / (bytes_i / 1e9)). */
@@ -397,12 +414,13 @@ int sv_sweep_targets(const sv_sweep_record *recs, int count, float *out);
 /* Attach a model to a state (NULL detaches); SV_PLAN_LEARNED uses it. */
 int sv_set_costmodel(sv_handle h, sv_costmodel_handle m);
 
-/* Rank the candidate plans of a gate list by predicted run time: greedy with
- * widest block 1..max_fused, and the LDS pass plan (SV_PLAN_PASSES with 8-qubit
- * passes).  predicted_ms (max_fused + 1 entries) receives the prediction for
- * width k at [k-1] and for the pass plan at [max_fused]; *chosen is the width
- * with the smallest prediction, 0 for the pass plan, or max_fused if a
- * prediction is not finite. */
+/* Rank the candidate plans of a gate list by predicted run time on a fresh
+ * n-qubit state of dtype (complex64 passes in SV_PREC_BF16X6 arithmetic):
+ * greedy with widest block 1..max_fused, and the best of the LDS pass plans
+ * SV_PLAN_LEARNED considers.  predicted_ms (max_fused + 1 entries) receives
+ * the prediction for width k at [k-1] and for the pass plan at [max_fused];
+ * *chosen is the width with the smallest prediction, 0 for the pass plan, or
+ * max_fused if a prediction is not finite. */
 int sv_costmodel_rank(sv_costmodel_handle m, int n, int dtype, const sv_gate *gates, int ngates, int max_fused,
                       int *chosen, float *predicted_ms);
 

@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import numpy as np
 
-F = 10
+F = 16
 H = 64
 
 

@@ -46,7 +46,8 @@ class sv_gate(ctypes.Structure):
 
 class sv_plan_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_fused", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("pass_qubits", ctypes.c_int32), ("pass_orders", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("pass_qubits", ctypes.c_int32), ("pass_orders", ctypes.c_int32),
+                ("pass_tile", ctypes.c_int32)]
 
 
 class sv_run_stats(ctypes.Structure):
@@ -149,8 +150,8 @@ class Circuit:
 
 
 def make_opts(mode: int = SV_PLAN_PLAIN, max_fused: int = 5, precision: int = SV_PREC_NATIVE,
-              pass_qubits: int = 0, pass_orders: int = 0) -> sv_plan_opts:
-    return sv_plan_opts(mode, max_fused, precision, pass_qubits, pass_orders)
+              pass_qubits: int = 0, pass_orders: int = 0, pass_tile: int = 0) -> sv_plan_opts:
+    return sv_plan_opts(mode, max_fused, precision, pass_qubits, pass_orders, pass_tile)
 
 
 def _as_circuit(gates) -> Circuit:
@@ -333,7 +334,9 @@ class sv_sweep_record(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("c", ctypes.c_int32),
                 ("lowest_target", ctypes.c_int32), ("highest_target", ctypes.c_int32),
                 ("num_gates", ctypes.c_int32), ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
-                ("ms", ctypes.c_float), ("precision", ctypes.c_int32), ("mfma_flops", ctypes.c_double)]
+                ("ms", ctypes.c_float), ("precision", ctypes.c_int32), ("mfma_flops", ctypes.c_double),
+                ("blocks", ctypes.c_int32), ("term_blocks", ctypes.c_int32), ("variant_blocks", ctypes.c_int32),
+                ("tile_log", ctypes.c_int32), ("tile_mask", ctypes.c_uint64)]
 
 
 SWEEP_KIND = {0: "gate1", 1: "diag1", 2: "dense_tile", 3: "dense_mfma", 4: "dense_group", 5: "bitswap",
@@ -466,7 +469,7 @@ def sv_profile_read_raw(h: int, max_records: int = 1 << 16):
 # ---------------------------------------------------------------------------
 # Learned cost model
 # ---------------------------------------------------------------------------
-SV_CM_FEATURES, SV_CM_HIDDEN = 10, 64
+SV_CM_FEATURES, SV_CM_HIDDEN = 16, 64
 _F32P = ctypes.POINTER(ctypes.c_float)
 for _name, _args in {
     "sv_costmodel_num_params": [ctypes.POINTER(ctypes.c_int)],

@@ -48,6 +48,15 @@ using namespace sv;
         }                                                                                \
     } while (0)
 
+// A plan kept on a handle for a circuit structure: the key lists the
+// options, the state's qubit map and, per gate, its width, controls, qubits,
+// diagonality and whether it is a pure phase (everything the planners read).
+struct PlanCacheEntry {
+    std::vector<uint64_t> key;
+    int width = 0;                     // SV_PLAN_LEARNED: greedy width chosen, 0 = the pass plan
+    std::vector<sv::PassGroup> plan;   // pass plan on the gate list with diagonal pairs pre-fused
+};
+
 struct sv_state {
     int n = 0;
     int dtype = 0;
@@ -71,6 +80,8 @@ struct sv_state {
     uint64_t h_arena_bytes = 0;
     hipEvent_t arena_done = nullptr;
     bool arena_pending = false;
+    // plans of recent circuit structures, most recent first
+    std::vector<PlanCacheEntry> plan_cache;
     // sweep timing
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -465,17 +476,10 @@ int run_groups(sv_state *h, const std::vector<Block> &gates, const std::vector<G
 // most four qubits (pass kernel; phase gates reaching outside the tile ride on
 // them as per-tile phases) or, when some gate is wider or the state is below
 // the pass tile, into ordinary <= max_fused sweeps.
-struct PassWork {
-    bool kernel = false;
-    uint64_t qmask = 0;      // logical tile qubits of the pass
-    uint64_t omask = 0;      // logical qubits only phase gates touch (outside the tile)
-    std::vector<Group> subs; // members index the circuit's gate list
-    std::vector<std::vector<int>> front, back;
-    std::vector<uint64_t> vq;  // per block: outer qubits whose values select its matrix variant
+struct PassWork : PassGroup {
     uint64_t off = 0;        // arena range of the pass: [off, off + bytes)
     uint64_t bytes = 0;
     uint64_t nterm_max = 0;  // bound on the pass's phase terms
-    int ngates = 0;
     bool split = false;      // complex64 blocks as split BF16 products (SV_PREC_BF16X6)
 };
 
@@ -579,7 +583,14 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
             avoid |= uint64_t(1) << h->qmap[q];
     int tb[16];
     const size_t nsub = w.subs.size();
-    int T = pass_tile_bits(h->n, pass_tile_log_for(h->n, h->dtype, int(nsub)), phys, avoid, tb);
+    // the planner's tile width if it set one (the split kernel has the
+    // smallest only), else by the pass's blocks; the smallest if the pass
+    // does not fit the wider tile
+    int T = -1;
+    if (w.tile_log > 0 && !(w.split && w.tile_log != pass_tile_log(h->dtype)))
+        T = pass_tile_bits(h->n, w.tile_log, phys, avoid, tb);
+    if (T < 0)
+        T = pass_tile_bits(h->n, pass_tile_log_for(h->n, h->dtype, int(nsub)), phys, avoid, tb);
     if (T < 0)
         T = pass_tile_bits(h->n, pass_tile_log(h->dtype), phys, avoid, tb);
     if (T < 0) {
@@ -782,6 +793,14 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     pr.rec.flops = double(nsub) * (8.0 * 16.0 - 2.0) * std::ldexp(1.0, h->n);
     pr.rec.mfma_flops = double(nsub) * (w.split ? 768.0 : 96.0) * std::ldexp(1.0, h->n);
     pr.rec.precision = w.split ? SV_PREC_BF16X6 : SV_PREC_NATIVE;
+    pr.rec.blocks = int(nsub);
+    for (size_t i = 0; i < nsub; ++i) {
+        pr.rec.term_blocks += (!w.front[i].empty() || !w.back[i].empty()) ? 1 : 0;
+        pr.rec.variant_blocks += w.vq[i] != 0 ? 1 : 0;
+    }
+    pr.rec.tile_log = T;
+    for (int b = 0; b < T; ++b)
+        pr.rec.tile_mask |= uint64_t(1) << tb[b];
     int rc = prof_begin(h, pr);
     if (rc != SV_OK)
         return rc;
@@ -808,26 +827,18 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
 
 // Run a circuit as LDS passes (SV_PLAN_PASSES), fused, uploaded and launched
 // in chunks of 1, 2, 4, ... passes as in run_groups.
-int run_passes(sv_state *h, const std::vector<Block> &circuit, int pass_qubits, int max_fused, int precision,
-               int pass_orders, int ngates, sv_run_stats *st)
+// Run a pass plan (plan_passes or the learned planner) on the gate list it
+// was made for (the circuit with diagonal pairs pre-fused).
+int run_pass_plan(sv_state *h, const std::vector<Block> &gates, const std::vector<PassGroup> &pg, int precision,
+                  int ngates, sv_run_stats *st)
 {
-    const std::vector<Block> gates = prefuse_diagonal_pairs(circuit);
     const uint64_t S = amp_bytes(h->dtype);
     const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
-    const std::vector<PassGroup> pg =
-        plan_passes(gates, pass_qubits, max_fused, h->n, pass_tile_log(h->dtype), h->qmap, pass_orders);
     std::vector<PassWork> work(pg.size());
     uint64_t total = 0;
     for (size_t i = 0; i < pg.size(); ++i) {
         PassWork &w = work[i];
-        w.kernel = pg[i].kernel;
-        w.qmask = pg[i].qmask;
-        w.omask = pg[i].omask;
-        w.subs = pg[i].subs;
-        w.front = pg[i].front;
-        w.back = pg[i].back;
-        w.vq = pg[i].vq;
-        w.ngates = pg[i].ngates;
+        static_cast<PassGroup &>(w) = pg[i];
         w.split = precision == SV_PREC_BF16X6 && h->dtype == SV_C64;
         w.off = total;
         if (w.kernel) {
@@ -1164,6 +1175,75 @@ int sv_apply_gate(sv_handle h, const double *U, const int *targets, int k, const
     return run_blocks(h, blocks, SV_PREC_NATIVE, 1, nullptr);
 }
 
+// Whether opts.pass_tile names a tile the pass kernels have for this state.
+static bool pass_tile_allowed(const sv_state *h, const sv_plan_opts &o)
+{
+    const int T0 = pass_tile_log(h->dtype);
+    if (o.pass_tile == T0)
+        return true;
+    const bool split = h->dtype == SV_C64 && o.precision == SV_PREC_BF16X6;
+    return o.pass_tile == T0 + 1 && !split && h->n >= T0 + 1;
+}
+
+static void key_gates(std::vector<uint64_t> &key, const std::vector<Block> &gates)
+{
+    key.push_back(gates.size());
+    for (const Block &b : gates) {
+        uint64_t t = 0, c = 0;
+        for (int j = 0; j < b.k; ++j)
+            t |= uint64_t(b.targets[j]) << (6 * j);
+        for (int j = 0; j < b.c; ++j)
+            c |= uint64_t(b.controls[j]) << (6 * j);
+        key.push_back(uint64_t(b.k) | uint64_t(b.c) << 4 | uint64_t(b.diag) << 8 | uint64_t(is_phase_gate(b)) << 9 |
+                      uint64_t(uint32_t(b.ngates)) << 16);
+        key.push_back(t);
+        key.push_back(c);
+    }
+}
+
+// Everything a plan for this circuit on this handle depends on.
+static std::vector<uint64_t> plan_key(const sv_state *h, const sv_plan_opts &o, const std::vector<Block> &gates,
+                                      const std::vector<Block> &pre)
+{
+    std::vector<uint64_t> key;
+    key.reserve(8 + h->n + 3 * (gates.size() + pre.size()));
+    key.push_back(uint64_t(uint32_t(o.mode)));
+    key.push_back(uint64_t(uint32_t(o.max_fused)) | uint64_t(uint32_t(o.precision)) << 8 |
+                  uint64_t(uint32_t(o.pass_qubits)) << 16 | uint64_t(uint32_t(o.pass_orders)) << 24 |
+                  uint64_t(uint32_t(o.pass_tile)) << 40);
+    key.push_back(uint64_t(h->n) | uint64_t(h->dtype) << 8);
+    if (o.mode == SV_PLAN_LEARNED) {
+        key.push_back(uint64_t(reinterpret_cast<uintptr_t>(h->model)));
+        key.push_back(costmodel_version(h->model));
+    }
+    for (int q = 0; q < h->n; ++q)
+        key.push_back(uint64_t(h->qmap[q]));
+    if (o.mode == SV_PLAN_LEARNED)
+        key_gates(key, gates);
+    key_gates(key, pre);
+    return key;
+}
+
+static PlanCacheEntry *find_plan(sv_state *h, const std::vector<uint64_t> &key)
+{
+    for (size_t i = 0; i < h->plan_cache.size(); ++i)
+        if (h->plan_cache[i].key == key) {
+            if (i > 0)
+                std::rotate(h->plan_cache.begin(), h->plan_cache.begin() + long(i), h->plan_cache.begin() + long(i) + 1);
+            return &h->plan_cache.front();
+        }
+    return nullptr;
+}
+
+static PlanCacheEntry *keep_plan(sv_state *h, PlanCacheEntry &&e)
+{
+    constexpr size_t kPlansKept = 4;
+    h->plan_cache.insert(h->plan_cache.begin(), std::move(e));
+    if (h->plan_cache.size() > kPlansKept)
+        h->plan_cache.pop_back();
+    return &h->plan_cache.front();
+}
+
 int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_plan_opts *opts, sv_run_stats *stats)
 {
     clear_error();
@@ -1178,6 +1258,7 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
     plain.mode = SV_PLAN_PLAIN;
     plain.pass_qubits = 0;
     plain.pass_orders = 0;
+    plain.pass_tile = 0;
     std::vector<Block> gates_b;
     rc = plan_circuit(h->n, h->dtype, gates, ngates, plain, gates_b);
     if (rc != SV_OK)
@@ -1200,25 +1281,44 @@ int sv_apply_circuit(sv_handle h, const sv_gate *gates, int ngates, const sv_pla
         set_error("pass_orders %d: -1..%d with SV_PLAN_PASSES, else 0", o.pass_orders, kMaxPassOrders);
         return SV_EINVAL;
     }
+    if (o.pass_tile != 0 && (o.mode != SV_PLAN_PASSES || !pass_tile_allowed(h, o))) {
+        set_error("pass_tile %d: 0, or with SV_PLAN_PASSES the smallest pass tile or (except complex64 split-BF16 "
+                  "blocks) twice it", o.pass_tile);
+        return SV_EINVAL;
+    }
     DeviceGuard dg(h->device);
-    if (o.mode == SV_PLAN_PASSES)
-        return run_passes(h, gates_b, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, o.precision,
-                          o.pass_orders, ngates, stats);
+    if (o.mode == SV_PLAN_PASSES || (o.mode == SV_PLAN_LEARNED && h->model)) {
+        const std::vector<Block> pre = prefuse_diagonal_pairs(gates_b);
+        const std::vector<uint64_t> key = plan_key(h, o, gates_b, pre);
+        PlanCacheEntry *e = find_plan(h, key);
+        if (e == nullptr) {
+            PlanCacheEntry ne;
+            ne.key = key;
+            if (o.mode == SV_PLAN_PASSES) {
+                ne.plan = plan_passes(pre, o.pass_qubits ? o.pass_qubits : kMaxPassQubits, o.max_fused, h->n,
+                                      pass_tile_log(h->dtype), h->qmap, o.pass_orders);
+                for (PassGroup &w : ne.plan)
+                    if (w.kernel)
+                        w.tile_log = o.pass_tile;
+            } else {
+                rc = rank_plans(h->model, h->n, h->dtype, gates_b, o.max_fused, o.precision, ne.width, nullptr,
+                                h->qmap, &ne.plan);
+                if (rc != SV_OK)
+                    return rc;
+            }
+            e = keep_plan(h, std::move(ne));
+        }
+        if (o.mode == SV_PLAN_PASSES || e->width == 0)
+            return run_pass_plan(h, pre, e->plan, o.precision, ngates, stats);
+        return run_groups(h, gates_b, group_greedy(gates_b, e->width), o.precision, ngates, stats);
+    }
     std::vector<Group> groups;
     if (o.mode == SV_PLAN_PLAIN) {
         groups.reserve(gates_b.size());
         for (size_t i = 0; i < gates_b.size(); ++i)
             groups.push_back(Group{std::vector<int>(1, int(i)), qubit_mask(gates_b[i])});
     } else {
-        int k = o.max_fused;
-        if (o.mode == SV_PLAN_LEARNED && h->model) {
-            rc = rank_plans(h->model, h->n, h->dtype, gates_b, o.max_fused, o.precision, k, nullptr);
-            if (rc != SV_OK)
-                return rc;
-            if (k == 0)  // the pass plan ranks first
-                return run_passes(h, gates_b, kMaxPassQubits, o.max_fused, o.precision, 0, ngates, stats);
-        }
-        groups = group_greedy(gates_b, k);
+        groups = group_greedy(gates_b, o.max_fused);
     }
     return run_groups(h, gates_b, groups, o.precision, ngates, stats);
 }
@@ -1722,6 +1822,7 @@ int sv_pass_plan_info(int n, int dtype, const sv_gate *gates, int ngates, const 
     plain.mode = SV_PLAN_PLAIN;
     plain.pass_qubits = 0;
     plain.pass_orders = 0;
+    plain.pass_tile = 0;
     std::vector<Block> gates_b;
     rc = plan_circuit(n, dtype, gates, ngates, plain, gates_b);
     if (rc != SV_OK)

@@ -242,6 +242,7 @@ struct sv_costmodel {
     int t = 0;
     hipStream_t s = nullptr;
     bool half_fresh = false;
+    uint64_t version = 1;  // changes whenever the parameters do
 };
 
 namespace {
@@ -325,17 +326,30 @@ namespace sv {
 
 void sweep_features(int n, int dtype, const sv_sweep_record &r, float *f)
 {
+    static_assert(F == 16, "feature layout");
     const float fn = float(n);
-    f[0] = float(r.k) / 6.0f;
+    const bool pass = r.kind == SV_SWEEP_PASS;
+    // tile bits among the top 8 index bits, and the contiguous low tile
+    // bits (a pass tile reads runs of 2^that amplitudes)
+    const uint64_t tm = pass ? r.tile_mask : 0;
+    const int top = n > 8 ? __builtin_popcountll(tm >> (n - 8)) : __builtin_popcountll(tm);
+    const int run = __builtin_ctzll(~tm);
+    f[0] = float(r.k) / 8.0f;
     f[1] = float(r.c) / 8.0f;
     f[2] = std::log2(1.0f + float(r.num_gates)) / 8.0f;
     f[3] = float(r.lowest_target) / fn;
     f[4] = float(r.highest_target) / fn;
-    f[5] = float(r.highest_target - r.lowest_target + 1) / fn;
-    f[6] = fn / 40.0f;
-    f[7] = float(dtype);
-    f[8] = float(r.kind) / 5.0f;
+    f[5] = float(top) / 8.0f;
+    f[6] = float(dtype);
+    f[7] = pass ? 1.0f : 0.0f;
+    f[8] = float(r.kind) / 7.0f;
     f[9] = float(std::log2(r.bytes > 1.0 ? r.bytes : 1.0)) / 40.0f;
+    f[10] = float(r.blocks) / 8.0f;
+    f[11] = float(r.term_blocks) / 8.0f;
+    f[12] = float(r.variant_blocks) / 8.0f;
+    f[13] = pass ? float(r.tile_log - pass_tile_log(dtype)) : 0.0f;
+    f[14] = r.precision == SV_PREC_BF16X6 ? 1.0f : (r.precision == SV_PREC_BF16X3 ? 0.5f : 0.0f);
+    f[15] = float(run) / 8.0f;
 }
 
 sv_sweep_record block_record(int n, int dtype, const Block &b, int precision)
@@ -353,85 +367,261 @@ sv_sweep_record block_record(int n, int dtype, const Block &b, int precision)
     return r;
 }
 
+// Physical bit of logical qubit q.
+static inline int phys_of(const int *phys, int q)
+{
+    return phys ? phys[q] : q;
+}
+
+// The sweep a greedy group becomes (physical positions): its shape, padded to
+// four targets where execution pads (the pad is the lowest free qubit >= 6).
+static sv_sweep_record group_record(int n, int dtype, int precision, const std::vector<Block> &gates,
+                                    const Group &g, const int *phys)
+{
+    Block b = group_shape(gates, g);
+    if (b.k == 3 && pads_to_four(n, dtype, b.c, precision)) {
+        uint64_t used = qubit_mask(b);
+        int pick = -1;
+        for (int q = 0; q < n && pick < 0; ++q)
+            if (q >= 6 && !((used >> q) & 1))
+                pick = q;
+        for (int q = 0; q < n && pick < 0; ++q)
+            if (!((used >> q) & 1))
+                pick = q;
+        b.targets[b.k++] = pick;
+    }
+    for (int j = 0; j < b.k; ++j)
+        b.targets[j] = phys_of(phys, b.targets[j]);
+    for (int j = 0; j < b.c; ++j)
+        b.controls[j] = phys_of(phys, b.controls[j]);
+    return block_record(n, dtype, b, precision);
+}
+
+sv_sweep_record pass_record(int n, int dtype, int precision, const PassGroup &w, const int *phys, int T)
+{
+    sv_sweep_record r{};
+    r.kind = SV_SWEEP_PASS;
+    uint64_t pm = 0, avoid = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((w.qmask >> q) & 1)
+            pm |= uint64_t(1) << phys_of(phys, q);
+        if ((w.omask >> q) & 1)
+            avoid |= uint64_t(1) << phys_of(phys, q);
+    }
+    r.k = __builtin_popcountll(pm);
+    r.lowest_target = pm ? __builtin_ctzll(pm) : 0;
+    r.highest_target = pm ? 63 - __builtin_clzll(pm) : 0;
+    r.num_gates = w.ngates;
+    const double amps = std::ldexp(1.0, n);
+    const bool split = dtype == SV_C64 && precision == SV_PREC_BF16X6;
+    r.bytes = 2.0 * (dtype == SV_C64 ? 8.0 : 16.0) * amps;
+    r.blocks = int(w.subs.size());
+    r.flops = double(r.blocks) * 126.0 * amps;
+    r.mfma_flops = double(r.blocks) * (split ? 768.0 : 96.0) * amps;
+    r.precision = split ? SV_PREC_BF16X6 : SV_PREC_NATIVE;
+    for (size_t i = 0; i < w.subs.size(); ++i) {
+        r.term_blocks += (!w.front[i].empty() || !w.back[i].empty()) ? 1 : 0;
+        r.variant_blocks += w.vq[i] != 0 ? 1 : 0;
+    }
+    int tb[16];
+    if (pass_tile_bits(n, T, pm, avoid, tb) == T) {
+        r.tile_log = T;
+        for (int b = 0; b < T; ++b)
+            r.tile_mask |= uint64_t(1) << tb[b];
+    }
+    return r;
+}
+
+// Tile widths a kernel pass may take: the smallest, and twice it where the
+// kernel has that form (not the complex64 split-BF16 kernel) and the state
+// holds enough tiles of it.
+static int pass_tile_options(int n, int dtype, int precision, int *opts)
+{
+    const int T0 = pass_tile_log(dtype);
+    int k = 0;
+    opts[k++] = T0;
+    const bool split = dtype == SV_C64 && precision == SV_PREC_BF16X6;
+    if (!split && n >= T0 + 1 + 6)
+        opts[k++] = T0 + 1;
+    return k;
+}
+
+// Feature rows of candidate sweeps and the predicted time of each (ms).
+struct Ranker {
+    int n, dtype;
+    std::vector<float> feats;
+    std::vector<double> gbytes;
+    std::vector<double> ms;
+    int add(const sv_sweep_record &r)
+    {
+        float f[F];
+        sweep_features(n, dtype, r, f);
+        feats.insert(feats.end(), f, f + F);
+        gbytes.push_back(r.bytes * 1e-9);
+        return int(gbytes.size()) - 1;
+    }
+    int run(sv_costmodel *m)
+    {
+        const int rows = int(gbytes.size());
+        ms.assign(size_t(rows), 0.0);
+        if (rows == 0)
+            return SV_OK;
+        std::vector<float> pred(static_cast<size_t>(rows));
+        int rc = sv_costmodel_predict(m, feats.data(), rows, pred.data());
+        if (rc != SV_OK)
+            return rc;
+        for (int i = 0; i < rows; ++i)
+            ms[size_t(i)] = std::exp(double(pred[size_t(i)])) * gbytes[size_t(i)];
+        return SV_OK;
+    }
+};
+
+// Rows of one candidate pass plan: per kernel pass one row per tile option,
+// per fallback pass its sweeps.
+struct PlanRows {
+    std::vector<std::vector<int>> pass_rows;  // rows of pass i (tile options, or its sweeps)
+    std::vector<std::vector<int>> tiles;      // kernel pass i: the tile width of each row
+};
+
+static PlanRows plan_rows(Ranker &rk, int precision, const std::vector<Block> &gates,
+                          const std::vector<PassGroup> &plan, const int *phys)
+{
+    PlanRows pr;
+    int opts[2];
+    const int nopt = pass_tile_options(rk.n, rk.dtype, precision, opts);
+    for (const PassGroup &w : plan) {
+        std::vector<int> rows, tiles;
+        if (w.kernel) {
+            for (int o = 0; o < nopt; ++o) {
+                const sv_sweep_record r = pass_record(rk.n, rk.dtype, precision, w, phys, opts[o]);
+                if (r.tile_log == 0)
+                    continue;  // the pass does not fit this tile
+                rows.push_back(rk.add(r));
+                tiles.push_back(opts[o]);
+            }
+        } else {
+            for (const Group &g : w.subs)
+                rows.push_back(rk.add(group_record(rk.n, rk.dtype, precision, gates, g, phys)));
+        }
+        pr.pass_rows.push_back(std::move(rows));
+        pr.tiles.push_back(std::move(tiles));
+    }
+    return pr;
+}
+
+// Predicted time of a plan with each kernel pass at its fastest tile (and
+// those tiles written into the plan).
+static double plan_time(const Ranker &rk, const PlanRows &pr, std::vector<PassGroup> *plan)
+{
+    double t = 0.0;
+    for (size_t i = 0; i < pr.pass_rows.size(); ++i) {
+        const std::vector<int> &rows = pr.pass_rows[i];
+        if (pr.tiles[i].empty()) {
+            for (int r : rows)
+                t += rk.ms[size_t(r)];
+            if (rows.empty() && plan && (*plan)[i].kernel)
+                return HUGE_VAL;  // a kernel pass that fits no tile
+            continue;
+        }
+        size_t best = 0;
+        for (size_t o = 1; o < rows.size(); ++o)
+            if (rk.ms[size_t(rows[o])] < rk.ms[size_t(rows[best])])
+                best = o;
+        t += rk.ms[size_t(rows[best])];
+        if (plan)
+            (*plan)[i].tile_log = pr.tiles[i][best];
+    }
+    return t;
+}
+
+int learned_pass_plan(sv_costmodel *m, int n, int dtype, int precision, const std::vector<Block> &gates,
+                      int max_fused, const int *phys, int orders, std::vector<PassGroup> &plan, double *pred_ms)
+{
+    const int T0 = pass_tile_log(dtype);
+    std::vector<std::vector<PassGroup>> cands;
+    for (int pq = 6; pq <= kMaxPassQubits; ++pq)
+        for (std::vector<PassGroup> &c : pass_plan_candidates(gates, pq, max_fused, n, T0, phys, orders))
+            cands.push_back(std::move(c));
+    Ranker rk{n, dtype, {}, {}, {}};
+    std::vector<PlanRows> rows;
+    rows.reserve(cands.size());
+    for (const std::vector<PassGroup> &c : cands)
+        rows.push_back(plan_rows(rk, precision, gates, c, phys));
+    int rc = rk.run(m);
+    if (rc != SV_OK)
+        return rc;
+    size_t best = 0;
+    double tbest = HUGE_VAL;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const double t = plan_time(rk, rows[i], nullptr);
+        if (t < tbest) {
+            tbest = t;
+            best = i;
+        }
+    }
+    if (!std::isfinite(tbest)) {
+        set_error("cost model: no finite prediction for any pass plan");
+        return SV_EINVAL;
+    }
+    plan = std::move(cands[best]);
+    plan_time(rk, rows[best], &plan);
+    if (pred_ms)
+        *pred_ms = tbest;
+    return SV_OK;
+}
+
 int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gates, int max_fused, int precision,
-               int &chosen, float *pred_ms)
+               int &chosen, float *pred_ms, const int *phys, std::vector<PassGroup> *pass_plan_out)
 {
     chosen = max_fused;
     if (!m)
         return SV_OK;
-    std::vector<float> feats;
-    std::vector<int> owner;  // candidate: width 1..max_fused, 0 = the pass plan
-    std::vector<double> gbytes;
-    auto add = [&](const sv_sweep_record &r, int cand) {
-        float f[F];
-        sweep_features(n, dtype, r, f);
-        feats.insert(feats.end(), f, f + F);
-        owner.push_back(cand);
-        gbytes.push_back(r.bytes * 1e-9);
-    };
-    // the sweep a group becomes: its shape, padded to four targets where
-    // execution pads (the pad is the lowest free qubit >= 6)
-    auto shape_record = [&](const std::vector<Block> &gl, const Group &g) {
-        Block b = group_shape(gl, g);
-        if (b.k == 3 && pads_to_four(n, dtype, b.c, precision)) {
-            uint64_t used = qubit_mask(b);
-            int pick = -1;
-            for (int q = 0; q < n && pick < 0; ++q)
-                if (q >= 6 && !((used >> q) & 1))
-                    pick = q;
-            for (int q = 0; q < n && pick < 0; ++q)
-                if (!((used >> q) & 1))
-                    pick = q;
-            b.targets[b.k++] = pick;
-        }
-        return block_record(n, dtype, b, precision);
-    };
+    // greedy widths 1..max_fused
+    Ranker rk{n, dtype, {}, {}, {}};
+    std::vector<std::vector<int>> width_rows(size_t(max_fused) + 1);
     for (int k = 1; k <= max_fused; ++k)
         for (const Group &g : group_greedy(gates, k))
-            add(shape_record(gates, g), k);
-    const std::vector<Block> pgates = prefuse_diagonal_pairs(gates);
-    for (const PassGroup &w : plan_passes(pgates, kMaxPassQubits, max_fused, n, pass_tile_log(dtype), nullptr)) {
-        if (!w.kernel) {
-            for (const Group &g : w.subs)
-                add(shape_record(pgates, g), 0);
-            continue;
-        }
-        sv_sweep_record r{};
-        r.kind = SV_SWEEP_PASS;
-        r.k = __builtin_popcountll(w.qmask);
-        r.lowest_target = __builtin_ctzll(w.qmask);
-        r.highest_target = 63 - __builtin_clzll(w.qmask);
-        r.num_gates = w.ngates;
-        r.bytes = 2.0 * (dtype == SV_C64 ? 8.0 : 16.0) * std::ldexp(1.0, n);
-        add(r, 0);
-    }
-    const int rows = int(owner.size());
-    if (rows == 0)
-        return SV_OK;
-    std::vector<float> pred(rows);
-    int rc = sv_costmodel_predict(m, feats.data(), rows, pred.data());
+            width_rows[size_t(k)].push_back(rk.add(group_record(n, dtype, precision, gates, g, phys)));
+    int rc = rk.run(m);
     if (rc != SV_OK)
         return rc;
-    std::vector<double> tot(max_fused + 1, 0.0);
-    for (int i = 0; i < rows; ++i)
-        tot[owner[i]] += std::exp(double(pred[i])) * gbytes[i];
+    std::vector<double> tot(size_t(max_fused) + 1, 0.0);
+    for (int k = 1; k <= max_fused; ++k)
+        for (int r : width_rows[size_t(k)])
+            tot[size_t(k)] += rk.ms[size_t(r)];
+    // the LDS pass plans, on the gate list with diagonal pairs fused
+    std::vector<PassGroup> pplan;
+    double tp = HUGE_VAL;
+    const std::vector<Block> pgates = prefuse_diagonal_pairs(gates);
+    constexpr int kLearnedOrders = 8;
+    rc = learned_pass_plan(m, n, dtype, precision, pgates, max_fused, phys, kLearnedOrders, pplan, &tp);
+    if (rc != SV_OK)
+        return rc;
+    tot[0] = tp;
     double best = 0.0;
     bool finite = true, any = false;
     for (int cand = 1; cand <= max_fused + 1; ++cand) {
         const int c = cand == max_fused + 1 ? 0 : cand;  // widths first, then the pass plan
         if (pred_ms)
-            pred_ms[cand - 1] = float(tot[c]);
-        if (!std::isfinite(tot[c]))
+            pred_ms[cand - 1] = float(tot[size_t(c)]);
+        if (!std::isfinite(tot[size_t(c)]))
             finite = false;
-        if (!any || tot[c] < best) {
-            best = tot[c];
+        if (!any || tot[size_t(c)] < best) {
+            best = tot[size_t(c)];
             chosen = c;
             any = true;
         }
     }
     if (!finite)
         chosen = max_fused;
+    if (pass_plan_out)
+        *pass_plan_out = std::move(pplan);
     return SV_OK;
+}
+
+uint64_t costmodel_version(const sv_costmodel *m)
+{
+    return m ? m->version : 0;
 }
 
 }  // namespace sv
@@ -521,6 +711,7 @@ int sv_costmodel_set_params(sv_costmodel_handle m, const float *in)
     CM_TRY(hipStreamSynchronize(m->s));
     CM_TRY(hipMemcpy(m->d_p, in, P * sizeof(float), hipMemcpyHostToDevice));
     m->half_fresh = false;
+    m->version += 1;
     return SV_OK;
 }
 
@@ -575,6 +766,7 @@ int sv_costmodel_train(sv_costmodel_handle m, const float *x, const float *y, in
         CM_TRY(hipGetLastError());
     }
     m->half_fresh = false;
+    m->version += 1;
     float l = 0.0f;
     CM_TRY(hipMemcpyAsync(&l, m->d_loss, sizeof(float), hipMemcpyDeviceToHost, m->s));
     CM_TRY(hipStreamSynchronize(m->s));
@@ -657,10 +849,11 @@ int sv_costmodel_rank(sv_costmodel_handle m, int n, int dtype, const sv_gate *ga
     if (rc != SV_OK)
         return rc;
     std::vector<Block> blocks;
-    sv_plan_opts o{SV_PLAN_PLAIN, max_fused, SV_PREC_NATIVE, 0, 0};
+    sv_plan_opts o{SV_PLAN_PLAIN, max_fused, SV_PREC_NATIVE, 0, 0, 0};
     if ((rc = plan_circuit(n, dtype, gates, ngates, o, blocks)) != SV_OK)
         return rc;
-    return rank_plans(m, n, dtype, blocks, max_fused, SV_PREC_NATIVE, *chosen, predicted_ms);
+    return rank_plans(m, n, dtype, blocks, max_fused, dtype == SV_C64 ? SV_PREC_BF16X6 : SV_PREC_NATIVE, *chosen,
+                      predicted_ms, nullptr, nullptr);
 }
 
 }  // extern "C"

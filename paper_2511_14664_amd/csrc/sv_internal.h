@@ -96,6 +96,7 @@ struct PassGroup {
     std::vector<std::vector<int>> front, back;
     std::vector<uint64_t> vq;
     int ngates = 0;
+    int tile_log = 0;  // kernel pass: LDS tile width chosen by the planner (0: by its blocks)
 };
 // Runs of gates on one qubit pair whose product is diagonal (CX RZ CX =
 // exp(-i theta/2 Z Z)) become one phase gate, placed at the run's first gate
@@ -109,6 +110,10 @@ std::vector<Block> prefuse_diagonal_pairs(const std::vector<Block> &gates);
 constexpr int kMaxPassOrders = 64;
 std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
                                    const int *phys, int orders = 0);
+// Every candidate plan_passes compares (the three outer-qubit strategies,
+// then the order search on the cheapest of them), in that order.
+std::vector<std::vector<PassGroup>> pass_plan_candidates(const std::vector<Block> &gates, int pass_qubits,
+                                                         int max_fused, int n, int T0, const int *phys, int orders);
 // Model time of a pass plan in HBM round trips of the state (the planner's
 // objective).
 double pass_plan_cost(const std::vector<PassGroup> &plan);
@@ -128,8 +133,22 @@ double block_flops(int n, const Block &b);
 // a plan block would produce, and ranking of greedy plans of width 1..max_fused.
 void sweep_features(int n, int dtype, const sv_sweep_record &r, float *f);
 sv_sweep_record block_record(int n, int dtype, const Block &b, int precision);
+// Rank greedy widths 1..max_fused and the learned pass plan (gates: logical,
+// phys: the state's map or nullptr); chosen = width, 0 for the pass plan,
+// whose plan (on the pre-fused gate list) goes to *pass_plan_out.
 int rank_plans(sv_costmodel *m, int n, int dtype, const std::vector<Block> &gates, int max_fused, int precision,
-               int &chosen, float *pred_ms);
+               int &chosen, float *pred_ms, const int *phys, std::vector<PassGroup> *pass_plan_out);
+uint64_t costmodel_version(const sv_costmodel *m);
+// Learned choice among pass plans (sv_costmodel.hip): candidates of 6, 7 and
+// 8 pass qubits over `orders` gate orders on the (pre-fused) gate list, each
+// kernel pass given the tile width the model predicts fastest.  phys: the
+// state's logical -> physical map (nullptr: identity).  On success `plan`
+// holds the winner and *pred_ms its predicted time.
+int learned_pass_plan(sv_costmodel *m, int n, int dtype, int precision, const std::vector<Block> &gates,
+                      int max_fused, const int *phys, int orders, std::vector<PassGroup> &plan, double *pred_ms);
+// The sweep record a kernel pass of a plan would produce (physical tile bits
+// from phys), for the tile width T.
+sv_sweep_record pass_record(int n, int dtype, int precision, const PassGroup &w, const int *phys, int T);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (device code in the .hip sources).  All pointers are

@@ -953,9 +953,10 @@ double pass_plan_cost(const std::vector<PassGroup> &plan)
     return c;
 }
 
-std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
-                                   const int *phys, int orders)
+std::vector<std::vector<PassGroup>> pass_plan_candidates(const std::vector<Block> &gates, int pass_qubits,
+                                                         int max_fused, int n, int T0, const int *phys, int orders)
 {
+    std::vector<std::vector<PassGroup>> cands;
     // Three candidate plans, each pass's gates partitioned in circuit order
     // and in reverse; the cheapest is then re-partitioned over random gate
     // orders as well, and re-planned over random orders of the whole
@@ -976,14 +977,13 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
         alt[ph - 1] = std::async(std::launch::async, [&, ph]() {
             return pass_plan(gates, pass_qubits, max_fused, n, T0, phys, ph, 0);
         });
-    std::vector<PassGroup> best = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0, 0);
-    double cbest = pass_plan_cost(best);
+    cands.push_back(pass_plan(gates, pass_qubits, max_fused, n, T0, phys, 0, 0));
+    double cbest = pass_plan_cost(cands.back());
     int pbest = 0;
     for (int ph = 1; ph <= 2 && any_phase; ++ph) {
-        std::vector<PassGroup> p = alt[ph - 1].get();
-        const double c = pass_plan_cost(p);
+        cands.push_back(alt[ph - 1].get());
+        const double c = pass_plan_cost(cands.back());
         if (c < cbest) {
-            best.swap(p);
             cbest = c;
             pbest = ph;
         }
@@ -1059,22 +1059,29 @@ std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qub
             fut.push_back(std::async(std::launch::async, plan_order, trial));
         // meanwhile: the winner in circuit order, each pass split over random
         // orders of its own gates
-        std::vector<PassGroup> p = pass_plan(gates, pass_qubits, max_fused, n, T0, phys, pbest, trials);
-        double c = pass_plan_cost(p);
+        cands.push_back(pass_plan(gates, pass_qubits, max_fused, n, T0, phys, pbest, trials));
+        for (auto &f : fut)
+            cands.push_back(f.get());
+    }
+    return cands;
+}
+
+std::vector<PassGroup> plan_passes(const std::vector<Block> &gates, int pass_qubits, int max_fused, int n, int T0,
+                                   const int *phys, int orders)
+{
+    // the cheapest candidate in the pass model; the earliest wins ties
+    std::vector<std::vector<PassGroup>> cands =
+        pass_plan_candidates(gates, pass_qubits, max_fused, n, T0, phys, orders);
+    size_t best = 0;
+    double cbest = pass_plan_cost(cands[0]);
+    for (size_t i = 1; i < cands.size(); ++i) {
+        const double c = pass_plan_cost(cands[i]);
         if (c < cbest) {
-            best.swap(p);
             cbest = c;
-        }
-        for (auto &f : fut) {
-            std::vector<PassGroup> q = f.get();
-            c = pass_plan_cost(q);
-            if (c < cbest) {
-                best.swap(q);
-                cbest = c;
-            }
+            best = i;
         }
     }
-    return best;
+    return std::move(cands[best]);
 }
 
 std::vector<Block> plan_greedy(const std::vector<Block> &gates, int kmax)
@@ -1105,8 +1112,8 @@ int plan_circuit(int n, int dtype, const sv_gate *gates, int ngates, const sv_pl
         set_error("unknown plan mode %d", o.mode);
         return SV_EINVAL;
     }
-    if (o.pass_qubits != 0 || o.pass_orders != 0) {
-        set_error("pass_qubits and pass_orders must be 0 outside SV_PLAN_PASSES");
+    if (o.pass_qubits != 0 || o.pass_orders != 0 || o.pass_tile != 0) {
+        set_error("pass_qubits, pass_orders and pass_tile must be 0 outside SV_PLAN_PASSES");
         return SV_EINVAL;
     }
     if (o.mode != SV_PLAN_PLAIN && (o.max_fused < 1 || o.max_fused > SV_MAX_TARGETS)) {

@@ -815,6 +815,60 @@ def test_pass_plan_qpe_exact_phase(dtype):
         assert abs(abs(a[m | (1 << k)]) - 1.0) <= TOL[dtype] * 10
 
 
+def with_new_angles(gates, seed):
+    """The same gates on the same qubits with fresh rotation angles."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in gates:
+        if g.name in ("u3", "rx", "ry", "rz", "p"):
+            g = Gate(g.name, g.targets, g.controls, tuple(float(x) for x in rng.uniform(0, 2 * math.pi, len(g.params))))
+        out.append(g)
+    return out
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pass_plan_kept_per_structure(dtype):
+    """A circuit of the same structure with new angles reuses the plan kept on
+    the handle (new block matrices, same grouping); a relayout or other
+    options make a new plan.  Every result against the oracle."""
+    n = 18
+    a = phase_circuit(n, 5, 3) + control_circuit(n, 6, 2)
+    b = with_new_angles(a, 7)
+    with State(n, dtype) as s:
+        for gates, opts in ((a, B.make_opts(B.SV_PLAN_PASSES)), (b, B.make_opts(B.SV_PLAN_PASSES)),
+                            (a, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 6))):
+            B.sv_reset(s.h)
+            run_checked(s, gates, opts, oracle.run(gates, n))
+        B.sv_reset(s.h)
+        B.sv_swap_bits(s.h, 0, n - 6, 6)
+        run_checked(s, b, B.make_opts(B.SV_PLAN_PASSES), oracle.run(b, n))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+def test_pass_plan_forced_tile_width(dtype):
+    """pass_tile: every kernel pass on the smallest tile or on twice it
+    (the wide form: 512 threads); the records show the width used."""
+    n = 20
+    gates = pass_circuit(n, 21)
+    want = oracle.run(gates, n)
+    T0 = 12 if dtype == B.SV_C64 else 11
+    for tile in (T0, T0 + 1):
+        with State(n, dtype) as s:
+            _, recs = run_checked(s, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 0, tile), want)
+        tiles = {r["tile_log"] for r in recs if r["kind_name"] == "pass"}
+        say(f"  pass_tile {tile}: tiles used {tiles}")
+        assert tiles and tiles <= {tile, T0} and tile in tiles
+    with State(n, dtype) as s:
+        for bad in (T0 - 1, T0 + 2):
+            with pytest.raises(B.SvError):
+                B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 8, 0, bad))
+        with pytest.raises(B.SvError):
+            B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_GREEDY, 5, B.SV_PREC_NATIVE, 0, 0, T0))
+        if dtype == B.SV_C64:
+            with pytest.raises(B.SvError):
+                B.sv_apply_circuit(s.h, gates, B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_BF16X6, 8, 0, T0 + 1))
+
+
 def test_pass_plan_rejects_bad_options():
     with State(12, B.SV_C64) as s:
         for opts in (B.make_opts(B.SV_PLAN_PASSES, 5, B.SV_PREC_NATIVE, 3),
