@@ -34,8 +34,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["layered", "share", "batch", "su4", "rcs", "qpe", "tfim"], default="layered",
-                    help="layered: 28-qubit random layered circuit (the headline line); share: 34q complex128 / "
+    ap.add_argument("--workload", choices=["layered", "c1", "share", "batch", "su4", "rcs", "qpe", "tfim"],
+                    default="layered",
+                    help="layered: 28-qubit random layered circuit (the headline line); c1: 12-qubit "
+                         "complex128 layered circuit (launch-latency bound); share: 34q complex128 / "
                          "35q complex64 share with 6-bit exchanges every 2 layers; batch: 512 HEA circuits "
                          "of 10..22 qubits in one graph launch vs one launch per gate; su4: 30-qubit U3 + "
                          "SU(4) circuit, depth 40, greedy vs learned fusion plan; rcs / qpe / tfim: the "
@@ -50,7 +52,8 @@ def parse():
                     help="native: FP32 (complex64) / FP64 (complex128) arithmetic; bf16x3: three-term BF16 "
                          "split for complex64 5-6-qubit greedy blocks; bf16x6: FP32-accurate six-product split "
                          "BF16 for complex64 pass blocks")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain (unfused) comparison run")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain (unfused) comparison run (batch: every per-circuit baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 reference run (CPU baseline and the accuracy fields)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -87,6 +90,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "c1":
+        return bench_c1(args)
     if args.workload == "share":
         return bench_share(args)
     if args.workload == "su4":
@@ -214,24 +219,7 @@ def main():
         plain_state = None if args.no_cpu_baseline else B.sv_copy_to_host(sv.handle, n, dtype)
         log(f"plain: {plain}")
 
-    copy_cal = None
-    if args.calibrate_copy:
-        a = torch.empty(S << n, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        af, bf = a.view(torch.float32), b.view(torch.float32)
-        torch.mul(af, 1.0, out=bf)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            torch.mul(af, 1.0, out=bf)
-        e1.record()
-        torch.cuda.synchronize()
-        cms = e0.elapsed_time(e1) / 5
-        copy_cal = {"bytes_per_launch": 2 * (S << n), "ms": round(cms, 4),
-                    "GB/s": round(2 * (S << n) / (cms / 1e3) / 1e9, 1)}
-        log(f"copy calibration: {copy_cal}")
-        del a, b
+    copy_cal = copy_calibration(S << n) if args.calibrate_copy else None
 
     cpu = None
     accuracy = None
@@ -295,6 +283,31 @@ def main():
         out["accuracy_vs_fp64_oracle"] = accuracy
     print(json.dumps(out), flush=True)
     sv.close()
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of nbytes (torch.mul(x, 1.0, out=y)), timed with
+    HIP events: the reference kernel for HBM counter calibration and the
+    practical streaming rate."""
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    af, bf = a.view(torch.float32), b.view(torch.float32)
+    torch.mul(af, 1.0, out=bf)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        torch.mul(af, 1.0, out=bf)
+    e1.record()
+    torch.cuda.synchronize()
+    cms = e0.elapsed_time(e1) / 5
+    cal = {"bytes_per_launch": 2 * nbytes, "ms": round(cms, 4), "GB/s": round(2 * nbytes / (cms / 1e3) / 1e9, 1)}
+    log(f"copy calibration: {cal}")
+    del a, b, af, bf
+    torch.cuda.empty_cache()
+    return cal
 
 
 def state_error(got, want, chunk=1 << 24):
@@ -536,6 +549,8 @@ def bench_share(args):
 
     dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
     n = 35 if dtype == B.SV_C64 else 34
+    if args.calibrate_copy:
+        copy_calibration(1 << 31)
     ops = W.share_layers(n, 10, W.circuit_seed(3, 1))
     segs, seg = [], []
     for op in ops:
@@ -589,6 +604,73 @@ def bench_share(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c1(args):
+    """12-qubit complex128 layered circuit (20 layers of U3 on every qubit +
+    CNOT on a random matching, 360 gates): the state is 64 KiB, so the
+    circuit is bound by launch latency, not HBM.  Wall time per circuit
+    (apply + synchronise) one sweep per gate, greedy-fused, and as a batch of
+    one circuit (the whole circuit in one persistent launch, in LDS); the
+    full state and all probabilities against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as W
+    from paper_2511_14664_amd import _binding as B
+
+    n = 12
+    gates = W.layered_u3_pairing(n, 20, W.circuit_seed(1, 1), "cx")
+    circ = B.Circuit(gates)
+    want = oracle.run(gates, n)
+    res = {}
+    h = B.sv_create(n, B.SV_C128)
+    for name, opts in (("plain", B.make_opts(B.SV_PLAN_PLAIN)), ("greedy5", B.make_opts(B.SV_PLAN_GREEDY, 5))):
+        for _ in range(max(1, args.warmup)):
+            B.sv_reset(h)
+            B.sv_apply_circuit(h, circ, opts)
+        ts = []
+        for _ in range(args.steps):
+            B.sv_reset(h)
+            B.sv_synchronize(h)
+            t0 = time.perf_counter()
+            st = B.sv_apply_circuit(h, circ, opts)
+            B.sv_synchronize(h)
+            ts.append(time.perf_counter() - t0)
+        got = B.sv_copy_to_host(h, n, B.SV_C128)
+        p = B.sv_probabilities(h, list(range(n)))
+        t = float(np.median(ts))
+        res[name] = {"us_per_circuit": round(t * 1e6, 1), "gate_apps_per_s": round(len(gates) / t, 1),
+                     "us_per_gate": round(t * 1e6 / len(gates), 3), "sweeps": st["sweeps"],
+                     "max_abs_err": float(np.max(np.abs(got - want))),
+                     "max_prob_err": float(np.max(np.abs(p - oracle.probabilities(want))))}
+        log(f"c1 {name}: {res[name]}")
+    B.sv_destroy(h)
+    # one circuit as a batch: every gate in LDS in one launch; the batch
+    # returns expectation values, so the state is read out as <Z_i> here
+    zt = W.hea_z_terms(n)[:n]
+    bt = B.Batch([gates], [n], [[1 << i for i in range(n)]])
+    hb = B.sv_batch_create(B.SV_C128, bt)
+    for _ in range(max(1, args.warmup)):
+        B.sv_batch_run(hb, bt)
+    ts, gms = [], []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        z = B.sv_batch_run(hb, bt)
+        ts.append(time.perf_counter() - t0)
+        gms.append(B.sv_batch_last_ms(hb))
+    B.sv_batch_destroy(hb)
+    zw = np.array([oracle.expect_pauli(want, t).real for t in zt])
+    t = float(np.median(ts))
+    res["batch_of_one"] = {"us_per_circuit": round(t * 1e6, 1), "graph_us": round(1e3 * float(np.median(gms)), 1),
+                           "gate_apps_per_s": round(len(gates) / t, 1), "us_per_gate": round(t * 1e6 / len(gates), 3),
+                           "max_abs_err_Z": float(np.max(np.abs(z - zw)))}
+    log(f"c1 batch_of_one: {res['batch_of_one']}")
+    out = {"metric": "gate-apps/s (12-qubit complex128, launch-latency bound)",
+           "workload": f"12-qubit complex128 layered circuit, 20 layers, {len(gates)} gates", "n_gpus": 1,
+           "steps": args.steps, "plans": res}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """512 hardware-efficient-ansatz circuits, 10..22 qubits, depth 8: one
     graph-captured persistent launch vs one launch per gate."""
@@ -599,6 +681,8 @@ def bench_batch(args):
     from paper_2511_14664_amd import _binding as B
 
     dtype = B.SV_C64 if args.dtype == "c64" else B.SV_C128
+    if args.calibrate_copy:
+        copy_calibration(1 << 31)
     hb = W.hea_batch(512, 10, 22, 8, W.circuit_seed(4, 1))
     circs = [hb.circuit(i) for i in range(512)]
     qs = [int(q) for q in hb.qubits]
@@ -619,6 +703,12 @@ def bench_batch(args):
         gms.append(B.sv_batch_last_ms(h))
     B.sv_batch_destroy(h)
     wall_ms = 1e3 * float(np.median(walls))
+    if args.no_plain:
+        out = {"workload": f"512 HEA circuits, 10..22 qubits, depth 8, {args.dtype}", "gates": hb.num_gates(),
+               "config": cfg, "graph_ms": round(float(np.median(gms)), 3), "wall_ms": round(wall_ms, 3),
+               "ms_per_circuit": round(wall_ms / 512, 5)}
+        print(json.dumps(out), flush=True)
+        return
     # baseline: every circuit on its own state, one launch per gate, then its read-out
     zterms = [W.hea_z_terms(q) for q in qs]
     torch.cuda.synchronize()
@@ -635,13 +725,36 @@ def bench_batch(args):
         base.append(B.sv_expect_pauli(s, zterms[i]))
     torch.cuda.synchronize()
     base_ms = (time.perf_counter() - t0) * 1e3
+    base = np.concatenate(base)
+    # fused baselines: every circuit on its own state through its own fused
+    # plan (greedy <= 4-qubit blocks; LDS passes, which fall back to greedy
+    # sweeps below the pass tile), then its read-out; best of two runs each
+    fused = {}
+    for name, opts in (("greedy4", B.make_opts(B.SV_PLAN_GREEDY, 4, precision_of(args, B))),
+                       ("passes", B.make_opts(B.SV_PLAN_PASSES, 4, precision_of(args, B)))):
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vals = []
+            for i in range(512):
+                s = states[qs[i]]
+                B.sv_reset(s)
+                B.sv_apply_circuit(s, bt.circs[i], opts)
+                vals.append(B.sv_expect_pauli(s, zterms[i]))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            best = ms if best is None else min(best, ms)
+        fused[name] = {"ms": round(best, 1), "max_abs_diff_vs_batch": float(np.max(np.abs(np.concatenate(vals) - res)))}
+        log(f"batch: per-circuit fused baseline {name}: {fused[name]}")
     for s in states.values():
         B.sv_destroy(s)
-    base = np.concatenate(base)
+    best_fused = min(v["ms"] for v in fused.values())
     out = {"workload": f"512 HEA circuits, 10..22 qubits, depth 8, {args.dtype}", "gates": hb.num_gates(),
            "config": cfg, "graph_ms": round(float(np.median(gms)), 3), "wall_ms": round(wall_ms, 3),
            "ms_per_circuit": round(wall_ms / 512, 5), "per_gate_launch_ms": round(base_ms, 1),
            "per_gate_ms_per_circuit": round(base_ms / 512, 5), "speedup": round(base_ms / wall_ms, 2),
+           "per_circuit_fused_ms": fused, "speedup_vs_best_fused": round(best_fused / wall_ms, 2),
            "max_abs_diff_vs_per_gate": float(np.max(np.abs(res - base)))}
     print(json.dumps(out), flush=True)
 
