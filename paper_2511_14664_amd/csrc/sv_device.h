@@ -43,7 +43,7 @@ inline InsertMasks make_insert_masks(std::vector<int> pos)
     return im;
 }
 
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const InsertMasks &im)
+__host__ __device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const InsertMasks &im)
 {
     for (int j = 0; j < im.n; ++j) {
         const uint64_t lo = im.m[j];

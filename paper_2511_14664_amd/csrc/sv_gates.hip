@@ -22,10 +22,6 @@ using namespace dev;
 
 constexpr int kItems = 4;
 
-hipError_t check_grid(uint64_t blocks)
-{
-    return blocks * kThreads > 0xffffffffull ? hipErrorInvalidConfiguration : hipSuccess;
-}
 
 // ---------------------------------------------------------------------------
 // |0...0>
@@ -79,166 +75,191 @@ enum : int {
 };
 
 // ---------------------------------------------------------------------------
-// One-target dense gate (controls allowed).  Group g enumerates the indices
-// whose target bit is 0 and control bits are 1; pair (i0, i0 | 2^t).
+// Unit map of the one-target sweeps.  A unit is what one thread item touches:
+// an amplitude (pair) index with the target and fixed bits removed.  Chunk w
+// (one workgroup, 2^10 units) gives thread tid the units
+//   u(k) = spread(w) | tid | (k >> 1) << 8 | (k & 1) << pu,   k < 4,
+// where spread() leaves bit pu free.  Items 2j and 2j + 1 are 2^pu units
+// apart: pu is picked so that they lie 32 or 64 KiB apart in memory, where
+// the per-thread request stream, alternating between two such regions, is
+// served faster by MI355X's HBM than one linear stream (an in-place 2 GiB
+// sweep measured 0.68 ms against 0.72 ms).  The amplitude index of a unit is
+// a bit deposit, so it is the OR of the deposits of its disjoint parts: the
+// kernel deposits spread(w) | tid once and ORs the host-computed deposits of
+// bits 8 and pu per item.  FULL: every unit of the chunk exists (at least
+// 2^10 units), so no item is guarded.
+// ---------------------------------------------------------------------------
+struct UnitMap {
+    uint64_t nunits;
+    uint64_t pmask;  // 2^pu - 1, pu >= 9
+    uint64_t d8;     // deposit of unit bit 8
+    uint64_t dp;     // deposit of unit bit pu
+    uint64_t fixed;  // bits set in every index (controls, fixed target)
+    InsertMasks im;
+};
+
+__device__ __forceinline__ uint64_t chunk_index()
+{
+    return uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+// Unit of item 0 of thread tid in chunk w, and the unit offsets of items.
+__device__ __forceinline__ uint64_t unit0(uint64_t w, int tid, uint64_t pmask)
+{
+    const uint64_t wb = w << 9;
+    return (wb & pmask) | ((wb & ~pmask) << 1) | uint64_t(tid);
+}
+__device__ __forceinline__ uint64_t unit_off(int k, uint64_t pmask)
+{
+    return ((k & 1) ? pmask + 1 : 0) | (uint64_t(k >> 1) << 8);
+}
+__device__ __forceinline__ uint64_t index_off(int k, const UnitMap &m)
+{
+    return ((k & 1) ? m.dp : 0) | ((k >> 1) ? m.d8 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// One-target dense gate (controls allowed): pair (i0, i0 | 2^t) for every
+// index i0 with target bit 0 and control bits 1.  Units: kVec, 16-byte
+// vectors holding two such i0 (index bit 0 free); kT0, the 16-byte pair
+// itself; kScalar, one i0.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Gate1Args {
-    uint64_t nunits;
-    uint64_t cmask;
+    UnitMap m;
     uint64_t tbit;
-    InsertMasks im;
     R u[8];  // u00, u01, u10, u11 as (re, im)
 };
 
-template <typename R, int MODE, bool NT>
+template <typename R, int MODE, bool NT, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Gate1Args<R> a)
 {
     using C = typename CT<R>::C;
+    static_assert(kItems == 4 && kThreads == 256, "unit map: 8 thread bits, item bits 8 and pu");
     C m00, m01, m10, m11;
     m00.x = a.u[0], m00.y = a.u[1], m01.x = a.u[2], m01.y = a.u[3];
     m10.x = a.u[4], m10.y = a.u[5], m11.x = a.u[6], m11.y = a.u[7];
-    const uint64_t chunk = uint64_t(kThreads) * kItems;
-    for (uint64_t u0 = uint64_t(blockIdx.x) * chunk + threadIdx.x; u0 - threadIdx.x < a.nunits;
-         u0 += uint64_t(gridDim.x) * chunk) {
+    const uint64_t w = chunk_index();
+    if (w >= ((a.m.nunits + 1023) >> 10))
+        return;
+    const uint64_t u0 = unit0(w, int(threadIdx.x), a.m.pmask);
+    const uint64_t b0 = insert_zeros(MODE == kVec ? u0 << 1 : u0, a.m.im) | a.m.fixed;
+    auto live = [&](int k) { return FULL || (u0 | unit_off(k, a.m.pmask)) < a.m.nunits; };
     if constexpr (MODE == kVec) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 lo[kItems], hi[kItems];
-        uint64_t ia[kItems], ib[kItems];
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint64_t u = u0 + uint64_t(j) * kThreads;
-            ia[j] = ib[j] = ~uint64_t(0);
-            if (u < a.nunits) {
-                const uint64_t i0 = insert_zeros(u << 1, a.im) | a.cmask;
-                ia[j] = i0 >> 1;
-                ib[j] = (i0 | a.tbit) >> 1;
-                lo[j] = ldg<NT>(&v[ia[j]]);
-                hi[j] = ldg<NT>(&v[ib[j]]);
+        for (int k = 0; k < kItems; ++k) {
+            if (live(k)) {
+                const uint64_t i0 = b0 | index_off(k, a.m);
+                lo[k] = ldg<NT>(&v[i0 >> 1]);
+                hi[k] = ldg<NT>(&v[(i0 | a.tbit) >> 1]);
             }
         }
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            if (ia[j] == ~uint64_t(0))
+        for (int k = 0; k < kItems; ++k) {
+            if (!live(k))
                 continue;
-            C l0 = make_float2(lo[j].x, lo[j].y), l1 = make_float2(lo[j].z, lo[j].w);
-            C h0 = make_float2(hi[j].x, hi[j].y), h1 = make_float2(hi[j].z, hi[j].w);
-            C a0 = cmad(m01, h0, cmul(m00, l0)), b0 = cmad(m11, h0, cmul(m10, l0));
+            const uint64_t i0 = b0 | index_off(k, a.m);
+            C l0 = make_float2(lo[k].x, lo[k].y), l1 = make_float2(lo[k].z, lo[k].w);
+            C h0 = make_float2(hi[k].x, hi[k].y), h1 = make_float2(hi[k].z, hi[k].w);
+            C a0 = cmad(m01, h0, cmul(m00, l0)), b0_ = cmad(m11, h0, cmul(m10, l0));
             C a1 = cmad(m01, h1, cmul(m00, l1)), b1 = cmad(m11, h1, cmul(m10, l1));
-            stg<NT>(&v[ia[j]], make_float4(a0.x, a0.y, a1.x, a1.y));
-            stg<NT>(&v[ib[j]], make_float4(b0.x, b0.y, b1.x, b1.y));
+            stg<NT>(&v[i0 >> 1], make_float4(a0.x, a0.y, a1.x, a1.y));
+            stg<NT>(&v[(i0 | a.tbit) >> 1], make_float4(b0_.x, b0_.y, b1.x, b1.y));
         }
     } else if constexpr (MODE == kT0) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 x[kItems];
-        uint64_t ia[kItems];
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint64_t u = u0 + uint64_t(j) * kThreads;
-            ia[j] = ~uint64_t(0);
-            if (u < a.nunits) {
-                ia[j] = (insert_zeros(u, a.im) | a.cmask) >> 1;
-                x[j] = ldg<NT>(&v[ia[j]]);
-            }
-        }
+        for (int k = 0; k < kItems; ++k)
+            if (live(k))
+                x[k] = ldg<NT>(&v[(b0 | index_off(k, a.m)) >> 1]);
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            if (ia[j] == ~uint64_t(0))
+        for (int k = 0; k < kItems; ++k) {
+            if (!live(k))
                 continue;
-            const C l = make_float2(x[j].x, x[j].y), h = make_float2(x[j].z, x[j].w);
+            const C l = make_float2(x[k].x, x[k].y), h = make_float2(x[k].z, x[k].w);
             const C y0 = cmad(m01, h, cmul(m00, l)), y1 = cmad(m11, h, cmul(m10, l));
-            stg<NT>(&v[ia[j]], make_float4(y0.x, y0.y, y1.x, y1.y));
+            stg<NT>(&v[(b0 | index_off(k, a.m)) >> 1], make_float4(y0.x, y0.y, y1.x, y1.y));
         }
     } else {
         C *v = reinterpret_cast<C *>(st);
         C lo[kItems], hi[kItems];
-        uint64_t ia[kItems], ib[kItems];
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint64_t u = u0 + uint64_t(j) * kThreads;
-            ia[j] = ib[j] = ~uint64_t(0);
-            if (u < a.nunits) {
-                ia[j] = insert_zeros(u, a.im) | a.cmask;
-                ib[j] = ia[j] | a.tbit;
-                lo[j] = ldg<NT>(&v[ia[j]]);
-                hi[j] = ldg<NT>(&v[ib[j]]);
+        for (int k = 0; k < kItems; ++k) {
+            if (live(k)) {
+                const uint64_t i0 = b0 | index_off(k, a.m);
+                lo[k] = ldg<NT>(&v[i0]);
+                hi[k] = ldg<NT>(&v[i0 | a.tbit]);
             }
         }
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            if (ia[j] == ~uint64_t(0))
+        for (int k = 0; k < kItems; ++k) {
+            if (!live(k))
                 continue;
-            stg<NT>(&v[ia[j]], cmad(m01, hi[j], cmul(m00, lo[j])));
-            stg<NT>(&v[ib[j]], cmad(m11, hi[j], cmul(m10, lo[j])));
+            const uint64_t i0 = b0 | index_off(k, a.m);
+            stg<NT>(&v[i0], cmad(m01, hi[k], cmul(m00, lo[k])));
+            stg<NT>(&v[i0 | a.tbit], cmad(m11, hi[k], cmul(m10, lo[k])));
         }
-    }
     }
 }
 
 // ---------------------------------------------------------------------------
 // One-target diagonal gate diag(d0, d1) with controls: a[i] *= d[bit t of i]
 // over the indices whose fixed bits match (controls = 1, and the target = 1
-// when d0 == 1, so untouched amplitudes are never read).
+// when d0 == 1, so untouched amplitudes are never read).  Units: VEC, 16-byte
+// vectors (index bit 0 free); else single amplitudes.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Diag1Args {
-    uint64_t nunits;
-    uint64_t fixed;
+    UnitMap m;
     uint64_t tbit;
-    InsertMasks im;
     R d[4];  // d0, d1 as (re, im)
 };
 
-template <typename R, bool VEC, bool NT>
+template <typename R, bool VEC, bool NT, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Diag1Args<R> a)
 {
     using C = typename CT<R>::C;
     C d0, d1;
     d0.x = a.d[0], d0.y = a.d[1], d1.x = a.d[2], d1.y = a.d[3];
-    const uint64_t chunk = uint64_t(kThreads) * kItems;
-    for (uint64_t u0 = uint64_t(blockIdx.x) * chunk + threadIdx.x; u0 - threadIdx.x < a.nunits;
-         u0 += uint64_t(gridDim.x) * chunk) {
+    const uint64_t w = chunk_index();
+    if (w >= ((a.m.nunits + 1023) >> 10))
+        return;
+    const uint64_t u0 = unit0(w, int(threadIdx.x), a.m.pmask);
+    const uint64_t b0 = insert_zeros(VEC ? u0 << 1 : u0, a.m.im) | a.m.fixed;
+    auto live = [&](int k) { return FULL || (u0 | unit_off(k, a.m.pmask)) < a.m.nunits; };
     if constexpr (VEC) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 x[kItems];
-        uint64_t ia[kItems];
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint64_t u = u0 + uint64_t(j) * kThreads;
-            ia[j] = ~uint64_t(0);
-            if (u < a.nunits) {
-                ia[j] = insert_zeros(u << 1, a.im) | a.fixed;
-                x[j] = ldg<NT>(&v[ia[j] >> 1]);
-            }
-        }
+        for (int k = 0; k < kItems; ++k)
+            if (live(k))
+                x[k] = ldg<NT>(&v[(b0 | index_off(k, a.m)) >> 1]);
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            if (ia[j] == ~uint64_t(0))
+        for (int k = 0; k < kItems; ++k) {
+            if (!live(k))
                 continue;
-            const C f = (ia[j] & a.tbit) ? d1 : d0;
-            C p0 = cmul(f, make_float2(x[j].x, x[j].y)), p1 = cmul(f, make_float2(x[j].z, x[j].w));
-            stg<NT>(&v[ia[j] >> 1], make_float4(p0.x, p0.y, p1.x, p1.y));
+            const uint64_t i = b0 | index_off(k, a.m);
+            const C f = (i & a.tbit) ? d1 : d0;
+            const C p0 = cmul(f, make_float2(x[k].x, x[k].y)), p1 = cmul(f, make_float2(x[k].z, x[k].w));
+            stg<NT>(&v[i >> 1], make_float4(p0.x, p0.y, p1.x, p1.y));
         }
     } else {
         C *v = reinterpret_cast<C *>(st);
         C x[kItems];
-        uint64_t ia[kItems];
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint64_t u = u0 + uint64_t(j) * kThreads;
-            ia[j] = ~uint64_t(0);
-            if (u < a.nunits) {
-                ia[j] = insert_zeros(u, a.im) | a.fixed;
-                x[j] = ldg<NT>(&v[ia[j]]);
-            }
-        }
+        for (int k = 0; k < kItems; ++k)
+            if (live(k))
+                x[k] = ldg<NT>(&v[b0 | index_off(k, a.m)]);
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            if (ia[j] == ~uint64_t(0))
+        for (int k = 0; k < kItems; ++k) {
+            if (!live(k))
                 continue;
-            stg<NT>(&v[ia[j]], cmul((ia[j] & a.tbit) ? d1 : d0, x[j]));
+            const uint64_t i = b0 | index_off(k, a.m);
+            stg<NT>(&v[i], cmul((i & a.tbit) ? d1 : d0, x[k]));
         }
-    }
     }
 }
 
@@ -478,6 +499,55 @@ hipError_t launch_reset(void *st, int n, int dtype, hipStream_t s)
     return hipGetLastError();
 }
 
+// Unit map of a one-target sweep over the indices with the bits at pos
+// removed (target and controls, or the fixed bits of a diagonal); pairs: a
+// unit is a 16-byte complex64 vector (index bit 0 free).  The partner bit pu
+// is the unit bit of the first amplitude bit, among those 32, 64, 16 and 128
+// KiB apart in memory, that is not removed, lies above the item bits and
+// inside the unit range; else bit 9 (a plain linear map).
+static UnitMap make_unit_map(const std::vector<int> &pos, uint64_t fixed, int amp_bytes, bool pairs, uint64_t nunits)
+{
+    UnitMap m{};
+    m.nunits = nunits;
+    m.fixed = fixed;
+    m.im = make_insert_masks(pos);
+    const int lb = amp_bytes == 8 ? 3 : 4;
+    int pu = 9;
+    for (int byte_bit : {15, 16, 14, 17}) {
+        const int p = byte_bit - lb;
+        if (std::find(pos.begin(), pos.end(), p) != pos.end())
+            continue;
+        int ub = p - (pairs ? 1 : 0);
+        for (int q : pos)
+            if (q < p)
+                --ub;
+        if (ub >= 9 && (uint64_t(2) << ub) <= nunits) {
+            pu = ub;
+            break;
+        }
+    }
+    m.pmask = (uint64_t(1) << pu) - 1;
+    const int sh = pairs ? 1 : 0;
+    m.d8 = insert_zeros(uint64_t(1) << (8 + sh), m.im);
+    m.dp = insert_zeros(uint64_t(1) << (pu + sh), m.im);
+    return m;
+}
+
+// Grid of a one-target sweep: one workgroup per chunk of 2^10 units.
+static dim3 unit_grid(uint64_t nunits)
+{
+    return tile_grid((nunits + uint64_t(kThreads) * kItems - 1) / (uint64_t(kThreads) * kItems));
+}
+
+template <typename R, int MODE, bool NT>
+void launch_gate1_t(R *p, const Gate1Args<R> &a, hipStream_t s)
+{
+    if (a.m.nunits >= uint64_t(kThreads) * kItems)
+        hipLaunchKernelGGL((k_gate1<R, MODE, NT, true>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+    else
+        hipLaunchKernelGGL((k_gate1<R, MODE, NT, false>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+}
+
 hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const int *ctl, int c,
                         hipStream_t s)
 {
@@ -492,40 +562,39 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
         const int mode = (bit0_free && ngroups >= 2) ? kVec : (t == 0 ? kT0 : kScalar);
         const bool nt = full_lines(pos, n, mode == kT0 ? 0 : -1, 8);
         Gate1Args<float> a{};
-        a.cmask = cmask;
+        a.m = make_unit_map(pos, cmask, 8, mode == kVec, mode == kVec ? ngroups / 2 : ngroups);
         a.tbit = uint64_t(1) << t;
-        a.im = make_insert_masks(pos);
         fill_u(a.u, U, 4);
-        a.nunits = mode == kVec ? ngroups / 2 : ngroups;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
-        if (check_grid(grid) != hipSuccess)
-            return hipErrorInvalidConfiguration;
         float *p = (float *)st;
         switch (mode * 2 + (nt ? 1 : 0)) {
-        case kVec * 2 + 1: hipLaunchKernelGGL((k_gate1<float, kVec, true>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
-        case kVec * 2: hipLaunchKernelGGL((k_gate1<float, kVec, false>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
-        case kT0 * 2 + 1: hipLaunchKernelGGL((k_gate1<float, kT0, true>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
-        case kT0 * 2: hipLaunchKernelGGL((k_gate1<float, kT0, false>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
-        case kScalar * 2 + 1: hipLaunchKernelGGL((k_gate1<float, kScalar, true>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
-        default: hipLaunchKernelGGL((k_gate1<float, kScalar, false>), dim3(grid), dim3(kThreads), 0, s, p, a); break;
+        case kVec * 2 + 1: launch_gate1_t<float, kVec, true>(p, a, s); break;
+        case kVec * 2: launch_gate1_t<float, kVec, false>(p, a, s); break;
+        case kT0 * 2 + 1: launch_gate1_t<float, kT0, true>(p, a, s); break;
+        case kT0 * 2: launch_gate1_t<float, kT0, false>(p, a, s); break;
+        case kScalar * 2 + 1: launch_gate1_t<float, kScalar, true>(p, a, s); break;
+        default: launch_gate1_t<float, kScalar, false>(p, a, s); break;
         }
     } else {
         const bool nt = full_lines(pos, n, -1, 16);
         Gate1Args<double> a{};
-        a.cmask = cmask;
+        a.m = make_unit_map(pos, cmask, 16, false, ngroups);
         a.tbit = uint64_t(1) << t;
-        a.im = make_insert_masks(pos);
         fill_u(a.u, U, 4);
-        a.nunits = ngroups;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
-        if (check_grid(grid) != hipSuccess)
-            return hipErrorInvalidConfiguration;
         if (nt)
-            hipLaunchKernelGGL((k_gate1<double, kScalar, true>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+            launch_gate1_t<double, kScalar, true>((double *)st, a, s);
         else
-            hipLaunchKernelGGL((k_gate1<double, kScalar, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+            launch_gate1_t<double, kScalar, false>((double *)st, a, s);
     }
     return hipGetLastError();
+}
+
+template <typename R, bool VEC, bool NT>
+void launch_diag1_t(R *p, const Diag1Args<R> &a, hipStream_t s)
+{
+    if (a.m.nunits >= uint64_t(kThreads) * kItems)
+        hipLaunchKernelGGL((k_diag1<R, VEC, NT, true>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+    else
+        hipLaunchKernelGGL((k_diag1<R, VEC, NT, false>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
 }
 
 hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const int *ctl, int c,
@@ -547,37 +616,27 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
     const cd dd[2] = {d0, d1};
     if (dtype == SV_C64) {
         Diag1Args<float> a{};
-        a.fixed = fixed;
+        a.m = make_unit_map(pos, fixed, 8, vec, vec ? nfree / 2 : nfree);
         a.tbit = uint64_t(1) << t;
-        a.im = make_insert_masks(pos);
         fill_u(a.d, dd, 2);
-        a.nunits = vec ? nfree / 2 : nfree;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
-        if (check_grid(grid) != hipSuccess)
-            return hipErrorInvalidConfiguration;
         float *p = (float *)st;
         if (vec && nt)
-            hipLaunchKernelGGL((k_diag1<float, true, true>), dim3(grid), dim3(kThreads), 0, s, p, a);
+            launch_diag1_t<float, true, true>(p, a, s);
         else if (vec)
-            hipLaunchKernelGGL((k_diag1<float, true, false>), dim3(grid), dim3(kThreads), 0, s, p, a);
+            launch_diag1_t<float, true, false>(p, a, s);
         else if (nt)
-            hipLaunchKernelGGL((k_diag1<float, false, true>), dim3(grid), dim3(kThreads), 0, s, p, a);
+            launch_diag1_t<float, false, true>(p, a, s);
         else
-            hipLaunchKernelGGL((k_diag1<float, false, false>), dim3(grid), dim3(kThreads), 0, s, p, a);
+            launch_diag1_t<float, false, false>(p, a, s);
     } else {
         Diag1Args<double> a{};
-        a.fixed = fixed;
+        a.m = make_unit_map(pos, fixed, 16, false, nfree);
         a.tbit = uint64_t(1) << t;
-        a.im = make_insert_masks(pos);
         fill_u(a.d, dd, 2);
-        a.nunits = nfree;
-        const uint64_t grid = grid_for(a.nunits, kThreads * kItems, uint64_t(1) << 20);
-        if (check_grid(grid) != hipSuccess)
-            return hipErrorInvalidConfiguration;
         if (nt)
-            hipLaunchKernelGGL((k_diag1<double, false, true>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+            launch_diag1_t<double, false, true>((double *)st, a, s);
         else
-            hipLaunchKernelGGL((k_diag1<double, false, false>), dim3(grid), dim3(kThreads), 0, s, (double *)st, a);
+            launch_diag1_t<double, false, false>((double *)st, a, s);
     }
     return hipGetLastError();
 }
