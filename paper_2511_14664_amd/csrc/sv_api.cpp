@@ -481,6 +481,7 @@ struct PassWork : PassGroup {
     uint64_t bytes = 0;
     uint64_t nterm_max = 0;  // bound on the pass's phase terms
     bool split = false;      // complex64 blocks as split BF16 products (SV_PREC_BF16X6)
+    bool presplit = false;   // split, no phase terms: matrices staged split (pass_presplit)
 };
 
 // Monomials of a phase gate's angle: a diagonal gate on qubits Q (targets,
@@ -601,7 +602,7 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
     for (int b = 0; b < T; ++b)
         slot_of[tb[b]] = b;
     const uint64_t S = amp_bytes(h->dtype);
-    const uint64_t mat16 = (256 * S + 255) & ~uint64_t(255);
+    const uint64_t mat16 = w.presplit ? kPresplitBytes : (256 * S + 255) & ~uint64_t(255);
     const uint64_t terms = w.off + ((nsub * sizeof(PassSub) + 255) & ~uint64_t(255));
     const uint64_t mats = terms + ((w.nterm_max * sizeof(PassTerm) + 255) & ~uint64_t(255));
     if (!launch) {
@@ -773,7 +774,10 @@ int stage_launch_pass(sv_state *h, const std::vector<Block> &gates, const PassWo
                     for (int c = 0; c < 16; ++c)
                         if ((r >> bv.k) == (c >> bv.k))
                             u4.U[size_t(r) * 16 + c] = bv.U[size_t(r & (dk - 1)) * dk + (c & (dk - 1))];
-                stage_matrix(h, u4, d.u_off + var * mat16);
+                if (w.presplit)
+                    pass_presplit(u4.U.data(), static_cast<char *>(h->h_arena) + d.u_off + var * mat16);
+                else
+                    stage_matrix(h, u4, d.u_off + var * mat16);
             }
         }
         return SV_OK;
@@ -847,8 +851,12 @@ int run_pass_plan(sv_state *h, const std::vector<Block> &gates, const std::vecto
                 w.nterm_max += uint64_t(1 << kMaxPhaseQubits) * (w.front[j].size() + w.back[j].size());
                 nmat += uint64_t(1) << __builtin_popcountll(w.vq[j]);
             }
+            // the launch runs the phase-free kernel exactly when no block has
+            // phase gates (stage_launch_pass)
+            w.presplit = w.split && w.nterm_max == 0;
             w.bytes = ((w.subs.size() * sizeof(PassSub) + 255) & ~uint64_t(255)) +
-                      ((w.nterm_max * sizeof(PassTerm) + 255) & ~uint64_t(255)) + nmat * mat16;
+                      ((w.nterm_max * sizeof(PassTerm) + 255) & ~uint64_t(255)) +
+                      nmat * (w.presplit ? kPresplitBytes : mat16);
         } else {
             for (const Group &g : w.subs) {
                 const Block &first = gates[size_t(g.members[0])];

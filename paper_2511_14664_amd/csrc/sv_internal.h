@@ -208,6 +208,14 @@ struct PassSub {
 // Blocks carrying phase terms per pass (rows of the kernel's per-tile angle
 // table in LDS); a pass with more runs as ordinary sweeps.
 constexpr int kMaxTermBlocks = 16;
+// A split-BF16 pass block without phase terms carries its 16 x 16 matrix
+// already split: per lane of the MFMA wave, 3 parts x (real, imaginary
+// output rows) x 4 packed BF16 pairs (pass_presplit).
+constexpr uint64_t kPresplitBytes = 3 * 2 * 64 * 16;
+// Write the split A fragments of the 16 x 16 complex matrix U (row-major,
+// FP64, rounded to FP32 first) to dst (kPresplitBytes): the same exact
+// three-part BF16 split that the pass kernel applies to per-tile matrices.
+void pass_presplit(const std::complex<double> *U, void *dst);
 static_assert(sizeof(PassSub) == 128, "pass block descriptor layout");
 // One monomial of a per-tile phase: where the tile's outer index bits cover
 // omask (physical bits), entry (r, c) of the block matrix gains the angle

@@ -31,6 +31,8 @@
 // phases are folded into the block's matrix as a column phase (applied before
 // the block) or a row phase (after it), from a list of monomials (outer-bit
 // mask, slot mask, angle) per block evaluated once per tile into LDS.
+#include <cstring>
+
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -375,6 +377,10 @@ __device__ __forceinline__ floatx4 mma_split6(const uint32_t *ah, const uint32_t
     return acc;
 }
 
+// PHASES: some block carries per-tile phase terms; the blocks' matrices are
+// FP32 and every workgroup applies its tile's phases and splits them.
+// Otherwise the matrices come split already (pass_presplit_layout), and the
+// kernel only loads each lane's A fragments.
 template <bool PHASES>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASES ? 4 : 5)))
 void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__restrict__ subs, int nsub,
@@ -395,14 +401,17 @@ void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__res
     const int q = lane / 16, j16 = lane % 16;
 
     const uint64_t tbase = insert_zeros(uint64_t(blockIdx.y) * gridDim.x + blockIdx.x, a.outer);
-    // this lane's FP32 fragment of block sb: U[j16][4 q + r], r < 4
-    auto load_u = [&](int sb, float *ur, float *ui) {
-        const PassSub &d = subs[sb];
+    auto variant = [&](const PassSub &d) {
         uint32_t var = 0;
         for (uint32_t v = 0; v < d.nvar; ++v)
             var |= uint32_t((tbase >> d.vpos[v]) & 1) << v;
+        return var;
+    };
+    // PHASES: this lane's FP32 fragment of block sb, U[j16][4 q + r], r < 4
+    auto load_u = [&](int sb, float *ur, float *ui) {
+        const PassSub &d = subs[sb];
         const float4 *U = reinterpret_cast<const float4 *>(reinterpret_cast<const C *>(mats + d.u_off) +
-                                                           size_t(var) * (D * D) + j16 * D + 4 * q);
+                                                           size_t(variant(d)) * (D * D) + j16 * D + 4 * q);
         const float4 u0 = U[0], u1 = U[1];
         ur[0] = u0.x;
         ui[0] = u0.y;
@@ -413,8 +422,27 @@ void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__res
         ur[3] = u1.z;
         ui[3] = u1.w;
     };
+    // otherwise: this lane's split A fragments of block sb, in the order
+    // (h, real rows), (h, imaginary rows), (m, real), (m, imag), (l, real),
+    // (l, imag), four registers each
+    auto load_a = [&](int sb, uint32_t *A) {
+        const PassSub &d = subs[sb];
+        const uint4 *P = reinterpret_cast<const uint4 *>(mats + d.u_off + size_t(variant(d)) * kPresplitBytes) + lane;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const uint4 v = P[i * 64];
+            A[4 * i] = v.x;
+            A[4 * i + 1] = v.y;
+            A[4 * i + 2] = v.z;
+            A[4 * i + 3] = v.w;
+        }
+    };
     float ur[4], ui[4];
-    load_u(0, ur, ui);  // in flight with the tile's loads
+    uint32_t an[PHASES ? 1 : 24];
+    if constexpr (PHASES)
+        load_u(0, ur, ui);  // in flight with the tile's loads
+    else
+        load_a(0, an);
 
     // per-tile phase angles, as in k_pass (fixed-point turns, 32 bits)
     __shared__ uint32_t angles[PHASES ? kMaxTermBlocks * 32 : 1];
@@ -451,28 +479,37 @@ void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__res
         }
         for (int sb = 0; sb < nsub; ++sb) {
             const PassSub &d = subs[sb];
-            if (PHASES && d.nterm > 0) {
-                // U[r][c] exp(i (front(c) + back(r))), r = j16, c = 4 q + k
-                const uint32_t *row = angles + d.pslot * 32;
-                const uint32_t tb = row[16 + j16];
+            // A operands: real rows [Ur, -Ui], imaginary rows [Ui, Ur], split
+            uint32_t A[24];
+            if constexpr (PHASES) {
+                if (d.nterm > 0) {
+                    // U[r][c] exp(i (front(c) + back(r))), r = j16, c = 4 q + k
+                    const uint32_t *row = angles + d.pslot * 32;
+                    const uint32_t tb = row[16 + j16];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        float sn, cs;
+                        turn_sincos(uint32_t(row[4 * q + k] + tb), sn, cs);
+                        const float r0 = ur[k], i0 = ui[k];
+                        ur[k] = r0 * cs - i0 * sn;
+                        ui[k] = r0 * sn + i0 * cs;
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    float sn, cs;
-                    turn_sincos(uint32_t(row[4 * q + k] + tb), sn, cs);
-                    const float r0 = ur[k], i0 = ui[k];
-                    ur[k] = r0 * cs - i0 * sn;
-                    ui[k] = r0 * sn + i0 * cs;
+                    split3(ur[k], -ui[k], A[k], A[8 + k], A[16 + k]);
+                    split3(ui[k], ur[k], A[4 + k], A[12 + k], A[20 + k]);
                 }
-            }
-            // A operands: real rows [Ur, -Ui], imaginary rows [Ui, Ur], split
-            uint32_t arh[4], arm[4], arl[4], aih[4], aim[4], ail[4];
+                if (sb + 1 < nsub)
+                    load_u(sb + 1, ur, ui);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                split3(ur[k], -ui[k], arh[k], arm[k], arl[k]);
-                split3(ui[k], ur[k], aih[k], aim[k], ail[k]);
+                for (int i = 0; i < 24; ++i)
+                    A[i] = an[i];
+                if (sb + 1 < nsub)
+                    load_a(sb + 1, an);
             }
-            if (sb + 1 < nsub)
-                load_u(sb + 1, ur, ui);
+            const uint32_t *arh = A, *aih = A + 4, *arm = A + 8, *aim = A + 12, *arl = A + 16, *ail = A + 20;
             // LDS byte offsets (XOR-linear parts, as in k_pass): lane part
             // from (q, j16), register part from the row r, wave-uniform part
             // from the group set
@@ -538,6 +575,52 @@ hipError_t launch_pass_t(void *st, const TileArgs &a, const void *subs, int nsub
 }
 
 }  // namespace
+
+// BF16 bits of x rounded to nearest even (x finite), as v_cvt_pk_bf16_f32.
+static uint32_t bf16_rne_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// Host twin of split3: (a, b) -> packed parts h, m, l.
+static void split3_host(float a, float b, uint32_t &h, uint32_t &m, uint32_t &l)
+{
+    auto part = [](float x, float &rest) {
+        const uint32_t bits = bf16_rne_bits(x);
+        const uint32_t w = bits << 16;
+        float v;
+        std::memcpy(&v, &w, 4);
+        rest = x - v;  // exact
+        return bits;
+    };
+    float ra, rb, sa, sb;
+    const uint32_t ha = part(a, ra), hb = part(b, rb);
+    const uint32_t ma = part(ra, sa), mb = part(rb, sb);
+    h = ha | (hb << 16);
+    m = ma | (mb << 16);
+    l = bf16_rne_bits(sa) | (bf16_rne_bits(sb) << 16);
+}
+
+void pass_presplit(const std::complex<double> *U, void *dst)
+{
+    uint32_t *o = static_cast<uint32_t *>(dst);
+    for (int lane = 0; lane < 64; ++lane) {
+        const int q = lane / 16, j = lane % 16;
+        for (int k = 0; k < 4; ++k) {
+            const std::complex<double> u = U[j * 16 + 4 * q + k];
+            const float re = float(u.real()), im = float(u.imag());
+            uint32_t p[2][3];
+            split3_host(re, -im, p[0][0], p[0][1], p[0][2]);
+            split3_host(im, re, p[1][0], p[1][1], p[1][2]);
+            for (int part = 0; part < 3; ++part)
+                for (int rt = 0; rt < 2; ++rt)
+                    o[((part * 2 + rt) * 64 + lane) * 4 + k] = p[rt][part];
+        }
+    }
+}
 
 int pass_tile_log(int dtype)
 {
