@@ -57,6 +57,27 @@ __device__ __forceinline__ double prob(C a)
     return x * x + y * y;
 }
 
+// Read-only sweeps read every byte once: loads carry the nontemporal hint
+// (a 2 GiB read measured 0.30 ms with it, 0.33 ms without).
+typedef float rd_f32x2 __attribute__((ext_vector_type(2)));
+typedef float rd_f32x4 __attribute__((ext_vector_type(4)));
+typedef double rd_f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ldnt(const float2 *p)
+{
+    const rd_f32x2 q = __builtin_nontemporal_load(reinterpret_cast<const rd_f32x2 *>(p));
+    return make_float2(q.x, q.y);
+}
+__device__ __forceinline__ float4 ldnt(const float4 *p)
+{
+    const rd_f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const rd_f32x4 *>(p));
+    return make_float4(q.x, q.y, q.z, q.w);
+}
+__device__ __forceinline__ double2 ldnt(const double2 *p)
+{
+    const rd_f64x2 q = __builtin_nontemporal_load(reinterpret_cast<const rd_f64x2 *>(p));
+    return make_double2(q.x, q.y);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -230,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_expect_z(const R *__restrict__ st,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = h0 + uint64_t(u) * kThreads + threadIdx.x;
-            x[u] = v[i < a.nelem ? i : 0];
+            x[u] = ldnt(&v[i < a.nelem ? i : 0]);
         }
         __builtin_amdgcn_sched_barrier(0);
         double w[U];
@@ -312,18 +333,38 @@ __global__ __launch_bounds__(kThreads) void k_expect_xy(const R *__restrict__ st
 // ---------------------------------------------------------------------------
 // Sampling.  Stage 1: sums of |a|^2 over blocks of 2^lbs amplitudes.
 // ---------------------------------------------------------------------------
+// The block is read in steps of 16 16-byte loads per thread, all issued
+// before the first is used (indices past the block end: its first vector,
+// weight 0).
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_block_sums(const R *__restrict__ st, double *__restrict__ bs,
                                                          int lbs)
 {
-    using C = typename CT<R>::C;
+    constexpr bool F32 = std::is_same<R, float>::value;
+    using V = typename std::conditional<F32, float4, double2>::type;  // 16 bytes
+    constexpr int NL = 16;
     __shared__ double sh[4];
-    const C *v = reinterpret_cast<const C *>(st);
-    const uint64_t base = uint64_t(blockIdx.x) << lbs;
-    const uint32_t bsz = 1u << lbs;
+    const uint32_t nv = F32 ? (1u << lbs) >> 1 : (1u << lbs);  // vectors in the block (lbs >= 1)
+    const V *v = reinterpret_cast<const V *>(st) + uint64_t(blockIdx.x) * nv;
     double acc = 0.0;
-    for (uint32_t e = threadIdx.x; e < bsz; e += kThreads)
-        acc += prob(v[base + e]);
+    for (uint32_t e0 = 0; e0 < nv; e0 += NL * kThreads) {
+        V x[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const uint32_t e = e0 + uint32_t(k * kThreads) + threadIdx.x;
+            x[k] = ldnt(&v[e < nv ? e : 0]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            double p;
+            if constexpr (F32)
+                p = prob(make_float2(x[k].x, x[k].y)) + prob(make_float2(x[k].z, x[k].w));
+            else
+                p = prob(x[k]);
+            acc += e0 + uint32_t(k * kThreads) + threadIdx.x < nv ? p : 0.0;
+        }
+    }
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0)
         bs[blockIdx.x] = acc;
@@ -537,7 +578,7 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) {
-                const float4 q = v4[tid + k * kThreads];
+                const float4 q = ldnt(&v4[tid + k * kThreads]);
                 const double p0 = double(q.x) * q.x + double(q.y) * q.y;
                 const double p1 = double(q.z) * q.z + double(q.w) * q.w;
                 if constexpr (KSUM) {
@@ -558,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
             double s0 = 0.0;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) {
-                const double2 q = v2[tid + k * kThreads];
+                const double2 q = ldnt(&v2[tid + k * kThreads]);
                 const double p0 = q.x * q.x + q.y * q.y;
                 if constexpr (KSUM)
                     s0 += p0;
