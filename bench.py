@@ -259,7 +259,8 @@ def main():
         "config": {"workload": f"{n}-qubit random layered circuit (U3 on every qubit + CNOT/CZ on a random "
                                f"matching, depth 20, {len(gates)} gates), {args.dtype}, "
                                + (f"LDS passes of <= {args.pass_qubits} qubits (fused 4-qubit blocks on the matrix "
-                                  f"cores, {PREC_LABEL[args.precision]})" if args.mode == "passes"
+                                  f"cores, {PREC_LABEL[args.precision] if dtype == B.SV_C64 else 'FP64 products'})"
+                                  if args.mode == "passes"
                                   else f"{args.mode} fusion <= {args.max_fused} qubits")
                                + f", + 6-bit index exchange, 10-qubit marginal, "
                                f"{len(terms)} Z-string expectations, 1000 shots",

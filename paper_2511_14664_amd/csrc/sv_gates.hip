@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kThreads) void k_reset(R *__restrict__ st, uint64_t
             else
                 z.x = 1.0;
         }
-        v[i] = z;
+        st_nt(&v[i], z);  // streaming store: the state is not read back soon
     }
 }
 
