@@ -52,6 +52,8 @@ def parse():
                     help="native: FP32 (complex64) / FP64 (complex128) arithmetic; bf16x3: three-term BF16 "
                          "split for complex64 5-6-qubit greedy blocks; bf16x6: FP32-accurate six-product split "
                          "BF16 for complex64 pass blocks")
+    ap.add_argument("--separate-readouts", action="store_true",
+                    help="read-outs as three calls (three reads of the state) instead of one sv_readout")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain (unfused) comparison run (batch: every per-circuit baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -122,9 +124,13 @@ def main():
         B.sv_reset(sv.handle)
         st = B.sv_apply_circuit(sv.handle, circ, opts)
         B.sv_swap_bits(sv.handle, 0, n - 6, 6)
-        B.sv_probabilities(sv.handle, marg_q)
-        B.sv_expect_pauli(sv.handle, terms)
-        B.sv_sample(sv.handle, uni)
+        if args.separate_readouts:
+            B.sv_probabilities(sv.handle, marg_q)
+            B.sv_expect_pauli(sv.handle, terms)
+            B.sv_sample(sv.handle, uni)
+        else:
+            # marginal, Z strings and shots from one read of the state
+            B.sv_readout(sv.handle, marg_q, terms, uni)
         return st
 
     log(f"bench: {n} qubits {args.dtype} mode={args.mode} k<={args.max_fused}, {len(gates)} gates")
@@ -263,7 +269,9 @@ def main():
                                   if args.mode == "passes"
                                   else f"{args.mode} fusion <= {args.max_fused} qubits")
                                + f", + 6-bit index exchange, 10-qubit marginal, "
-                               f"{len(terms)} Z-string expectations, 1000 shots",
+                               f"{len(terms)} Z-string expectations, 1000 shots"
+                               + (" (three read-out calls)" if args.separate_readouts
+                                  else " (one sv_readout call)"),
                    "qubits": n, "state_bytes": S << n, "gates": len(gates),
                    "sweeps_per_step": stats["sweeps"] if stats else None, "parallelism": "single GPU"},
         "achieved_GB/s_all_sweeps": round(sweep_bytes / (sweep_ms / 1e3) / 1e9, 1),
@@ -575,8 +583,7 @@ def bench_share(args):
             sweeps += B.sv_apply_circuit(h, circ, opts)["sweeps"]
             if sw is not None:
                 B.sv_swap_bits(h, sw.lo, sw.hi, sw.width)
-        B.sv_probabilities(h, list(range(n - 10, n)))
-        B.sv_sample(h, W.uniforms(7, 1000))
+        B.sv_readout(h, list(range(n - 10, n)), [], W.uniforms(7, 1000))
         return sweeps
 
     log(f"share: {n} qubits {args.dtype}, {ngates} gates, mode {args.mode}")

@@ -257,6 +257,24 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out);
  * int64 host values.  Synchronises. */
 int sv_sample_seeded(sv_handle h, int shots, uint64_t seed, int64_t *out);
 
+/* The three read-outs of Sec. 2.1 "Measurement and Sampling" of one state in
+ * one call: the marginal over qubits[0..m) as sv_probabilities (probs: 2^m
+ * doubles; NULL with m = 0 for none), the expectation values of nterms Pauli
+ * strings as sv_expect_pauli (expect: nterms doubles; nterms = 0 for none),
+ * and `shots` outcomes for the caller's uniforms as sv_sample (samples:
+ * shots int64; shots = 0 for none).  Where every string is a Z string (at
+ * most 32 of them), the state has at least 14 qubits and the marginal's bits
+ * allow it (none of the index bits 9..11 of complex64 or 8..11 of
+ * complex128, counted in physical positions), the three share one read of
+ * the state: the marginal's partial sums, the strings' partial sums and the
+ * totals of 2^12..2^14-amplitude blocks come from one sweep.  Otherwise the
+ * three run one after another.  Results equal those of the separate calls
+ * up to the order of FP64 additions (shots can differ only where a uniform
+ * falls within rounding of a CDF step).
+ * Argument errors as in the separate calls.  Synchronises. */
+int sv_readout(sv_handle h, const int *qubits, int m, double *probs, const char *const *terms, int nterms,
+               double *expect, const double *uniforms, int shots, int64_t *samples);
+
 /* The library's uniform stream, host only (no device work): out[j] = u_{first+j}
  * for j < count, where u_s is the s-th output of SplitMix64 (Steele, Lea, Flood,
  * OOPSLA 2014) started from state `seed`:

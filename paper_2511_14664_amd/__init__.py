@@ -84,6 +84,10 @@ class StateVector:
     def sample_seeded(self, shots: int, seed: int) -> np.ndarray:
         return _b.sv_sample_seeded(self.handle, shots, seed)
 
+    def readout(self, qubits: Optional[Sequence[int]] = None, terms: Sequence[str] = (), uniforms=None):
+        """Marginal, expectation values and samples in one call (one read of the state where possible)."""
+        return _b.sv_readout(self.handle, qubits, terms, uniforms)
+
     def to_host(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         return _b.sv_copy_to_host(self.handle, self.n, self.dtype, first, count)
 

@@ -87,6 +87,7 @@ def _load():
         "sv_expect_pauli_noalloc": ([P, ctypes.POINTER(ctypes.c_char_p), I, P], I),
         "sv_sample": ([P, P, I, P], I),
         "sv_sample_seeded": ([P, I, U64, P], I),
+        "sv_readout": ([P, P, I, P, ctypes.POINTER(ctypes.c_char_p), I, P, P, I, P], I),
         "sv_uniforms": ([U64, U64, I, P], I),
         "sv_copy_to_host": ([P, P, U64, U64], I),
         "sv_copy_from_host": ([P, P, U64, U64], I),
@@ -257,6 +258,22 @@ def sv_sample_seeded(h: int, shots: int, seed: int) -> np.ndarray:
     out = np.empty(max(1, shots), dtype=np.int64)
     _check(_lib.sv_sample_seeded(ctypes.c_void_p(h), shots, seed, out.ctypes.data), "sv_sample_seeded")
     return out[:shots]
+
+
+def sv_readout(h: int, qubits: Optional[Sequence[int]] = None, terms: Sequence[str] = (), uniforms=None):
+    """sv_readout: (marginal or None, expectation values, samples) of one state."""
+    want_p = qubits is not None
+    q = np.ascontiguousarray(np.asarray(list(qubits or []) or [0], dtype=np.int32))
+    m = len(qubits) if want_p else 0
+    probs = np.empty(1 << m, dtype=np.float64) if want_p else None
+    arr = (ctypes.c_char_p * max(1, len(terms)))(*[t.encode() for t in terms])
+    expect = np.empty(max(1, len(terms)), dtype=np.float64)
+    u = np.ascontiguousarray(np.asarray([] if uniforms is None else uniforms, dtype=np.float64))
+    samples = np.empty(max(1, u.size), dtype=np.int64)
+    _check(_lib.sv_readout(ctypes.c_void_p(h), q.ctypes.data if m else None, m,
+                           probs.ctypes.data if want_p else None, arr, len(terms), expect.ctypes.data,
+                           u.ctypes.data if u.size else None, u.size, samples.ctypes.data), "sv_readout")
+    return probs, expect[:len(terms)], samples[:u.size]
 
 
 def sv_uniforms(seed: int, count: int, first: int = 0) -> np.ndarray:

@@ -1555,12 +1555,9 @@ int sv_expect_pauli_noalloc(sv_handle h, const char *const *terms, int nterms, d
     return expect_core(h, nterms, xs, yzs, nys, d_scr, d_scr + part, h_res, order, out);
 }
 
-int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
+// Check a shot request: shots >= 0, uniforms in [0, 1).
+static int check_shots(const double *uniforms, int shots, const int64_t *out)
 {
-    clear_error();
-    int rc = check_handle(h);
-    if (rc != SV_OK)
-        return rc;
     if (shots < 0 || (shots > 0 && (!uniforms || !out))) {
         set_error("bad sampling arguments");
         return SV_EINVAL;
@@ -1570,33 +1567,20 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
             set_error("uniform %d = %g outside [0, 1)", s, uniforms[s]);
             return SV_EINVAL;
         }
-    if (shots == 0)
-        return SV_OK;
-    DeviceGuard dg(h->device);
-    const int lbs = sample_log_block(h->n);
-    const uint64_t nb = uint64_t(1) << (h->n - lbs);
-    // scratch: block sums | blocks (int64) | targets | outputs (int64)
-    const uint64_t need = (nb + 3 * uint64_t(shots)) * 8;
-    rc = ensure_scratch(h, need);
-    if (rc != SV_OK)
-        return rc;
-    rc = ensure_pinned(h, std::max<uint64_t>(nb, 2 * uint64_t(shots)) * 8);
-    if (rc != SV_OK)
-        return rc;
-    double *d_bs = h->d_scratch;
-    int64_t *d_blk = reinterpret_cast<int64_t *>(h->d_scratch + nb);
-    double *d_tgt = h->d_scratch + nb + shots;
-    int64_t *d_out = reinterpret_cast<int64_t *>(h->d_scratch + nb + 2 * uint64_t(shots));
-    hipError_t e = launch_block_sums(h->d_state, h->n, h->dtype, d_bs, h->stream);
-    if (e != hipSuccess) {
-        set_error("block-sum launch failed: %s", hipGetErrorString(e));
-        return SV_EDEVICE;
-    }
-    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_bs, nb * 8, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    // inclusive prefix of block sums, sequential FP64
+    return SV_OK;
+}
+
+// Shots from the totals bs[0..nb) of consecutive 2^lbs-amplitude blocks (on
+// the host): the inclusive prefix of the totals in FP64, sequentially; each
+// shot's block (first prefix above u * norm) and its residual target; then
+// the in-block search on the device.  d_work holds 3 * shots doubles; the
+// pinned staging is reused, so bs must not live in the part of it that the
+// shots' blocks and targets overwrite before the prefix is taken (it is
+// taken first).
+static int sample_from_blocks(sv_state *h, const double *bs, uint64_t nb, int lbs, const double *uniforms, int shots,
+                              double *d_work, int64_t *out)
+{
     std::vector<double> pre(nb);
-    const double *bs = static_cast<const double *>(h->h_pinned);
     double run = 0.0;
     uint64_t last_pos = 0;
     for (uint64_t b = 0; b < nb; ++b) {
@@ -1606,6 +1590,7 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
             last_pos = b;
     }
     const double norm = run;
+    const double last_total = bs[last_pos];
     std::vector<int64_t> blk(shots);
     std::vector<double> tgt(shots);
     for (int s = 0; s < shots; ++s) {
@@ -1613,17 +1598,19 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
         const uint64_t b = uint64_t(std::upper_bound(pre.begin(), pre.end(), t) - pre.begin());
         if (b >= nb) {
             blk[s] = int64_t(last_pos);
-            tgt[s] = bs[last_pos];  // no in-block index exceeds it: last nonzero is returned
+            tgt[s] = last_total;  // no in-block index exceeds it: last nonzero is returned
         } else {
             blk[s] = int64_t(b);
             tgt[s] = t - (b > 0 ? pre[b - 1] : 0.0);
         }
     }
-    // pinned staging is free again (synchronised above)
+    int64_t *d_blk = reinterpret_cast<int64_t *>(d_work);
+    double *d_tgt = d_work + shots;
+    int64_t *d_out = reinterpret_cast<int64_t *>(d_work + 2 * uint64_t(shots));
     memcpy(h->h_pinned, blk.data(), shots * 8);
     memcpy(static_cast<char *>(h->h_pinned) + shots * 8, tgt.data(), shots * 8);
     HIP_TRY(hipMemcpyAsync(d_blk, h->h_pinned, 2 * uint64_t(shots) * 8, hipMemcpyHostToDevice, h->stream));
-    e = launch_sample_search(h->d_state, h->n, h->dtype, d_blk, d_tgt, shots, d_out, h->stream);
+    hipError_t e = launch_sample_search(h->d_state, h->n, h->dtype, d_blk, d_tgt, shots, d_out, lbs, h->stream);
     if (e != hipSuccess) {
         set_error("sample search launch failed: %s", hipGetErrorString(e));
         return SV_EDEVICE;
@@ -1643,6 +1630,129 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
         }
     }
     return SV_OK;
+}
+
+int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    rc = check_shots(uniforms, shots, out);
+    if (rc != SV_OK || shots == 0)
+        return rc;
+    DeviceGuard dg(h->device);
+    const int lbs = sample_log_block(h->n);
+    const uint64_t nb = uint64_t(1) << (h->n - lbs);
+    // scratch: block sums | blocks (int64) | targets | outputs (int64)
+    const uint64_t need = (nb + 3 * uint64_t(shots)) * 8;
+    rc = ensure_scratch(h, need);
+    if (rc != SV_OK)
+        return rc;
+    // pinned: the block sums, then (after the prefix) the shots' staging
+    rc = ensure_pinned(h, std::max<uint64_t>(nb, 2 * uint64_t(shots)) * 8);
+    if (rc != SV_OK)
+        return rc;
+    double *d_bs = h->d_scratch;
+    hipError_t e = launch_block_sums(h->d_state, h->n, h->dtype, d_bs, h->stream);
+    if (e != hipSuccess) {
+        set_error("block-sum launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_bs, nb * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return sample_from_blocks(h, static_cast<const double *>(h->h_pinned), nb, lbs, uniforms, shots, h->d_scratch + nb,
+                              out);
+}
+
+int sv_readout(sv_handle h, const int *qubits, int m, double *probs, const char *const *terms, int nterms,
+               double *expect, const double *uniforms, int shots, int64_t *samples)
+{
+    clear_error();
+    int rc = check_handle(h);
+    if (rc != SV_OK)
+        return rc;
+    if (m < 0 || m > h->n || m > 30 || (probs && m > 0 && !qubits) || (!probs && m != 0)) {
+        set_error("bad marginal request (m=%d, n=%d)", m, h->n);
+        return SV_EINVAL;
+    }
+    int phys[30];
+    uint64_t used = 0;
+    for (int b = 0; b < m; ++b) {
+        if (qubits[b] < 0 || qubits[b] >= h->n || ((used >> qubits[b]) & 1)) {
+            set_error("bad or repeated qubit %d", qubits[b]);
+            return SV_EINVAL;
+        }
+        used |= uint64_t(1) << qubits[b];
+        phys[b] = h->qmap[qubits[b]];
+    }
+    if (nterms < 0 || (nterms > 0 && (!terms || !expect))) {
+        set_error("bad term list");
+        return SV_EINVAL;
+    }
+    std::vector<uint64_t> xs(nterms), zs(nterms);
+    bool z_only = nterms <= kReadoutMaxZ;
+    for (int t = 0; t < nterms; ++t) {
+        int ny = 0;
+        rc = parse_pauli(h, terms[t], xs[t], zs[t], ny);
+        if (rc != SV_OK)
+            return rc;
+        z_only = z_only && xs[t] == 0;
+    }
+    rc = check_shots(uniforms, shots, samples);
+    if (rc != SV_OK)
+        return rc;
+    const bool want_p = probs != nullptr;
+    if (!want_p && nterms == 0 && shots == 0)
+        return SV_OK;
+    // one read of the state where the marginal's fold route allows it and
+    // every string is a Z string; else the three read-outs one after another
+    if (!z_only || !readout_fusable(h->n, want_p ? m : 0, phys, h->dtype) || (want_p && m == 0)) {
+        if (want_p && (rc = sv_probabilities(h, qubits, m, probs)) != SV_OK)
+            return rc;
+        if (nterms > 0 && (rc = sv_expect_pauli(h, terms, nterms, expect)) != SV_OK)
+            return rc;
+        if (shots > 0 && (rc = sv_sample(h, uniforms, shots, samples)) != SV_OK)
+            return rc;
+        return SV_OK;
+    }
+    DeviceGuard dg(h->device);
+    const int mm = want_p ? m : 0;
+    const int lbs = readout_log_block(h->n, mm, phys, h->dtype);
+    const uint64_t nb = uint64_t(1) << (h->n - lbs);
+    const uint64_t nbins = want_p ? uint64_t(1) << m : 0;
+    const uint64_t red = readout_scratch_doubles(h->n, mm, phys, h->dtype);
+    // scratch: fold and Z partials | block totals | marginal | Z values | shots (3 per shot)
+    const uint64_t need = red + nb + nbins + uint64_t(nterms) + 3 * uint64_t(shots);
+    rc = ensure_scratch(h, need * 8);
+    if (rc != SV_OK)
+        return rc;
+    // pinned: block totals | marginal | Z values, then the shots' staging
+    rc = ensure_pinned(h, std::max<uint64_t>(nb + nbins + uint64_t(nterms), 2 * uint64_t(shots)) * 8);
+    if (rc != SV_OK)
+        return rc;
+    double *d_tot = h->d_scratch + red;
+    double *d_marg = d_tot + nb;
+    double *d_z = d_marg + nbins;
+    double *d_work = d_z + nterms;
+    hipError_t e = launch_readout(h->d_state, h->n, h->dtype, phys, mm, zs.data(), nterms, h->d_scratch,
+                                  want_p ? d_marg : nullptr, d_z, d_tot, h->stream);
+    if (e != hipSuccess) {
+        set_error("read-out launch failed: %s", hipGetErrorString(e));
+        return SV_EDEVICE;
+    }
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_tot, (nb + nbins + uint64_t(nterms)) * 8, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double *hp = static_cast<const double *>(h->h_pinned);
+    if (want_p)
+        memcpy(probs, hp + nb, nbins * 8);
+    if (nterms > 0)
+        memcpy(expect, hp + nb + nbins, uint64_t(nterms) * 8);
+    if (shots == 0)
+        return SV_OK;
+    std::vector<double> tot(hp, hp + nb);
+    return sample_from_blocks(h, tot.data(), nb, lbs, uniforms, shots, d_work, samples);
 }
 
 // Uniform s of the shot stream of `seed`: the s-th output of SplitMix64

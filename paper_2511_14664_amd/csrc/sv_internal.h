@@ -253,7 +253,18 @@ hipError_t launch_expect_xy(const void *st, int n, int dtype, uint64_t xmask, ui
                             double *d_scratch, double *d_out2, hipStream_t s);
 int sample_log_block(int n);
 hipError_t launch_block_sums(const void *st, int n, int dtype, double *d_bsums, hipStream_t s);
+// Per-shot search inside 2^lbs-amplitude blocks (lbs <= 20).
 hipError_t launch_sample_search(const void *st, int n, int dtype, const int64_t *d_blocks,
-                                const double *d_targets, int shots, int64_t *d_out, hipStream_t s);
+                                const double *d_targets, int shots, int64_t *d_out, int lbs, hipStream_t s);
+// Z strings of one fused read-out.
+constexpr int kReadoutMaxZ = 32;
+// Fused read-out (one read of the state): marginal over phys_q[0..m) (m = 0:
+// none), nt <= 32 Z strings, and the totals of 2^readout_log_block blocks.
+// Possible where readout_fusable; scratch of readout_scratch_doubles.
+bool readout_fusable(int n, int m, const int *phys_q, int dtype);
+int readout_log_block(int n, int m, const int *phys_q, int dtype);
+uint64_t readout_scratch_doubles(int n, int m, const int *phys_q, int dtype);
+hipError_t launch_readout(const void *st, int n, int dtype, const int *phys_q, int m, const uint64_t *zmasks,
+                          int nt, double *d_scratch, double *d_marg, double *d_z, double *d_tot, hipStream_t s);
 
 }  // namespace sv

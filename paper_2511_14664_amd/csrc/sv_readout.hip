@@ -544,10 +544,29 @@ __device__ __forceinline__ uint32_t deposit(uint32_t x, uint32_t mask)
     return r;
 }
 
-template <typename R, bool KSUM>
+// Optional outputs of the same read (one read of the state for several
+// read-outs): NZ > 0, the partial sums of nt <= NZ Z strings (as k_expect_z:
+// a Walsh transform over the thread's 16 amplitudes of a segment, indexed by
+// the index bits its loads differ in, picks one coefficient per string; the
+// segment's higher bits give a workgroup-uniform sign and the lane's bits a
+// sign applied once at the end), part[t * grid + block]; TOT, the total
+// probability of every 2^tlog consecutive segments, tot[block * 2^(F - tlog)
+// + j].
+typedef double f64x16 __attribute__((ext_vector_type(16)));
+struct ReadoutArgs {
+    uint64_t z[kMaxZ];
+    int nt;
+    int tlog;
+    double *zpart;
+    double *tot;
+};
+
+template <typename R, bool KSUM, int NZ = 0, bool TOT = false>
 __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st, double *__restrict__ red,
-                                                        const FoldArgs a)
+                                                        const FoldArgs a, const ReadoutArgs ra)
 {
+    static_assert(NZ == 0 || KSUM, "Z strings ride on the register-summed fold only");
+    static_assert(NZ <= kMaxZ && NZ <= 64, "one string per lane");
     constexpr int SEG = 1 << kSegLog;
     constexpr int LOW = fold_low_bits<R>();
     constexpr int PR = KSUM ? (1 << LOW) : SEG;  // LDS entries per segment
@@ -555,6 +574,7 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
     constexpr bool F32 = std::is_same<R, float>::value;
     constexpr int NLD = F32 ? SEG / (2 * kThreads) : SEG / kThreads;  // loads per thread per segment
     __shared__ double pr[PR];
+    __shared__ double sh_tot[TOT || NZ > 0 ? 4 : 1];
     const int tid = threadIdx.x;
     const uint32_t restmask = KSUM ? (a.restmask & uint32_t(PR - 1)) : a.restmask;
     const int B = 1 << a.lb;
@@ -571,8 +591,22 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
     const uint32_t x_first = deposit(uint32_t(gi), restmask);
     const uint32_t x_step = deposit(uint32_t(G), restmask);
     const uint32_t d_bin0 = deposit(uint32_t(bin0), a.binmask);
+    // Z strings: the lane reports string `lane`'s segment parity by ballot;
+    // walsh index of a string: its bits among the loads' varying index bits
+    const int lane = tid & 63;
+    const uint64_t zl = (NZ > 0 && lane < NZ) ? ra.z[lane] : 0;
+    double zacc[NZ > 0 ? NZ : 1];
+#pragma unroll
+    for (int t = 0; t < (NZ > 0 ? NZ : 1); ++t)
+        zacc[t] = 0.0;
+    double tsum = 0.0;
     for (uint32_t j = 0; j < (1u << a.F); ++j) {
         const uint64_t base = ((uint64_t(blockIdx.x) << a.F) | j) << kSegLog;
+        // the thread's 16 probabilities, by the index bits its loads differ in
+        // (c64: bit 0 and bits 9..11, as 2 k + c; c128: bits 8..11, as k); a
+        // vector value, so that picking a string's coefficient by its
+        // (uniform) index indexes registers rather than private memory
+        f64x16 w;
         if constexpr (F32) {
             const float4 *v4 = reinterpret_cast<const float4 *>(st) + (base >> 1);
             double s0 = 0.0, s1 = 0.0;
@@ -589,10 +623,16 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
                     pr[e] = p0;
                     pr[e + 1] = p1;
                 }
+                if constexpr (NZ > 0) {
+                    w[2 * k] = p0;
+                    w[2 * k + 1] = p1;
+                }
             }
             if constexpr (KSUM) {
                 pr[2 * tid] = s0;
                 pr[2 * tid + 1] = s1;
+                if constexpr (TOT)
+                    tsum += s0 + s1;
             }
         } else {
             const double2 *v2 = reinterpret_cast<const double2 *>(st) + base;
@@ -605,9 +645,42 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
                     s0 += p0;
                 else
                     pr[tid + k * kThreads] = p0;
+                if constexpr (NZ > 0)
+                    w[k] = p0;
             }
-            if constexpr (KSUM)
+            if constexpr (KSUM) {
                 pr[tid] = s0;
+                if constexpr (TOT)
+                    tsum += s0;
+            }
+        }
+        if constexpr (NZ > 0) {
+            static_assert(NZ == 0 || NLD * (F32 ? 2 : 1) == 16, "16 probabilities per thread and segment");
+            // w[k] <- sum_u (-1)^popcount(u & k) p_u
+#pragma unroll
+            for (int b = 1; b < 16; b <<= 1)
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (!(u & b)) {
+                        const double x = w[u], y = w[u | b];
+                        w[u] = x + y;
+                        w[u | b] = x - y;
+                    }
+            const uint64_t sgn = __ballot((__popcll(base & zl) & 1) != 0);
+#pragma unroll
+            for (int t = 0; t < NZ; ++t) {
+                const uint64_t zt = ra.z[t];
+                const int k = F32 ? int((zt & 1) | (((zt >> 9) & 7) << 1)) : int((zt >> 8) & 15);
+                zacc[t] = fma(((sgn >> t) & 1) ? -1.0 : 1.0, w[k], zacc[t]);
+            }
+        }
+        if constexpr (TOT) {
+            if (((j + 1) & ((1u << ra.tlog) - 1)) == 0) {
+                const double tt = block_sum(tsum, sh_tot);
+                if (tid == 0)
+                    ra.tot[(uint64_t(blockIdx.x) << (a.F - ra.tlog)) + (j >> ra.tlog)] = tt;
+                tsum = 0.0;
+            }
         }
         __syncthreads();
         if (owner_mode) {
@@ -647,6 +720,19 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
                 red[out0 + tid + k * kThreads] = acc[k];
     } else if (bin0 < B && gi == 0) {
         red[out0 + bin0] = acc[0];
+    }
+    if constexpr (NZ > 0) {
+        // the lane's index bits: c64 bits 1..8, c128 bits 0..7
+        const uint32_t lbits = F32 ? uint32_t(tid) << 1 : uint32_t(tid);
+#pragma unroll
+        for (int t = 0; t < NZ; ++t) {
+            if (t < ra.nt) {
+                const double r = (__popc(lbits & uint32_t(ra.z[t])) & 1) ? -zacc[t] : zacc[t];
+                const double v = block_sum(r, sh_tot);
+                if (tid == 0)
+                    ra.zpart[uint64_t(t) * gridDim.x + blockIdx.x] = v;
+            }
+        }
     }
 }
 
@@ -722,6 +808,41 @@ struct MargRoute {
 
 constexpr uint64_t kMaxFolded = uint64_t(1) << 24;  // doubles
 
+// The fold route with 2^F segments per workgroup (the caller checks that
+// bits 12 .. 12 + F - 1 hold no bin and that n >= 14).
+MargRoute fold_route(int n, int m, const int *phys_q, int F)
+{
+    MargRoute r{};
+    uint32_t binmask = 0;
+    for (int b = 0; b < m; ++b)
+        if (phys_q[b] < kSegLog)
+            binmask |= 1u << phys_q[b];
+    const int lb = __builtin_popcount(binmask);
+    const int n2 = n - kSegLog - F + lb;
+    r.kind = 2;
+    r.fold.binmask = binmask;
+    r.fold.restmask = ((1u << kSegLog) - 1u) & ~binmask;
+    r.fold.lb = lb;
+    r.fold.F = F;
+    r.n2 = n2;
+    r.red = uint64_t(1) << n2;
+    r.q2.resize(size_t(m));
+    for (int b = 0; b < m; ++b) {
+        const int q = phys_q[b];
+        r.q2[size_t(b)] = q < kSegLog ? __builtin_popcount(binmask & ((1u << q) - 1u)) : lb + q - kSegLog - F;
+    }
+    r.p2 = marg_plan(n2, m);
+    if (!r.p2.rmajor && m <= 15) {
+        // few rest entries per bin: still one workgroup per bin (a thread per
+        // bin would leave the GPU nearly empty for up to 2^15 bins)
+        r.p2.rmajor = true;
+        r.p2.chunks = 1;
+        r.p2.per_chunk = uint64_t(1) << (n2 - m);
+    }
+    r.scratch = r.red + (r.p2.rmajor ? (uint64_t(1) << m) * r.p2.chunks : 0);
+    return r;
+}
+
 MargRoute marg_route(int n, int m, const int *phys_q)
 {
     MargRoute r{};
@@ -750,24 +871,8 @@ MargRoute marg_route(int n, int m, const int *phys_q)
         while (F < n - kSegLog - 1 && !((hibins >> (kSegLog + F)) & 1) &&
                (uint64_t(1) << (n - kSegLog - F + lb)) > kMaxFolded)
             ++F;
-        const int n2 = n - kSegLog - F + lb;
-        if ((uint64_t(1) << n2) <= 4 * kMaxFolded) {
-            r.kind = 2;
-            r.fold.binmask = binmask;
-            r.fold.restmask = ((1u << kSegLog) - 1u) & ~binmask;
-            r.fold.lb = lb;
-            r.fold.F = F;
-            r.n2 = n2;
-            r.red = uint64_t(1) << n2;
-            r.q2.resize(size_t(m));
-            for (int b = 0; b < m; ++b) {
-                const int q = phys_q[b];
-                r.q2[size_t(b)] = q < kSegLog ? __builtin_popcount(binmask & ((1u << q) - 1u)) : lb + q - kSegLog - F;
-            }
-            r.p2 = marg_plan(n2, m);
-            r.scratch = r.red + (r.p2.rmajor ? (uint64_t(1) << m) * r.p2.chunks : 0);
-            return r;
-        }
+        if ((uint64_t(1) << (n - kSegLog - F + lb)) <= 4 * kMaxFolded)
+            return fold_route(n, m, phys_q, F);
     }
     const MargPlan p = marg_plan(n, m);
     r.kind = 0;
@@ -819,17 +924,17 @@ hipError_t launch_marginal(const void *st, int n, int dtype, const int *phys_q, 
         if (dtype == SV_C64) {
             if ((route.fold.binmask >> fold_low_bits<float>()) == 0)
                 hipLaunchKernelGGL((k_marg_fold<float, true>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
-                                   (const float *)st, d_scratch, route.fold);
+                                   (const float *)st, d_scratch, route.fold, ReadoutArgs{});
             else
                 hipLaunchKernelGGL((k_marg_fold<float, false>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
-                                   (const float *)st, d_scratch, route.fold);
+                                   (const float *)st, d_scratch, route.fold, ReadoutArgs{});
         } else {
             if ((route.fold.binmask >> fold_low_bits<double>()) == 0)
                 hipLaunchKernelGGL((k_marg_fold<double, true>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
-                                   (const double *)st, d_scratch, route.fold);
+                                   (const double *)st, d_scratch, route.fold, ReadoutArgs{});
             else
                 hipLaunchKernelGGL((k_marg_fold<double, false>), dim3(uint32_t(nblk)), dim3(kThreads), 0, s,
-                                   (const double *)st, d_scratch, route.fold);
+                                   (const double *)st, d_scratch, route.fold, ReadoutArgs{});
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
@@ -1023,10 +1128,9 @@ hipError_t launch_block_sums(const void *st, int n, int dtype, double *d_bsums, 
 }
 
 hipError_t launch_sample_search(const void *st, int n, int dtype, const int64_t *d_blocks, const double *d_targets,
-                                int shots, int64_t *d_out, hipStream_t s)
+                                int shots, int64_t *d_out, int lbs, hipStream_t s)
 {
-    const int lbs = sample_log_block(n);
-    if (shots <= 0)
+    if (shots <= 0 || lbs < 1 || lbs > n || lbs > 20)
         return hipSuccess;
     if (dtype == SV_C64)
         hipLaunchKernelGGL(k_sample_search<float>, dim3(shots), dim3(kThreads), 0, s, (const float *)st, d_blocks,
@@ -1034,6 +1138,134 @@ hipError_t launch_sample_search(const void *st, int n, int dtype, const int64_t 
     else
         hipLaunchKernelGGL(k_sample_search<double>, dim3(shots), dim3(kThreads), 0, s, (const double *)st, d_blocks,
                            d_targets, d_out, lbs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused read-out: one k_marg_fold launch over the state gives the marginal's
+// fold (when it takes the register-summed fold route), the partial sums of up
+// to kMaxZ Z strings and the block totals for sampling; then the marginal's
+// second stage and the Z reduction.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Route of the fused launch; false where the marginal takes another route.
+// m = 0: a fold with no bin bits (the total only).
+// More segments per workgroup than the marginal alone needs: at most 2^12
+// workgroups, so that the per-workgroup reductions of the Z strings (one per
+// string) and the partial sums they leave stay small against the read.
+bool fused_route(int n, int m, const int *phys_q, int dtype, MargRoute &r)
+{
+    if (n < kSegLog + 2)
+        return false;
+    int F = 0;
+    uint64_t hibins = 0;
+    if (m > 0) {
+        r = marg_route(n, m, phys_q);
+        if (r.kind != 2)
+            return false;
+        const int low = dtype == SV_C64 ? fold_low_bits<float>() : fold_low_bits<double>();
+        if ((r.fold.binmask >> low) != 0)
+            return false;
+        F = r.fold.F;
+        for (int b = 0; b < m; ++b)
+            if (phys_q[b] >= kSegLog)
+                hibins |= uint64_t(1) << phys_q[b];
+    }
+    const int want = std::max(0, n - kSegLog - 12);
+    while (F < want && F < n - kSegLog - 1 && !((hibins >> (kSegLog + F)) & 1))
+        ++F;
+    while (F < n - kSegLog - 1 && !((hibins >> (kSegLog + F)) & 1) &&
+           (uint64_t(1) << (n - kSegLog - F)) > kMaxFolded)
+        ++F;
+    r = fold_route(n, m, phys_q, F);
+    return true;
+}
+
+}  // namespace
+
+static_assert(kMaxZ == kReadoutMaxZ, "Z strings of one fused read-out");
+
+bool readout_fusable(int n, int m, const int *phys_q, int dtype)
+{
+    MargRoute r;
+    return fused_route(n, m, phys_q, dtype, r);
+}
+
+int readout_log_block(int n, int m, const int *phys_q, int dtype)
+{
+    MargRoute r;
+    if (!fused_route(n, m, phys_q, dtype, r))
+        return -1;
+    return kSegLog + std::min(r.fold.F, 2);
+}
+
+uint64_t readout_scratch_doubles(int n, int m, const int *phys_q, int dtype)
+{
+    MargRoute r;
+    if (!fused_route(n, m, phys_q, dtype, r))
+        return 0;
+    const uint64_t nblk = uint64_t(1) << (n - kSegLog - r.fold.F);
+    return r.scratch + uint64_t(kMaxZ) * nblk;
+}
+
+hipError_t launch_readout(const void *st, int n, int dtype, const int *phys_q, int m, const uint64_t *zmasks,
+                          int nt, double *d_scratch, double *d_marg, double *d_z, double *d_tot, hipStream_t s)
+{
+    MargRoute r;
+    if (nt < 0 || nt > kMaxZ || !fused_route(n, m, phys_q, dtype, r))
+        return hipErrorInvalidValue;
+    const uint64_t nblk = uint64_t(1) << (n - kSegLog - r.fold.F);
+    ReadoutArgs ra{};
+    ra.nt = nt;
+    for (int t = 0; t < nt; ++t)
+        ra.z[t] = zmasks[t];
+    ra.tlog = std::min(r.fold.F, 2);
+    ra.zpart = d_scratch + r.scratch;
+    ra.tot = d_tot;
+    const dim3 g{uint32_t(nblk)}, b{uint32_t(kThreads)};
+    if (dtype == SV_C64) {
+        const float *p = (const float *)st;
+        if (nt > 0)
+            hipLaunchKernelGGL((k_marg_fold<float, true, kMaxZ, true>), g, b, 0, s, p, d_scratch, r.fold, ra);
+        else
+            hipLaunchKernelGGL((k_marg_fold<float, true, 0, true>), g, b, 0, s, p, d_scratch, r.fold, ra);
+    } else {
+        const double *p = (const double *)st;
+        if (nt > 0)
+            hipLaunchKernelGGL((k_marg_fold<double, true, kMaxZ, true>), g, b, 0, s, p, d_scratch, r.fold, ra);
+        else
+            hipLaunchKernelGGL((k_marg_fold<double, true, 0, true>), g, b, 0, s, p, d_scratch, r.fold, ra);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (nt > 0) {
+        e = launch_sum_rows(ra.zpart, d_z, uint64_t(nt), uint32_t(nblk), s);
+        if (e != hipSuccess)
+            return e;
+    }
+    if (m == 0 || !d_marg)
+        return hipSuccess;
+    MargArgs a2{};
+    a2.m = m;
+    a2.rest = uint64_t(1) << (r.n2 - m);
+    a2.nbins = uint32_t(1u << m);
+    for (int b2 = 0; b2 < m; ++b2)
+        a2.qbit[b2] = uint64_t(1) << r.q2[size_t(b2)];
+    a2.rest_im = make_masks(r.q2);
+    a2.chunks = r.p2.chunks;
+    a2.per_chunk = r.p2.per_chunk;
+    if (r.p2.rmajor) {
+        double *part = d_scratch + r.red;
+        hipLaunchKernelGGL(k_marg_rmajor_d, dim3(a2.chunks, a2.nbins), dim3(kThreads), 0, s, d_scratch, part, a2);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        return launch_sum_rows(part, d_marg, uint64_t(a2.nbins), a2.chunks, s);
+    }
+    const uint64_t gg = std::min<uint64_t>((uint64_t(a2.nbins) + kThreads - 1) / kThreads, 1u << 20);
+    hipLaunchKernelGGL(k_marg_doubles, dim3(gg), dim3(kThreads), 0, s, d_scratch, d_marg, a2);
     return hipGetLastError();
 }
 

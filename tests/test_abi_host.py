@@ -289,3 +289,9 @@ def test_sample_seeded_rejects_before_touching_the_device():
     with pytest.raises(B.SvError) as e:
         B.sv_sample_seeded(0, 10, 1)
     assert e.value.code == B.SV_EINVAL
+
+
+def test_readout_rejects_before_touching_the_device():
+    with pytest.raises(B.SvError) as e:
+        B.sv_readout(0, [0], ["Z"], [0.5])
+    assert e.value.code == B.SV_EINVAL
