@@ -126,6 +126,25 @@ def test_one_qubit_gates_every_position(dtype):
                     assert e <= TOL[dtype] / 10, (name, t, ctrls, e)
 
 
+@pytest.mark.parametrize("n", [12, 16])
+def test_one_target_low_targets_with_high_controls(n):
+    """Targets 1..3 of complex64 states with no control on index bits 1..8
+    swap vector halves between lanes (the other modes stay for controls on
+    bits 0..8); every target and control placement against the reference."""
+    psi = W.random_state(n, 5 + n)
+    with State(n, B.SV_C64) as s:
+        for t in (1, 2, 3):
+            for ctrls in [(), (9,), (n - 1,), (9, n - 2), (9, 10, n - 1), (0,), (5,), (8, n - 1)]:
+                for name, params in (("u3", (0.3, 1.1, -0.7)), ("h", ()), ("x", ())):
+                    g = Gate(name, (t,), ctrls, params)
+                    ref = s.load(psi)
+                    B.sv_apply_circuit(s.h, [g])
+                    got = s.host()
+                    want = oracle.apply_gate(ref.copy(), g)
+                    e = maxerr(got, want)
+                    assert e <= TOL[B.SV_C64] / 10, (name, t, ctrls, e)
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 @pytest.mark.parametrize("n", [8, 14, 17])
 def test_multi_target_gates(dtype, n):
