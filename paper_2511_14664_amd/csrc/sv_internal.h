@@ -233,9 +233,9 @@ static_assert(sizeof(PassTerm) == 24, "pass phase term layout");
 // nsub blocks on an n-qubit state (the smallest or one more).
 int pass_tile_log(int dtype);
 int pass_tile_log_for(int n, int dtype, int nsub);
-// Sorted physical tile bits of a T-bit pass tile (the pass qubits + the
-// lowest free bits outside phys_avoid); returns T, or -1 if the pass does not
-// fit.
+// Sorted physical tile bits of a T-bit pass tile (the pass qubits, at most
+// T, + the lowest free bits outside phys_avoid); returns T, or -1 if the pass
+// does not fit.
 int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *tile_bits);
 // phases: some block carries phase terms (selects the kernel that reads them);
 // split: complex64 blocks as FP32-accurate split BF16 products (T = 12 only).

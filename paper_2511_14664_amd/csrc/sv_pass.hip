@@ -646,7 +646,7 @@ int pass_tile_log_for(int n, int dtype, int nsub)
 int pass_tile_bits(int n, int T, uint64_t phys_qmask, uint64_t phys_avoid, int *tile_bits)
 {
     const int q = __builtin_popcountll(phys_qmask);
-    if (T < 1 || T > 16 || n < T || n > 63 || q > kMaxPassQubits || (phys_qmask >> n) != 0 ||
+    if (T < 1 || T > 16 || n < T || n > 63 || q > T || (phys_qmask >> n) != 0 ||
         (phys_qmask & phys_avoid) != 0)
         return -1;
     int got = 0;

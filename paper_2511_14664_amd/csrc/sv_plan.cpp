@@ -372,7 +372,7 @@ uint64_t qubit_mask(const Block &b)
 // merge applies.  dep[] holds each block's qubits for the commutation test,
 // g[].qmask those that count towards kmax; at most omax qubits of dep lie
 // outside qmask.
-static void merge_groups(std::vector<Group> &g, std::vector<uint64_t> &dep, int kmax, int omax)
+static void merge_groups(std::vector<Group> &g, std::vector<uint64_t> &dep, int kmax, int omax, uint64_t freem)
 {
     auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
     bool changed = true;
@@ -381,7 +381,7 @@ static void merge_groups(std::vector<Group> &g, std::vector<uint64_t> &dep, int 
         for (size_t i = 0; i < g.size() && !changed; ++i) {
             uint64_t between = 0;  // union of qubits of blocks strictly between i and j
             for (size_t j = i + 1; j < g.size(); ++j) {
-                if (popc(g[i].qmask | g[j].qmask) <= kmax &&
+                if (popc((g[i].qmask | g[j].qmask) & ~freem) <= kmax &&
                     popc((dep[i] | dep[j]) & ~(g[i].qmask | g[j].qmask)) <= omax) {
                     if ((between & dep[j]) == 0) {
                         // move j back into i: members of j follow those of i
@@ -418,10 +418,12 @@ static void merge_groups(std::vector<Group> &g, std::vector<uint64_t> &dep, int 
 // diagonal gate a second, smaller budget mask (qubits outside a pass tile are
 // constant per tile, so there a diagonal gate needs only its in-tile qubits):
 // a gate joins with its full mask when that fits, else with the small one,
-// and a block may hold at most omax qubits outside its budget.
+// and a block may hold at most omax qubits outside its budget.  Qubits in
+// freem do not count towards kmax (a pass tile holds the lowest index bits
+// whether or not its gates act on them).
 static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const std::vector<uint64_t> &budm,
                                        const std::vector<uint64_t> *minm, int kmax, int omax,
-                                       std::vector<uint64_t> *dep_out)
+                                       std::vector<uint64_t> *dep_out, uint64_t freem = 0)
 {
     // blocks as linked member lists (head, tail, next[]): moving a free
     // block into another splices its list in front in constant time
@@ -437,7 +439,9 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
     int last[64];
     std::fill(last, last + 64, -1);
     auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
-    auto fits = [&](uint64_t bud, uint64_t dep) { return popc(bud) <= kmax && popc(dep & ~bud) <= omax; };
+    auto fits = [&](uint64_t bud, uint64_t dep) {
+        return popc(bud & ~freem) <= kmax && popc(dep & ~bud) <= omax;
+    };
     // set bits of a mask, lowest first
     auto each_bit = [](uint64_t x, auto &&f) {
         while (x) {
@@ -515,7 +519,7 @@ static std::vector<Group> greedy_masks(const std::vector<uint64_t> &depm, const 
         out.push_back(std::move(g));
         dep.push_back(b.dep);
     }
-    merge_groups(out, dep, kmax, omax);
+    merge_groups(out, dep, kmax, omax, freem);
     if (dep_out)
         *dep_out = dep;
     return out;
@@ -888,8 +892,14 @@ static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pas
     std::vector<uint64_t> pdep;
     // a pass keeps at least T0 index bits off its outer qubits for the tile
     const int omax = std::max(0, n - T0);
-    const std::vector<Group> pg = phases == 2 ? greedy_masks(depm, minm, nullptr, pass_qubits, omax, &pdep)
-                                              : greedy_masks(depm, depm, &minm, pass_qubits, omax, &pdep);
+    // the tile always holds the T0 - kMaxPassQubits lowest index bits (its
+    // contiguous runs), so qubits there join a pass without using its budget
+    uint64_t freem = 0;
+    for (int q = 0; q < n; ++q)
+        if ((phys ? phys[q] : q) < T0 - kMaxPassQubits)
+            freem |= uint64_t(1) << q;
+    const std::vector<Group> pg = phases == 2 ? greedy_masks(depm, minm, nullptr, pass_qubits, omax, &pdep, freem)
+                                              : greedy_masks(depm, depm, &minm, pass_qubits, omax, &pdep, freem);
     std::vector<PassGroup> out(pg.size());
     std::vector<Block> mem;
     for (size_t i = 0; i < pg.size(); ++i) {
@@ -899,7 +909,8 @@ static std::vector<PassGroup> pass_plan(const std::vector<Block> &gates, int pas
         for (int m : pg[i].members)
             w.ngates += gates[size_t(m)].ngates;
         const int q = __builtin_popcountll(w.qmask), o = __builtin_popcountll(w.omask);
-        w.kernel = n >= T0 && q >= 1 && q <= kMaxPassQubits && n - o >= T0;
+        const int qb = __builtin_popcountll(w.qmask & ~freem);
+        w.kernel = n >= T0 && q >= 1 && qb <= kMaxPassQubits && q <= T0 && n - o >= T0;
         if (w.kernel) {
             pass_subblocks(gates, pg[i].members, w.qmask, trials, w);
             int term_blocks = 0;

@@ -574,7 +574,8 @@ def test_pass_plan_after_relayout_and_profile_records(dtype):
         kinds = {r["kind_name"] for r in recs}
         assert "pass" in kinds and len(recs) == st["sweeps"]
         assert sum(r["num_gates"] for r in recs) == len(b)
-        assert all(r["k"] <= 8 and r["ms"] > 0 for r in recs if r["kind_name"] == "pass")
+        # a pass holds at most 8 qubits above the tile's lowest bits, and at most the tile
+        assert all(r["k"] <= r["tile_log"] and r["ms"] > 0 for r in recs if r["kind_name"] == "pass")
 
 
 def phase_circuit(n, seed, layers=6):
@@ -672,14 +673,24 @@ def term_heavy_circuit(n, reps, seed):
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 def test_pass_plan_term_heavy_matches_oracle(dtype):
+    """The default plan, and passes of at most 6 qubits above the tile's
+    lowest bits, which take most of the phase gates as per-tile phase terms
+    (at least 20 blocks with terms)."""
     n = 20
     gates = term_heavy_circuit(n, 12, 5)
-    info = B.sv_pass_plan_info(n, dtype, gates)
-    assert info["term_blocks"] >= 20 and info["gates"] == len(gates)
     want = oracle.run(gates, n)
-    say(f"term-heavy passes n={n} {DNAME[dtype]}: {info}")
-    with State(n, dtype) as s:
-        run_checked(s, gates, B.make_opts(B.SV_PLAN_PASSES), want)
+    runs = [(0, B.SV_PREC_NATIVE), (6, B.SV_PREC_NATIVE)]
+    if dtype == B.SV_C64:
+        runs.append((6, B.SV_PREC_BF16X6))
+    for pq, prec in runs:
+        opts = B.make_opts(B.SV_PLAN_PASSES, 5, prec, pq)
+        info = B.sv_pass_plan_info(n, dtype, gates, opts)
+        assert info["gates"] == len(gates)
+        if pq == 6:
+            assert info["term_blocks"] >= 20
+        say(f"term-heavy passes n={n} {DNAME[dtype]} pass qubits {pq or 8} precision {prec}: {info}")
+        with State(n, dtype) as s:
+            run_checked(s, gates, opts, want)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
