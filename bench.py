@@ -264,7 +264,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}-qubit random layered circuit (U3 on every qubit + CNOT/CZ on a random "
                                f"matching, depth 20, {len(gates)} gates), {args.dtype}, "
-                               + (f"LDS passes of <= {args.pass_qubits} qubits (fused 4-qubit blocks on the matrix "
+                               + (f"LDS passes of <= {args.pass_qubits} qubits above the tile's lowest bits (fused 4-qubit blocks on the matrix "
                                   f"cores, {PREC_LABEL[args.precision] if dtype == B.SV_C64 else 'FP64 products'})"
                                   if args.mode == "passes"
                                   else f"{args.mode} fusion <= {args.max_fused} qubits")
