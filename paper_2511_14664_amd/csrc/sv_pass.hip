@@ -379,10 +379,12 @@ __device__ __forceinline__ floatx4 mma_split6(const uint32_t *ah, const uint32_t
 
 // PHASES: some block carries per-tile phase terms; the blocks' matrices are
 // FP32 and every workgroup applies its tile's phases and splits them.
-// Otherwise the matrices come split already (pass_presplit_layout), and the
-// kernel only loads each lane's A fragments.
-template <bool PHASES>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASES ? 4 : 5)))
+// Otherwise the matrices come split already (pass_presplit), and the kernel
+// only loads each lane's A fragments.  NTH: 256 threads (five workgroups per
+// CU, for passes of several blocks) or 512 (three, for one-block passes,
+// which are bound by HBM: 8 waves share a tile's loads and its one block).
+template <bool PHASES, int NTH>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 256 ? (PHASES ? 4 : 5) : 1)))
 void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__restrict__ subs, int nsub,
                   const char *__restrict__ mats)
 {
@@ -390,7 +392,7 @@ void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__res
     constexpr int TA_LOG = 12;
     constexpr int D = 16, NT = 16;
     constexpr int NGS = (1 << (TA_LOG - 4)) / NT;  // group sets of 16 groups
-    constexpr int NW = kThreads / 64;
+    constexpr int NW = NTH / 64;
     constexpr int PER_WAVE = NGS / NW;
     static_assert(PER_WAVE >= 1 && NGS % NW == 0, "tile shape");
 
@@ -472,7 +474,7 @@ void k_pass_split(float *__restrict__ st, const TileArgs a, const PassSub *__res
         }
     };
 
-    tile_sweep<float, TA_LOG, true, kThreads, true, true>(st, a, tile, [&](C *t) {
+    tile_sweep<float, TA_LOG, true, NTH, true, true>(st, a, tile, [&](C *t) {
         if (PHASES) {
             fill_angles();
             __syncthreads();
@@ -681,12 +683,22 @@ hipError_t launch_pass(void *st, int n, int dtype, int T, const int *tile_bits, 
             return hipErrorInvalidValue;
         const PassSub *ps = static_cast<const PassSub *>(d_subs);
         const char *m = static_cast<const char *>(d_mats);
-        if (phases)
-            hipLaunchKernelGGL(k_pass_split<true>, tile_grid(a.ntiles), dim3(kThreads), 0, s, (float *)st, a, ps,
-                               nsub, m);
-        else
-            hipLaunchKernelGGL(k_pass_split<false>, tile_grid(a.ntiles), dim3(kThreads), 0, s, (float *)st, a, ps,
-                               nsub, m);
+        // one-block passes on 512 threads: on 28-qubit tiles 0.67-0.77 ms
+        // against 0.70-0.93 on 256 (most for high pass qubits), while from
+        // two blocks on 256 threads are faster (2 blocks 0.775 against 0.823,
+        // 4 blocks 1.11 against 1.27 ms)
+        const dim3 g = tile_grid(a.ntiles);
+        if (nsub == 1) {
+            if (phases)
+                hipLaunchKernelGGL((k_pass_split<true, 512>), g, dim3(512), 0, s, (float *)st, a, ps, nsub, m);
+            else
+                hipLaunchKernelGGL((k_pass_split<false, 512>), g, dim3(512), 0, s, (float *)st, a, ps, nsub, m);
+        } else {
+            if (phases)
+                hipLaunchKernelGGL((k_pass_split<true, 256>), g, dim3(256), 0, s, (float *)st, a, ps, nsub, m);
+            else
+                hipLaunchKernelGGL((k_pass_split<false, 256>), g, dim3(256), 0, s, (float *)st, a, ps, nsub, m);
+        }
         return hipGetLastError();
     }
     if (dtype == SV_C64)
