@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--mode", choices=["plain", "greedy", "learned", "passes"], default="passes")
     ap.add_argument("--pass-qubits", type=int, default=8, help="qubits per LDS pass (--mode passes)")
+    ap.add_argument("--pass-orders", type=int, default=None,
+                    help="seeded gate orders the pass planner tries (sv_plan_opts.pass_orders; default: 64 for the "
+                         "28-qubit headline, whose plan is kept across steps, else the library's default)")
     ap.add_argument("--max-fused", type=int, default=5)
     ap.add_argument("--precision", choices=["native", "bf16x3", "bf16x6"], default="bf16x6",
                     help="native: FP32 (complex64) / FP64 (complex128) arithmetic; bf16x3: three-term BF16 "
@@ -108,7 +111,10 @@ def main():
     mode = {"plain": B.SV_PLAN_PLAIN, "greedy": B.SV_PLAN_GREEDY, "learned": B.SV_PLAN_LEARNED,
             "passes": B.SV_PLAN_PASSES}[args.mode]
     prec = precision_of(args, B)
-    opts = B.make_opts(mode, args.max_fused, prec, args.pass_qubits if args.mode == "passes" else 0)
+    # the plan is made once and kept for the repeated steps (plans are kept
+    # per circuit structure), so the planner may search gate orders
+    orders = (64 if args.pass_orders is None else args.pass_orders) if args.mode == "passes" else 0
+    opts = B.make_opts(mode, args.max_fused, prec, args.pass_qubits if args.mode == "passes" else 0, orders)
     marg_q = list(range(n - 10, n))
     terms = W.hea_z_terms(n)[: 2 * 16]
     uni = W.uniforms(7, 1000)
@@ -264,7 +270,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}-qubit random layered circuit (U3 on every qubit + CNOT/CZ on a random "
                                f"matching, depth 20, {len(gates)} gates), {args.dtype}, "
-                               + (f"LDS passes of <= {args.pass_qubits} qubits above the tile's lowest bits (fused 4-qubit blocks on the matrix "
+                               + (f"LDS passes of <= {args.pass_qubits} qubits above the tile's lowest bits, {orders} gate orders searched "
+                                  f"(fused 4-qubit blocks on the matrix "
                                   f"cores, {PREC_LABEL[args.precision] if dtype == B.SV_C64 else 'FP64 products'})"
                                   if args.mode == "passes"
                                   else f"{args.mode} fusion <= {args.max_fused} qubits")
