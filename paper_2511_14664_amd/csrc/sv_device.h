@@ -229,10 +229,18 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v)
 //
 // compute(tile) starts after a barrier that follows the tile's LDS writes; it
 // must leave its results in the same LDS slots and end with __syncthreads().
+// src(x) (identity by default) is the tile-local index whose LDS slot the
+// store of element x reads: a permutation of the tile applied on the way out
+// (not with PSWZ).
 // ---------------------------------------------------------------------------
-template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, bool REMAT = false, bool PSWZ = false, typename F>
+struct SameSlot {
+    __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return x; }
+};
+
+template <typename R, int TA_LOG, bool PAIR, int NTH = kThreads, bool REMAT = false, bool PSWZ = false, typename F,
+          typename S = SameSlot>
 __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a, typename CT<R>::C *tile,
-                                           F &&compute)
+                                           F &&compute, S src = S())
 {
     using C = typename CT<R>::C;
     constexpr int TA = 1 << TA_LOG;
@@ -324,7 +332,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
                 if constexpr (PSWZ) {
                     st_nt(&v4[(base + offset2(s)) >> 1], *reinterpret_cast<const float4 *>(&tile[swz_p(x)]));
                 } else {
-                    const C lo = tile[swz(x)], hi = tile[swz(x + 1)];
+                    const C lo = tile[swz(src(x))], hi = tile[swz(src(x + 1))];
                     st_nt(&v4[(base + offset2(s)) >> 1], make_float4(lo.x, lo.y, hi.x, hi.y));
                 }
             }
@@ -333,7 +341,7 @@ __device__ __forceinline__ void tile_sweep(R *__restrict__ st, const TileArgs &a
 #pragma unroll
             for (int s = 0; s < OPT; ++s)
                 st_nt(&v[base + offset2(s)],
-                      tile[PSWZ ? swz_p(uint32_t(s * NTH + tid2)) : swz(uint32_t(s * NTH + tid2))]);
+                      tile[PSWZ ? swz_p(uint32_t(s * NTH + tid2)) : swz(src(uint32_t(s * NTH + tid2)))]);
         }
     }
 }

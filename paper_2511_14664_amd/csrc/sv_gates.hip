@@ -778,38 +778,23 @@ hipError_t launch_gatek(void *st, int n, int dtype, const void *d_U, int k, cons
 
 namespace {
 
-// Bit-field exchange on the LDS tile driver: the tile is read into LDS
-// in memory order, permuted inside LDS, and written back in memory order.
+// Bit-field exchange on the LDS tile driver: the tile is read into LDS in
+// memory order and written back in memory order, each output element taken
+// from the LDS slot of its source (the map swaps the tile-local bit fields
+// [L, L + w) and [L + w, L + 2w), its own inverse).
 template <typename R, int TLOG, bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_bitswap_p(R *__restrict__ st, const TileArgs a, int L, int w)
 {
     using C = typename CT<R>::C;
     constexpr int TA = 1 << TLOG;
-    constexpr int OPT = TA / kThreads;
     __shared__ C tile[TA];
-    const int tid = threadIdx.x;
     const uint32_t wm = (1u << w) - 1u;
     const uint32_t fmask = (wm << L) | (wm << (L + w));
-    tile_sweep<R, TLOG, PAIR>(st, a, tile, [&](C *t) {
-        R tr[OPT], ti[OPT];
-#pragma unroll
-        for (int s = 0; s < OPT; ++s) {
-            const uint32_t y = uint32_t(s * kThreads + tid);
-            const uint32_t f1 = (y >> L) & wm, f2 = (y >> (L + w)) & wm;
-            const C q = t[swz((y & ~fmask) | (f1 << (L + w)) | (f2 << L))];
-            tr[s] = q.x;
-            ti[s] = q.y;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < OPT; ++s) {
-            C q;
-            q.x = tr[s];
-            q.y = ti[s];
-            t[swz(uint32_t(s * kThreads + tid))] = q;
-        }
-        __syncthreads();
-    });
+    auto src = [=](uint32_t y) {
+        const uint32_t f1 = (y >> L) & wm, f2 = (y >> (L + w)) & wm;
+        return (y & ~fmask) | (f1 << (L + w)) | (f2 << L);
+    };
+    tile_sweep<R, TLOG, PAIR>(st, a, tile, [](C *) {}, src);
 }
 
 template <typename R, int TLOG>
