@@ -72,8 +72,8 @@ enum : int {
     kScalar = 0,  // one amplitude per access
     kVec = 1,     // complex64, index bit 0 free: two adjacent groups per 16-byte access
     kT0 = 2,      // complex64, target bit 0: the pair (i0, i0 + 1) is one 16-byte access
-    kShfl = 3,    // complex64, target bit 1..3: every lane moves its own 16-byte vector, the partner
-                  // vector (target bit flipped) comes from lane l ^ 2^(t-1)
+    kShfl = 3,    // complex64 target bit 1..3 (complex128: 0..2): every lane moves its own 16-byte
+                  // vector, the partner vector (target bit flipped) comes from lane l ^ 2^(t-1) (2^t)
 };
 
 // ---------------------------------------------------------------------------
@@ -124,14 +124,24 @@ __device__ __forceinline__ uint64_t index_off(int k, const UnitMap &m)
 // One-target dense gate (controls allowed): pair (i0, i0 | 2^t) for every
 // index i0 with target bit 0 and control bits 1.  Units: kVec, 16-byte
 // vectors holding two such i0 (index bit 0 free); kT0, the 16-byte pair
-// itself; kScalar, one i0.
+// itself; kScalar, one i0.  Controls on index bits inside one 128-byte line
+// stay out of the unit map: every amplitude of the line is read and written,
+// those whose in-line controls are not all set unchanged, so the stores cover
+// whole lines instead of leaving the HBM partial-line writes.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Gate1Args {
     UnitMap m;
     uint64_t tbit;
-    R u[8];  // u00, u01, u10, u11 as (re, im)
+    uint64_t lmask;  // controls inside one 128-byte line: applied per amplitude
+    R u[8];          // u00, u01, u10, u11 as (re, im)
 };
+
+// Whether amplitude index i meets the in-line controls lm (all set).
+__device__ __forceinline__ bool lines_on(uint64_t i, uint64_t lm)
+{
+    return (i & lm) == lm;
+}
 
 template <typename R, int MODE, bool NT, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Gate1Args<R> a)
@@ -145,9 +155,33 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
     if (w >= ((a.m.nunits + 1023) >> 10))
         return;
     const uint64_t u0 = unit0(w, int(threadIdx.x), a.m.pmask);
-    const uint64_t b0 = insert_zeros((MODE == kVec || MODE == kShfl) ? u0 << 1 : u0, a.m.im) | a.m.fixed;
+    constexpr bool kPairs = MODE == kVec || (MODE == kShfl && std::is_same<R, float>::value);
+    const uint64_t b0 = insert_zeros(kPairs ? u0 << 1 : u0, a.m.im) | a.m.fixed;
     auto live = [&](int k) { return FULL || (u0 | unit_off(k, a.m.pmask)) < a.m.nunits; };
-    if constexpr (MODE == kVec) {
+    if constexpr (MODE == kShfl && std::is_same<R, double>::value) {
+        // complex128: lane bits 0..2 are index bits 0..2; the lane whose bit
+        // t is set holds the upper partner and computes it
+        C *v = reinterpret_cast<C *>(st);
+        const int sx = int(a.tbit);
+        const bool upper = (threadIdx.x & sx) != 0;
+        C x[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (live(k))
+                x[k] = ldg<NT>(&v[b0 | index_off(k, a.m)]);
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (!live(k))
+                continue;
+            C y;
+            y.x = __shfl_xor(x[k].x, sx);
+            y.y = __shfl_xor(x[k].y, sx);
+            const C lo = upper ? y : x[k], hi = upper ? x[k] : y;
+            const C ma = upper ? m10 : m00, mb = upper ? m11 : m01;
+            const uint64_t i = b0 | index_off(k, a.m);
+            stg<NT>(&v[i], lines_on(i, a.lmask) ? cmad(mb, hi, cmul(ma, lo)) : x[k]);
+        }
+    } else if constexpr (MODE == kVec) {
         float4 *v = reinterpret_cast<float4 *>(st);
         float4 lo[kItems], hi[kItems];
 #pragma unroll
@@ -167,6 +201,10 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             C h0 = make_float2(hi[k].x, hi[k].y), h1 = make_float2(hi[k].z, hi[k].w);
             C a0 = cmad(m01, h0, cmul(m00, l0)), b0_ = cmad(m11, h0, cmul(m10, l0));
             C a1 = cmad(m01, h1, cmul(m00, l1)), b1 = cmad(m11, h1, cmul(m10, l1));
+            if (!lines_on(i0, a.lmask))
+                a0 = l0, b0_ = h0;
+            if (!lines_on(i0 | 1, a.lmask))
+                a1 = l1, b1 = h1;
             stg<NT>(&v[i0 >> 1], make_float4(a0.x, a0.y, a1.x, a1.y));
             stg<NT>(&v[(i0 | a.tbit) >> 1], make_float4(b0_.x, b0_.y, b1.x, b1.y));
         }
@@ -195,8 +233,13 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             const C l0 = make_float2(lo.x, lo.y), l1 = make_float2(lo.z, lo.w);
             const C h0 = make_float2(hi.x, hi.y), h1 = make_float2(hi.z, hi.w);
             const C ma = upper ? m10 : m00, mb = upper ? m11 : m01;
-            const C r0 = cmad(mb, h0, cmul(ma, l0)), r1 = cmad(mb, h1, cmul(ma, l1));
-            stg<NT>(&v[(b0 | index_off(k, a.m)) >> 1], make_float4(r0.x, r0.y, r1.x, r1.y));
+            C r0 = cmad(mb, h0, cmul(ma, l0)), r1 = cmad(mb, h1, cmul(ma, l1));
+            const uint64_t i = b0 | index_off(k, a.m);
+            if (!lines_on(i, a.lmask))
+                r0 = make_float2(x[k].x, x[k].y);
+            if (!lines_on(i | 1, a.lmask))
+                r1 = make_float2(x[k].z, x[k].w);
+            stg<NT>(&v[i >> 1], make_float4(r0.x, r0.y, r1.x, r1.y));
         }
     } else if constexpr (MODE == kT0) {
         float4 *v = reinterpret_cast<float4 *>(st);
@@ -210,8 +253,11 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             if (!live(k))
                 continue;
             const C l = make_float2(x[k].x, x[k].y), h = make_float2(x[k].z, x[k].w);
-            const C y0 = cmad(m01, h, cmul(m00, l)), y1 = cmad(m11, h, cmul(m10, l));
-            stg<NT>(&v[(b0 | index_off(k, a.m)) >> 1], make_float4(y0.x, y0.y, y1.x, y1.y));
+            C y0 = cmad(m01, h, cmul(m00, l)), y1 = cmad(m11, h, cmul(m10, l));
+            const uint64_t i = b0 | index_off(k, a.m);
+            if (!lines_on(i, a.lmask))
+                y0 = l, y1 = h;
+            stg<NT>(&v[i >> 1], make_float4(y0.x, y0.y, y1.x, y1.y));
         }
     } else {
         C *v = reinterpret_cast<C *>(st);
@@ -229,8 +275,11 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             if (!live(k))
                 continue;
             const uint64_t i0 = b0 | index_off(k, a.m);
-            stg<NT>(&v[i0], cmad(m01, hi[k], cmul(m00, lo[k])));
-            stg<NT>(&v[i0 | a.tbit], cmad(m11, hi[k], cmul(m10, lo[k])));
+            C y0 = cmad(m01, hi[k], cmul(m00, lo[k])), y1 = cmad(m11, hi[k], cmul(m10, lo[k]));
+            if (!lines_on(i0, a.lmask))
+                y0 = lo[k], y1 = hi[k];
+            stg<NT>(&v[i0], y0);
+            stg<NT>(&v[i0 | a.tbit], y1);
         }
     }
 }
@@ -238,14 +287,16 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
 // ---------------------------------------------------------------------------
 // One-target diagonal gate diag(d0, d1) with controls: a[i] *= d[bit t of i]
 // over the indices whose fixed bits match (controls = 1, and the target = 1
-// when d0 == 1, so untouched amplitudes are never read).  Units: VEC, 16-byte
-// vectors (index bit 0 free); else single amplitudes.
+// when d0 == 1, so lines holding no such index are never read).  Fixed bits
+// inside one 128-byte line are tested per amplitude, as for the dense gate.
+// Units: VEC, 16-byte vectors (index bit 0 free); else single amplitudes.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Diag1Args {
     UnitMap m;
     uint64_t tbit;
-    R d[4];  // d0, d1 as (re, im)
+    uint64_t lmask;  // fixed bits inside one 128-byte line: applied per amplitude
+    R d[4];          // d0, d1 as (re, im)
 };
 
 template <typename R, bool VEC, bool NT, bool FULL>
@@ -272,8 +323,12 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
             if (!live(k))
                 continue;
             const uint64_t i = b0 | index_off(k, a.m);
-            const C f = (i & a.tbit) ? d1 : d0;
-            const C p0 = cmul(f, make_float2(x[k].x, x[k].y)), p1 = cmul(f, make_float2(x[k].z, x[k].w));
+            const C x0 = make_float2(x[k].x, x[k].y), x1 = make_float2(x[k].z, x[k].w);
+            C p0 = cmul((i & a.tbit) ? d1 : d0, x0), p1 = cmul(((i | 1) & a.tbit) ? d1 : d0, x1);
+            if (!lines_on(i, a.lmask))
+                p0 = x0;
+            if (!lines_on(i | 1, a.lmask))
+                p1 = x1;
             stg<NT>(&v[i >> 1], make_float4(p0.x, p0.y, p1.x, p1.y));
         }
     } else {
@@ -288,7 +343,7 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
             if (!live(k))
                 continue;
             const uint64_t i = b0 | index_off(k, a.m);
-            stg<NT>(&v[i], cmul((i & a.tbit) ? d1 : d0, x[k]));
+            stg<NT>(&v[i], lines_on(i, a.lmask) ? cmul((i & a.tbit) ? d1 : d0, x[k]) : x[k]);
         }
     }
 }
@@ -584,32 +639,42 @@ void launch_gate1_t(R *p, const Gate1Args<R> &a, hipStream_t s)
 hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const int *ctl, int c,
                         hipStream_t s)
 {
-    std::vector<int> pos(ctl, ctl + c);
+    // controls on the index bits of one 128-byte line (4 for complex64, 3 for
+    // complex128) are tested per amplitude; the others shape the unit map
+    const int line_bits = dtype == SV_C64 ? 4 : 3;
+    std::vector<int> cpos;
+    uint64_t cmask = 0, lmask = 0;
+    for (int j = 0; j < c; ++j) {
+        if (ctl[j] < line_bits) {
+            lmask |= uint64_t(1) << ctl[j];
+        } else {
+            cpos.push_back(ctl[j]);
+            cmask |= uint64_t(1) << ctl[j];
+        }
+    }
+    std::vector<int> pos(cpos);
     pos.push_back(t);
-    uint64_t cmask = 0;
-    for (int j = 0; j < c; ++j)
-        cmask |= uint64_t(1) << ctl[j];
-    const uint64_t ngroups = uint64_t(1) << (n - 1 - c);
+    const uint64_t ngroups = uint64_t(1) << (n - 1 - int(cpos.size()));
     if (dtype == SV_C64) {
-        const bool bit0_free = std::find(pos.begin(), pos.end(), 0) == pos.end();
-        // targets 1..3 with no control on index bits 1..8 and every chunk
+        const bool bit0_free = t != 0;
+        // targets 1..3 with no control on index bits 4..8 and every chunk
         // full: each lane moves whole 16-byte vectors (whole lines per store
         // instruction, so streaming stores) and swaps halves with a partner lane
-        bool low_ctl = false;
-        for (int j = 0; j < c; ++j)
-            low_ctl = low_ctl || (ctl[j] >= 1 && ctl[j] <= 8);
-        const bool shfl = bit0_free && t >= 1 && t <= 3 && !low_ctl && ngroups >= uint64_t(kThreads) * kItems;
+        bool mid_ctl = false;
+        for (int q : cpos)
+            mid_ctl = mid_ctl || q <= 8;
+        const bool shfl = bit0_free && t <= 3 && !mid_ctl && ngroups >= uint64_t(kThreads) * kItems;
         const int mode = shfl ? kShfl : (bit0_free && ngroups >= 2) ? kVec : (t == 0 ? kT0 : kScalar);
         const bool nt = shfl || full_lines(pos, n, mode == kT0 ? 0 : -1, 8);
         Gate1Args<float> a{};
         if (shfl) {
             // units: all 16-byte vectors with the controls removed
-            std::vector<int> cpos(ctl, ctl + c);
             a.m = make_unit_map(cpos, cmask, 8, true, ngroups);
         } else {
             a.m = make_unit_map(pos, cmask, 8, mode == kVec, mode == kVec ? ngroups / 2 : ngroups);
         }
         a.tbit = uint64_t(1) << t;
+        a.lmask = lmask;
         fill_u(a.u, U, 4);
         float *p = (float *)st;
         switch (mode * 2 + (nt ? 1 : 0)) {
@@ -622,12 +687,25 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
         default: launch_gate1_t<float, kScalar, false>(p, a, s); break;
         }
     } else {
-        const bool nt = full_lines(pos, n, -1, 16);
+        // targets 0..2 (inside one line) with no control on index bits 3..8
+        // and every chunk full: lanes move their own amplitudes, partners
+        // swap through lane shuffles, stores cover whole lines
+        bool mid_ctl = false;
+        for (int q : cpos)
+            mid_ctl = mid_ctl || q <= 8;
+        const bool shfl = t < line_bits && !mid_ctl && 2 * ngroups >= uint64_t(kThreads) * kItems;
+        const bool nt = shfl || full_lines(pos, n, -1, 16);
         Gate1Args<double> a{};
-        a.m = make_unit_map(pos, cmask, 16, false, ngroups);
+        if (shfl)
+            a.m = make_unit_map(cpos, cmask, 16, false, 2 * ngroups);  // units: amplitudes
+        else
+            a.m = make_unit_map(pos, cmask, 16, false, ngroups);
         a.tbit = uint64_t(1) << t;
+        a.lmask = lmask;
         fill_u(a.u, U, 4);
-        if (nt)
+        if (shfl)
+            launch_gate1_t<double, kShfl, true>((double *)st, a, s);
+        else if (nt)
             launch_gate1_t<double, kScalar, true>((double *)st, a, s);
         else
             launch_gate1_t<double, kScalar, false>((double *)st, a, s);
@@ -647,24 +725,32 @@ void launch_diag1_t(R *p, const Diag1Args<R> &a, hipStream_t s)
 hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const int *ctl, int c,
                         hipStream_t s)
 {
-    std::vector<int> pos(ctl, ctl + c);
-    uint64_t fixed = 0;
+    // fixed bits (controls, and the target when d0 == 1) on the index bits of
+    // one 128-byte line are tested per amplitude; the others shape the unit map
+    const int line_bits = dtype == SV_C64 ? 4 : 3;
+    std::vector<int> pos;
+    uint64_t fixed = 0, lmask = 0;
+    auto fix = [&](int q) {
+        if (q < line_bits) {
+            lmask |= uint64_t(1) << q;
+        } else {
+            pos.push_back(q);
+            fixed |= uint64_t(1) << q;
+        }
+    };
     for (int j = 0; j < c; ++j)
-        fixed |= uint64_t(1) << ctl[j];
-    const bool skip0 = (d0 == cd(1.0, 0.0));
-    if (skip0) {
-        pos.push_back(t);
-        fixed |= uint64_t(1) << t;
-    }
+        fix(ctl[j]);
+    if (d0 == cd(1.0, 0.0))
+        fix(t);
     const uint64_t nfree = uint64_t(1) << (n - int(pos.size()));
-    const bool vec = dtype == SV_C64 && std::find(pos.begin(), pos.end(), 0) == pos.end() && t != 0 &&
-                     nfree >= 2;
+    const bool vec = dtype == SV_C64 && nfree >= 2;
     const bool nt = full_lines(pos, n, -1, dtype == SV_C64 ? 8 : 16);
     const cd dd[2] = {d0, d1};
     if (dtype == SV_C64) {
         Diag1Args<float> a{};
         a.m = make_unit_map(pos, fixed, 8, vec, vec ? nfree / 2 : nfree);
         a.tbit = uint64_t(1) << t;
+        a.lmask = lmask;
         fill_u(a.d, dd, 2);
         float *p = (float *)st;
         if (vec && nt)
@@ -679,6 +765,7 @@ hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const i
         Diag1Args<double> a{};
         a.m = make_unit_map(pos, fixed, 16, false, nfree);
         a.tbit = uint64_t(1) << t;
+        a.lmask = lmask;
         fill_u(a.d, dd, 2);
         if (nt)
             launch_diag1_t<double, false, true>((double *)st, a, s);

@@ -126,15 +126,19 @@ def test_one_qubit_gates_every_position(dtype):
                     assert e <= TOL[dtype] / 10, (name, t, ctrls, e)
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
 @pytest.mark.parametrize("n", [12, 16])
-def test_one_target_low_targets_with_high_controls(n):
-    """Targets 1..3 of complex64 states with no control on index bits 1..8
-    swap vector halves between lanes (the other modes stay for controls on
-    bits 0..8); every target and control placement against the reference."""
+def test_one_target_low_targets_with_high_controls(dtype, n):
+    """Targets inside one 128-byte line (index bits 1..3 of complex64, 0..2
+    of complex128) with no control on the bits above them up to 8 swap
+    partners between lanes (the other modes stay for controls on bits 4..8,
+    3..8); every target and control placement against the reference."""
     psi = W.random_state(n, 5 + n)
-    with State(n, B.SV_C64) as s:
-        for t in (1, 2, 3):
-            for ctrls in [(), (9,), (n - 1,), (9, n - 2), (9, 10, n - 1), (0,), (5,), (8, n - 1)]:
+    with State(n, dtype) as s:
+        for t in ((1, 2, 3) if dtype == B.SV_C64 else (0, 1, 2)):
+            for ctrls in [(), (9,), (n - 1,), (9, n - 2), (9, 10, n - 1), (0,), (5,), (8, n - 1), (3,)]:
+                if t in ctrls:
+                    continue
                 for name, params in (("u3", (0.3, 1.1, -0.7)), ("h", ()), ("x", ())):
                     g = Gate(name, (t,), ctrls, params)
                     ref = s.load(psi)
@@ -142,7 +146,45 @@ def test_one_target_low_targets_with_high_controls(n):
                     got = s.host()
                     want = oracle.apply_gate(ref.copy(), g)
                     e = maxerr(got, want)
-                    assert e <= TOL[B.SV_C64] / 10, (name, t, ctrls, e)
+                    assert e <= TOL[dtype] / 10, (name, t, ctrls, e)
+
+
+IN_LINE_CTRLS = [(0,), (1,), (2,), (3,), (1, 2), (0, 3), (0, 1, 2, 3), (2, 5), (3, -1), (0, 9), (1, 4, -1)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
+@pytest.mark.parametrize("n", [13, 16])
+def test_one_target_in_line_controls(dtype, n):
+    """Controls on the index bits of one 128-byte line are tested per
+    amplitude while whole lines are read and written: dense and diagonal
+    one-target gates (d0 = 1 or not) at low and high targets against the
+    reference, and every amplitude whose controls (or, for d0 = 1, target)
+    are not all set comes back bit for bit as it went in."""
+    psi = W.random_state(n, 17 + n)
+    kinds = [("u3", (0.3, 1.1, -0.7)), ("x", ()), ("h", ()), ("z", ()), ("s", ()), ("rz", (0.9,)),
+             ("p", (-1.3,))]
+    idx = np.arange(1 << n)
+    with State(n, dtype) as s:
+        for t in (0, 1, 2, 3, 4, 7, n - 1):
+            for cs in IN_LINE_CTRLS:
+                ctrls = tuple(sorted({q % n for q in cs} - {t}))
+                if not ctrls:
+                    continue
+                for name, params in kinds:
+                    g = Gate(name, (t,), ctrls, params)
+                    say(f"n={n} {DNAME[dtype]} {name} t={t} controls={ctrls}")
+                    ref = s.load(psi)
+                    B.sv_apply_circuit(s.h, [g])
+                    raw = s.host_raw()
+                    want = oracle.apply_gate(ref.copy(), g)
+                    e = maxerr(raw.astype(np.complex128), want)
+                    assert e <= TOL[dtype] / 10, (name, t, ctrls, e)
+                    cm = sum(1 << q for q in ctrls)
+                    keep = (idx & cm) != cm
+                    if name in ("z", "s", "p"):
+                        keep |= ((idx >> t) & 1) == 0
+                    before = np.asarray(psi, dtype=B.amp_dtype(dtype))
+                    assert np.array_equal(raw[keep].view(np.uint8), before[keep].view(np.uint8)), (name, t, ctrls)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DNAME.get)
