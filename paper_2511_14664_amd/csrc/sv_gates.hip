@@ -137,13 +137,15 @@ struct Gate1Args {
     R u[8];          // u00, u01, u10, u11 as (re, im)
 };
 
-// Whether amplitude index i meets the in-line controls lm (all set).
+// Whether amplitude index i meets the in-line controls lm (all set); LM:
+// the sweep has any (else the test compiles away).
+template <bool LM>
 __device__ __forceinline__ bool lines_on(uint64_t i, uint64_t lm)
 {
-    return (i & lm) == lm;
+    return !LM || (i & lm) == lm;
 }
 
-template <typename R, int MODE, bool NT, bool FULL>
+template <typename R, int MODE, bool NT, bool FULL, bool LM>
 __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Gate1Args<R> a)
 {
     using C = typename CT<R>::C;
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
         for (int k = 0; k < kItems; ++k)
             if (live(k))
                 x[k] = ldg<NT>(&v[b0 | index_off(k, a.m)]);
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             const C lo = upper ? y : x[k], hi = upper ? x[k] : y;
             const C ma = upper ? m10 : m00, mb = upper ? m11 : m01;
             const uint64_t i = b0 | index_off(k, a.m);
-            stg<NT>(&v[i], lines_on(i, a.lmask) ? cmad(mb, hi, cmul(ma, lo)) : x[k]);
+            stg<NT>(&v[i], lines_on<LM>(i, a.lmask) ? cmad(mb, hi, cmul(ma, lo)) : x[k]);
         }
     } else if constexpr (MODE == kVec) {
         float4 *v = reinterpret_cast<float4 *>(st);
@@ -192,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
                 hi[k] = ldg<NT>(&v[(i0 | a.tbit) >> 1]);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
@@ -201,9 +205,9 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             C h0 = make_float2(hi[k].x, hi[k].y), h1 = make_float2(hi[k].z, hi[k].w);
             C a0 = cmad(m01, h0, cmul(m00, l0)), b0_ = cmad(m11, h0, cmul(m10, l0));
             C a1 = cmad(m01, h1, cmul(m00, l1)), b1 = cmad(m11, h1, cmul(m10, l1));
-            if (!lines_on(i0, a.lmask))
+            if (!lines_on<LM>(i0, a.lmask))
                 a0 = l0, b0_ = h0;
-            if (!lines_on(i0 | 1, a.lmask))
+            if (!lines_on<LM>(i0 | 1, a.lmask))
                 a1 = l1, b1 = h1;
             stg<NT>(&v[i0 >> 1], make_float4(a0.x, a0.y, a1.x, a1.y));
             stg<NT>(&v[(i0 | a.tbit) >> 1], make_float4(b0_.x, b0_.y, b1.x, b1.y));
@@ -220,6 +224,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
         for (int k = 0; k < kItems; ++k)
             if (live(k))
                 x[k] = ldg<NT>(&v[(b0 | index_off(k, a.m)) >> 1]);
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
@@ -235,9 +240,9 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             const C ma = upper ? m10 : m00, mb = upper ? m11 : m01;
             C r0 = cmad(mb, h0, cmul(ma, l0)), r1 = cmad(mb, h1, cmul(ma, l1));
             const uint64_t i = b0 | index_off(k, a.m);
-            if (!lines_on(i, a.lmask))
+            if (!lines_on<LM>(i, a.lmask))
                 r0 = make_float2(x[k].x, x[k].y);
-            if (!lines_on(i | 1, a.lmask))
+            if (!lines_on<LM>(i | 1, a.lmask))
                 r1 = make_float2(x[k].z, x[k].w);
             stg<NT>(&v[i >> 1], make_float4(r0.x, r0.y, r1.x, r1.y));
         }
@@ -248,6 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
         for (int k = 0; k < kItems; ++k)
             if (live(k))
                 x[k] = ldg<NT>(&v[(b0 | index_off(k, a.m)) >> 1]);
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
             const C l = make_float2(x[k].x, x[k].y), h = make_float2(x[k].z, x[k].w);
             C y0 = cmad(m01, h, cmul(m00, l)), y1 = cmad(m11, h, cmul(m10, l));
             const uint64_t i = b0 | index_off(k, a.m);
-            if (!lines_on(i, a.lmask))
+            if (!lines_on<LM>(i, a.lmask))
                 y0 = l, y1 = h;
             stg<NT>(&v[i >> 1], make_float4(y0.x, y0.y, y1.x, y1.y));
         }
@@ -270,13 +276,14 @@ __global__ __launch_bounds__(kThreads) void k_gate1(R *__restrict__ st, const Ga
                 hi[k] = ldg<NT>(&v[i0 | a.tbit]);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
                 continue;
             const uint64_t i0 = b0 | index_off(k, a.m);
             C y0 = cmad(m01, hi[k], cmul(m00, lo[k])), y1 = cmad(m11, hi[k], cmul(m10, lo[k]));
-            if (!lines_on(i0, a.lmask))
+            if (!lines_on<LM>(i0, a.lmask))
                 y0 = lo[k], y1 = hi[k];
             stg<NT>(&v[i0], y0);
             stg<NT>(&v[i0 | a.tbit], y1);
@@ -299,7 +306,7 @@ struct Diag1Args {
     R d[4];          // d0, d1 as (re, im)
 };
 
-template <typename R, bool VEC, bool NT, bool FULL>
+template <typename R, bool VEC, bool NT, bool FULL, bool LM>
 __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Diag1Args<R> a)
 {
     using C = typename CT<R>::C;
@@ -318,6 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
         for (int k = 0; k < kItems; ++k)
             if (live(k))
                 x[k] = ldg<NT>(&v[(b0 | index_off(k, a.m)) >> 1]);
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
@@ -325,9 +333,9 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
             const uint64_t i = b0 | index_off(k, a.m);
             const C x0 = make_float2(x[k].x, x[k].y), x1 = make_float2(x[k].z, x[k].w);
             C p0 = cmul((i & a.tbit) ? d1 : d0, x0), p1 = cmul(((i | 1) & a.tbit) ? d1 : d0, x1);
-            if (!lines_on(i, a.lmask))
+            if (!lines_on<LM>(i, a.lmask))
                 p0 = x0;
-            if (!lines_on(i | 1, a.lmask))
+            if (!lines_on<LM>(i | 1, a.lmask))
                 p1 = x1;
             stg<NT>(&v[i >> 1], make_float4(p0.x, p0.y, p1.x, p1.y));
         }
@@ -338,12 +346,13 @@ __global__ __launch_bounds__(kThreads) void k_diag1(R *__restrict__ st, const Di
         for (int k = 0; k < kItems; ++k)
             if (live(k))
                 x[k] = ldg<NT>(&v[b0 | index_off(k, a.m)]);
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (!live(k))
                 continue;
             const uint64_t i = b0 | index_off(k, a.m);
-            stg<NT>(&v[i], lines_on(i, a.lmask) ? cmul((i & a.tbit) ? d1 : d0, x[k]) : x[k]);
+            stg<NT>(&v[i], lines_on<LM>(i, a.lmask) ? cmul((i & a.tbit) ? d1 : d0, x[k]) : x[k]);
         }
     }
 }
@@ -627,13 +636,22 @@ static dim3 unit_grid(uint64_t nunits)
     return tile_grid((nunits + uint64_t(kThreads) * kItems - 1) / (uint64_t(kThreads) * kItems));
 }
 
+template <typename R, int MODE, bool NT, bool LM>
+void launch_gate1_l(R *p, const Gate1Args<R> &a, hipStream_t s)
+{
+    if (a.m.nunits >= uint64_t(kThreads) * kItems)
+        hipLaunchKernelGGL((k_gate1<R, MODE, NT, true, LM>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+    else
+        hipLaunchKernelGGL((k_gate1<R, MODE, NT, false, LM>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+}
+
 template <typename R, int MODE, bool NT>
 void launch_gate1_t(R *p, const Gate1Args<R> &a, hipStream_t s)
 {
-    if (a.m.nunits >= uint64_t(kThreads) * kItems)
-        hipLaunchKernelGGL((k_gate1<R, MODE, NT, true>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+    if (a.lmask)
+        launch_gate1_l<R, MODE, NT, true>(p, a, s);
     else
-        hipLaunchKernelGGL((k_gate1<R, MODE, NT, false>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+        launch_gate1_l<R, MODE, NT, false>(p, a, s);
 }
 
 hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const int *ctl, int c,
@@ -713,13 +731,22 @@ hipError_t launch_gate1(void *st, int n, int dtype, const cd U[4], int t, const 
     return hipGetLastError();
 }
 
+template <typename R, bool VEC, bool NT, bool LM>
+void launch_diag1_l(R *p, const Diag1Args<R> &a, hipStream_t s)
+{
+    if (a.m.nunits >= uint64_t(kThreads) * kItems)
+        hipLaunchKernelGGL((k_diag1<R, VEC, NT, true, LM>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+    else
+        hipLaunchKernelGGL((k_diag1<R, VEC, NT, false, LM>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+}
+
 template <typename R, bool VEC, bool NT>
 void launch_diag1_t(R *p, const Diag1Args<R> &a, hipStream_t s)
 {
-    if (a.m.nunits >= uint64_t(kThreads) * kItems)
-        hipLaunchKernelGGL((k_diag1<R, VEC, NT, true>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+    if (a.lmask)
+        launch_diag1_l<R, VEC, NT, true>(p, a, s);
     else
-        hipLaunchKernelGGL((k_diag1<R, VEC, NT, false>), unit_grid(a.m.nunits), dim3(kThreads), 0, s, p, a);
+        launch_diag1_l<R, VEC, NT, false>(p, a, s);
 }
 
 hipError_t launch_diag1(void *st, int n, int dtype, cd d0, cd d1, int t, const int *ctl, int c,
