@@ -9,6 +9,11 @@ namespace sv {
 
 constexpr int kBatchMaxTileLog = 13;
 constexpr int kBatchMaxTerms = 64;
+// Threads per workgroup (2^kBatchThreadLog); one workgroup holds one LDS
+// tile.  512 threads took 1.5x (complex64) and 1.7x (complex128) longer on
+// the 512-circuit HEA batch than 256.
+constexpr int kBatchThreadLog = 8;
+constexpr int kBatchThreads = 1 << kBatchThreadLog;
 
 struct BInst {
     uint64_t state_off;  // amplitude offset into the batch state buffer (multi-pass circuits)
@@ -31,7 +36,15 @@ struct BPass {
     uint32_t ntiles;
     uint32_t need;                   // finished tiles of earlier passes required before start
     int32_t last;                    // last pass: reduce expectation values instead of storing
+    uint32_t mat0;                   // first matrix element of the pass's steps
+    uint32_t nmat;                   // matrix elements of the pass's steps, contiguous from mat0
 };
+
+// Per-pass copies in LDS, taken at the start of every task: the first
+// kBatchStepCache steps, and every matrix when they fit in
+// kBatchMatCacheBytes (else the steps read them from global memory).
+constexpr int kBatchStepCache = 128;
+constexpr int kBatchMatCacheBytes = 8192;
 
 // One in-LDS gate step.  type 0: dense one-qubit on tile bit a; 1: one-qubit
 // on tile bit a controlled by tile bit b; 2: dense two-qubit, matrix index bit
@@ -43,6 +56,14 @@ struct BStep {
     uint8_t b;
     uint8_t pad;
 };
+
+// Dynamic LDS bytes of a batch launch with tiles of 2^tile_log amplitudes of
+// amp_bytes each: tile | per-wave partial sums | matrix copy | step copy.
+constexpr size_t batch_lds_bytes(int tile_log, size_t amp_bytes)
+{
+    return (amp_bytes << tile_log) + size_t(kBatchThreads / 64) * 16 * sizeof(double) + kBatchMatCacheBytes +
+           kBatchStepCache * sizeof(BStep);
+}
 
 struct BTask {
     uint32_t inst;

@@ -32,6 +32,34 @@ __device__ __forceinline__ uint32_t ins2(uint32_t j, int lo, int hi)
     return ins1(ins1(j, lo), hi);
 }
 
+// acc + u * v as four fused multiply-adds (the state arithmetic of the
+// in-LDS sweeps; every product is rounded once, into the running sum)
+__device__ __forceinline__ float fma_r(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fma_r(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+template <typename C>
+__device__ __forceinline__ C cfma(C u, C v, C acc)
+{
+    acc.x = fma_r(u.x, v.x, acc.x);
+    acc.x = fma_r(-u.y, v.y, acc.x);
+    acc.y = fma_r(u.x, v.y, acc.y);
+    acc.y = fma_r(u.y, v.x, acc.y);
+    return acc;
+}
+
+// Element of the LDS tile at byte offset o.  swz() is linear over XOR, so
+// the offsets of a group's members are one XOR away from its first one.
+template <typename C>
+__device__ __forceinline__ C &lds_at(unsigned char *tileb, uint32_t o)
+{
+    return *reinterpret_cast<C *>(tileb + o);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -41,12 +69,22 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
 {
     using C = typename CT<R>::C;
+    // tile amplitudes per thread in flight between global memory and LDS, and
+    // gate groups per thread per LDS sweep iteration (fewer for complex128,
+    // whose matrix and groups take twice the registers)
+    constexpr uint32_t kU = 8;
+    typedef R VU __attribute__((ext_vector_type(2 * kU)));
+    constexpr int kG = std::is_same<R, float>::value ? 4 : 2;
     extern __shared__ __align__(16) unsigned char smem[];
     C *tile = reinterpret_cast<C *>(smem);
-    double *red = reinterpret_cast<double *>(smem + (sizeof(C) << a.tile_log_max));  // [4][16]
+    unsigned char *tileb = smem;
+    double *red = reinterpret_cast<double *>(smem + (sizeof(C) << a.tile_log_max));  // [waves][16]
+    C *mcache = reinterpret_cast<C *>(red + (kBatchThreads / 64) * 16);
+    BStep *scache = reinterpret_cast<BStep *>(reinterpret_cast<unsigned char *>(mcache) + kBatchMatCacheBytes);
+    constexpr uint32_t kMatCap = kBatchMatCacheBytes / sizeof(C);
     __shared__ uint32_t s_task;
     __shared__ int s_flag;
 
@@ -97,6 +135,17 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
 
+        // the pass's steps and matrices into LDS (visible after the barrier
+        // that ends the tile load; the previous task's last reads of them
+        // ended at its final barrier)
+        const bool cached = ps.nsteps <= kBatchStepCache && ps.nmat <= kMatCap;
+        if (cached) {
+            for (int i = tid; i < ps.nsteps; i += kBatchThreads)
+                scache[i] = a.steps[ps.step0 + i];
+            for (uint32_t i = tid; i < ps.nmat; i += kBatchThreads)
+                mcache[i] = mats[ps.mat0 + i];
+        }
+
         // tile index -> base, and per-thread low part of the tile offsets
         uint64_t base = tk.tile;
         for (int b = 0; b < lp; ++b) {
@@ -104,17 +153,25 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
             base = (base & m) | ((base & ~m) << 1);
         }
         uint64_t off_lo = 0;
-        for (int b = 0; b < 8 && b < lp; ++b)
+        for (int b = 0; b < kBatchThreadLog && b < lp; ++b)
             if ((tid >> b) & 1)
                 off_lo |= ps.dep[b];
+        // deposits of the tile bits above the thread bits in registers: the
+        // pass table is not re-read after every store of the tile
+        constexpr int kHi = kBatchMaxTileLog - kBatchThreadLog;
+        uint64_t dep_hi[kHi];
+#pragma unroll
+        for (int b = 0; b < kHi; ++b)
+            dep_hi[b] = b + kBatchThreadLog < lp ? ps.dep[b + kBatchThreadLog] : 0;
         auto off_of = [&](uint32_t s) {
             uint64_t off = off_lo;
-            for (int b = 8; b < lp; ++b)
-                if ((s >> (b - 8)) & 1)
-                    off |= ps.dep[b];
+#pragma unroll
+            for (int b = 0; b < kHi; ++b)
+                if ((s >> b) & 1)
+                    off |= dep_hi[b];
             return off;
         };
-        const uint32_t nsteps_x = TA >= kThreads ? TA / kThreads : 1;
+        const uint32_t nsteps_x = TA >= kBatchThreads ? TA / kBatchThreads : 1;
         const bool active = uint32_t(tid) < TA;
         C *st = states + in.state_off;
 
@@ -122,41 +179,86 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
             for (uint32_t s = 0; s < nsteps_x; ++s) {
                 if (!active)
                     break;
-                const uint32_t x = s * kThreads + uint32_t(tid);
+                const uint32_t x = s * kBatchThreads + uint32_t(tid);
                 C z;
                 z.x = (tk.tile == 0 && x == 0) ? R(1) : R(0);
                 z.y = R(0);
                 tile[swz(x)] = z;
             }
+        } else if (nsteps_x >= kU) {
+            // kU global loads in flight per thread before the first LDS store
+            // (nsteps_x and kU are powers of two: whole chunks)
+            for (uint32_t s0 = 0; s0 < nsteps_x; s0 += kU) {
+                VU v;  // a vector, not an array: stays in registers
+#pragma unroll
+                for (uint32_t u = 0; u < kU; ++u) {
+                    const C x = st[base + off_of(s0 + u)];
+                    v[2 * u] = x.x;
+                    v[2 * u + 1] = x.y;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kU; ++u) {
+                    C x;
+                    x.x = v[2 * u];
+                    x.y = v[2 * u + 1];
+                    tile[swz((s0 + u) * kBatchThreads + uint32_t(tid))] = x;
+                }
+            }
         } else {
             for (uint32_t s = 0; s < nsteps_x; ++s) {
                 if (!active)
                     break;
-                tile[swz(s * kThreads + uint32_t(tid))] = st[base + off_of(s)];
+                tile[swz(s * kBatchThreads + uint32_t(tid))] = st[base + off_of(s)];
             }
         }
         __syncthreads();
 
-        for (int si = 0; si < ps.nsteps; ++si) {
-            const BStep sp = a.steps[ps.step0 + si];
-            const C *M = mats + sp.mat;
+        // the steps, reading step records and matrices from the LDS copies
+        // (LDS) or from global memory (false)
+        auto sweeps = [&](auto lds_tag) __attribute__((always_inline)) {
+          constexpr bool kLds = decltype(lds_tag)::value;
+          for (int si = 0; si < ps.nsteps; ++si) {
+            BStep sp;
+            if constexpr (kLds)
+                sp = scache[si];
+            else
+                sp = a.steps[ps.step0 + si];
+            const C *M = kLds ? mcache + (sp.mat - ps.mat0) : mats + sp.mat;
             const int ta = sp.a, tb = sp.b;
-            if (sp.type == 0) {
-                const C m00 = M[0], m01 = M[1], m10 = M[2], m11 = M[3];
-                for (uint32_t j = tid; j < TA / 2; j += kThreads) {
-                    const uint32_t x0 = ins1(j, ta), x1 = x0 | (1u << ta);
-                    const C v0 = tile[swz(x0)], v1 = tile[swz(x1)];
-                    tile[swz(x0)] = cmad(m01, v1, cmul(m00, v0));
-                    tile[swz(x1)] = cmad(m11, v1, cmul(m10, v0));
-                }
-            } else if (sp.type == 1) {
+            // Each sweep takes kG groups per thread per iteration, all LDS
+            // reads before the first write (the groups are disjoint), while
+            // at least kG * kBatchThreads groups remain; then one at a time.
+            if (sp.type <= 1) {
                 const C m00 = M[0], m01 = M[1], m10 = M[2], m11 = M[3];
                 const int lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
-                for (uint32_t j = tid; j < TA / 4; j += kThreads) {
-                    const uint32_t x0 = ins2(j, lo, hi) | (1u << tb), x1 = x0 | (1u << ta);
-                    const C v0 = tile[swz(x0)], v1 = tile[swz(x1)];
-                    tile[swz(x0)] = cmad(m01, v1, cmul(m00, v0));
-                    tile[swz(x1)] = cmad(m11, v1, cmul(m10, v0));
+                const bool ctl = sp.type == 1;
+                const uint32_t cnt = ctl ? TA / 4 : TA / 2;
+                const uint32_t cbit = ctl ? 1u << tb : 0u;
+                const uint32_t pt = swz(1u << ta) * uint32_t(sizeof(C));  // partner: byte offset XOR
+                auto first = [&](uint32_t j) __attribute__((always_inline)) {
+                    return swz((ctl ? ins2(j, lo, hi) : ins1(j, ta)) | cbit) * uint32_t(sizeof(C));
+                };
+                uint32_t j = tid;
+                for (; j + (kG - 1) * kBatchThreads < cnt; j += kG * kBatchThreads) {
+                    uint32_t o[kG];
+                    C v0[kG], v1[kG];
+#pragma unroll
+                    for (int g = 0; g < kG; ++g) {
+                        o[g] = first(j + g * kBatchThreads);
+                        v0[g] = lds_at<C>(tileb, o[g]);
+                        v1[g] = lds_at<C>(tileb, o[g] ^ pt);
+                    }
+#pragma unroll
+                    for (int g = 0; g < kG; ++g) {
+                        lds_at<C>(tileb, o[g]) = cfma(m01, v1[g], cmul(m00, v0[g]));
+                        lds_at<C>(tileb, o[g] ^ pt) = cfma(m11, v1[g], cmul(m10, v0[g]));
+                    }
+                }
+                for (; j < cnt; j += kBatchThreads) {
+                    const uint32_t o = first(j);
+                    const C v0 = lds_at<C>(tileb, o), v1 = lds_at<C>(tileb, o ^ pt);
+                    lds_at<C>(tileb, o) = cfma(m01, v1, cmul(m00, v0));
+                    lds_at<C>(tileb, o ^ pt) = cfma(m11, v1, cmul(m10, v0));
                 }
             } else {
                 C m[16];
@@ -164,33 +266,79 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
                 for (int e = 0; e < 16; ++e)
                     m[e] = M[e];
                 const int lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
-                for (uint32_t j = tid; j < TA / 4; j += kThreads) {
-                    const uint32_t b0 = ins2(j, lo, hi);
-                    uint32_t xi[4];
-                    C v[4];
+                const uint32_t cnt = TA / 4;
+                // byte-offset XORs of the group members (matrix index e:
+                // bit 0 on tile bit ta, bit 1 on tile bit tb)
+                uint32_t px[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        xi[e] = b0 | (uint32_t(e & 1) << ta) | (uint32_t(e >> 1) << tb);
-                        v[e] = tile[swz(xi[e])];
-                    }
+                for (int e = 0; e < 4; ++e)
+                    px[e] = swz(((e & 1) ? 1u << ta : 0u) | ((e & 2) ? 1u << tb : 0u)) * uint32_t(sizeof(C));
+                auto group = [&](const C *v, uint32_t o) __attribute__((always_inline)) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        C acc = czero<C>();
+                        C acc = cmul(m[r * 4], v[0]);
 #pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            acc = cmad(m[r * 4 + c], v[c], acc);
-                        tile[swz(xi[r])] = acc;
+                        for (int c = 1; c < 4; ++c)
+                            acc = cfma(m[r * 4 + c], v[c], acc);
+                        lds_at<C>(tileb, o ^ px[r]) = acc;
                     }
+                };
+                uint32_t j = tid;
+                for (; j + (kG - 1) * kBatchThreads < cnt; j += kG * kBatchThreads) {
+                    uint32_t o[kG];
+                    C v[kG][4];
+#pragma unroll
+                    for (int g = 0; g < kG; ++g) {
+                        o[g] = swz(ins2(j + g * kBatchThreads, lo, hi)) * uint32_t(sizeof(C));
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            v[g][e] = lds_at<C>(tileb, o[g] ^ px[e]);
+                    }
+#pragma unroll
+                    for (int g = 0; g < kG; ++g)
+                        group(v[g], o[g]);
+                }
+                for (; j < cnt; j += kBatchThreads) {
+                    const uint32_t o = swz(ins2(j, lo, hi)) * uint32_t(sizeof(C));
+                    C v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        v[e] = lds_at<C>(tileb, o ^ px[e]);
+                    group(v, o);
                 }
             }
             __syncthreads();
-        }
+          }
+        };
+        if (cached)
+            sweeps(std::true_type{});
+        else
+            sweeps(std::false_type{});
 
         if (!ps.last) {
-            for (uint32_t s = 0; s < nsteps_x; ++s) {
-                if (!active)
-                    break;
-                st[base + off_of(s)] = tile[swz(s * kThreads + uint32_t(tid))];
+            if (nsteps_x >= kU) {
+                for (uint32_t s0 = 0; s0 < nsteps_x; s0 += kU) {
+                    VU v;
+#pragma unroll
+                    for (uint32_t u = 0; u < kU; ++u) {
+                        const C x = tile[swz((s0 + u) * kBatchThreads + uint32_t(tid))];
+                        v[2 * u] = x.x;
+                        v[2 * u + 1] = x.y;
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kU; ++u) {
+                        C x;
+                        x.x = v[2 * u];
+                        x.y = v[2 * u + 1];
+                        st[base + off_of(s0 + u)] = x;
+                    }
+                }
+            } else {
+                for (uint32_t s = 0; s < nsteps_x; ++s) {
+                    if (!active)
+                        break;
+                    st[base + off_of(s)] = tile[swz(s * kBatchThreads + uint32_t(tid))];
+                }
             }
             __threadfence();
             __syncthreads();
@@ -206,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
                 for (uint32_t s = 0; s < nsteps_x; ++s) {
                     if (!active)
                         break;
-                    const uint32_t x = s * kThreads + uint32_t(tid);
+                    const uint32_t x = s * kBatchThreads + uint32_t(tid);
                     const uint64_t gi = base + off_of(s);
                     const C v = tile[swz(x)];
                     const double p = double(v.x) * double(v.x) + double(v.y) * double(v.y);
@@ -223,7 +371,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
                 }
                 __syncthreads();
                 if (tid < 16 && c0 + tid < in.nterms) {
-                    const double v = ((red[tid] + red[16 + tid]) + red[32 + tid]) + red[48 + tid];
+                    double v = red[tid];
+#pragma unroll
+                    for (int w = 1; w < kBatchThreads / 64; ++w)
+                        v += red[16 * w + tid];
                     if (ps.ntiles == 1)
                         a.out[in.out0 + c0 + tid] = v;
                     else
@@ -239,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchArgs a)
                 __syncthreads();
                 if (s_flag) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    for (int j = tid; j < in.nterms; j += kThreads) {
+                    for (int j = tid; j < in.nterms; j += kBatchThreads) {
                         double sum = 0.0;
                         for (uint32_t tl = 0; tl < ps.ntiles; ++tl)
                             sum += __hip_atomic_load(&a.partials[in.part0 + size_t(tl) * in.nterms + j],
@@ -264,9 +415,9 @@ __global__ void k_batch_fill(uint32_t *ctr, uint32_t n)
 hipError_t launch_batch(int dtype, const BatchArgs &a, uint32_t grid, size_t lds, hipStream_t s)
 {
     if (dtype == SV_C64)
-        hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), lds, s, a);
     else
-        hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -286,7 +437,7 @@ uint32_t batch_grid(int dtype, size_t lds)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess || per_cu <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBatchThreads, lds) != hipSuccess || per_cu <= 0)
         per_cu = 1;
     return uint32_t(cus * per_cu);
 }

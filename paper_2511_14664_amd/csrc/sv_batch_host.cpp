@@ -326,6 +326,8 @@ int build(sv_batch *b)
                 b->steps.push_back(sp);
             }
             bp.nsteps = int(steps.size()) - bp.step0;
+            bp.mat0 = bp.nsteps > 0 ? steps[size_t(bp.step0)].mat : mat;
+            bp.nmat = mat - bp.mat0;
             passes.push_back(bp);
         }
         ntiles_of[i].assign(pp.size(), nt);
@@ -379,7 +381,7 @@ int build(sv_batch *b)
         set_error("batch: upload synchronisation failed");
         return SV_EDEVICE;
     }
-    b->lds = (size_t(S) << L) + 4 * 16 * sizeof(double);
+    b->lds = batch_lds_bytes(L, S);
     b->grid = batch_grid(b->dtype, b->lds);
 
     BatchArgs a{};
