@@ -10,9 +10,10 @@
 // wait always ends.  The wait is still bounded: past the spin limit the task
 // raises the error flag, every workgroup drains, and the host reports it.
 //
-// Cross-workgroup visibility uses agent-scope release (every thread fences
-// its own stores, then one atomic increment) and acquire (atomic load, then an
-// agent-scope acquire fence in every thread).
+// Cross-workgroup visibility: every thread issues an agent-scope release
+// fence after its stores (L2 write-back and wait), then a barrier, then one
+// atomic increment; a consumer reads the count, passes a barrier, and every
+// thread issues an agent-scope acquire fence before loading.
 #include "sv_batch.h"
 #include "sv_device.h"
 
@@ -58,6 +59,15 @@ template <typename C>
 __device__ __forceinline__ C &lds_at(unsigned char *tileb, uint32_t o)
 {
     return *reinterpret_cast<C *>(tileb + o);
+}
+
+// Agent-scope release of this wave's global stores, completed before the
+// wave goes on: the compiler may otherwise leave the write-back's wait for the
+// next atomic, which only one wave of the workgroup issues.
+__device__ __forceinline__ void publish()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt and lgkmcnt all zero
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -117,7 +127,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
             if (tid == 0) {
                 int ok = 1;
                 uint32_t spins = 0;
-                while (__hip_atomic_load(&done[tk.inst], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < ps.need) {
+                while (__hip_atomic_load(&done[tk.inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ps.need) {
                     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                         ++spins > a.spin_limit) {
                         ok = 0;
@@ -132,6 +142,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
             __syncthreads();
             if (!s_flag)
                 break;
+            // pairs with the producers' release (the count was read relaxed)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
 
@@ -340,10 +351,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
                     st[base + off_of(s)] = tile[swz(s * kBatchThreads + uint32_t(tid))];
                 }
             }
-            __threadfence();
+            // Every wave writes its stores back past L2 (an agent-scope release:
+            // write-back, no invalidate) and waits for the write-back before
+            // the barrier; then one thread raises the count.
+            publish();
             __syncthreads();
             if (tid == 0)
-                atomicAdd(&done[tk.inst], 1u);
+                __hip_atomic_fetch_add(&done[tk.inst], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const uint64_t *zm = a.zmasks + in.term0;
             for (int c0 = 0; c0 < in.nterms; c0 += 16) {
@@ -383,10 +397,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
                 __syncthreads();
             }
             if (ps.ntiles > 1) {
-                __threadfence();
+                publish();
                 __syncthreads();
                 if (tid == 0)
-                    s_flag = atomicAdd(&fin[tk.inst], 1u) == ps.ntiles - 1;
+                    s_flag = __hip_atomic_fetch_add(&fin[tk.inst], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                             ps.ntiles - 1;
                 __syncthreads();
                 if (s_flag) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
