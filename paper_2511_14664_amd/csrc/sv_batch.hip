@@ -70,6 +70,21 @@ __device__ __forceinline__ void publish()
     __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt and lgkmcnt all zero
 }
 
+// Device-scope store of one amplitude (relaxed atomic 64-bit stores): the
+// write goes through the XCD's L2, so the release after the tile finds no
+// dirty lines of it there to write back.
+template <typename C>
+__device__ __forceinline__ void store_dev(C *p, C v)
+{
+    static_assert(sizeof(C) % 8 == 0, "amplitudes of 8 or 16 bytes");
+    uint64_t w[sizeof(C) / 8];
+    __builtin_memcpy(w, &v, sizeof(C));
+    uint64_t *q = reinterpret_cast<uint64_t *>(p);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(C) / 8; ++i)
+        __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -341,14 +356,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
                         C x;
                         x.x = v[2 * u];
                         x.y = v[2 * u + 1];
-                        st[base + off_of(s0 + u)] = x;
+                        store_dev(&st[base + off_of(s0 + u)], x);
                     }
                 }
             } else {
                 for (uint32_t s = 0; s < nsteps_x; ++s) {
                     if (!active)
                         break;
-                    st[base + off_of(s)] = tile[swz(s * kBatchThreads + uint32_t(tid))];
+                    store_dev(&st[base + off_of(s)], tile[swz(s * kBatchThreads + uint32_t(tid))]);
                 }
             }
             // Every wave writes its stores back past L2 (an agent-scope release:
