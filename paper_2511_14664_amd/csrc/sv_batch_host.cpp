@@ -10,10 +10,12 @@
 // one-qubit runs (fuse width 1) or blocks of at most two qubits (width 2),
 // using the same greedy grouping as the sweep planner.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "sv_batch.h"
@@ -207,31 +209,51 @@ void fill_pass_bits(BPass &bp, uint64_t bits, int q)
 }
 
 // Compute the current matrices of every step into the pinned buffer.
+// The step matrices of every circuit into the pinned staging buffer: the
+// circuits' gate matrices, then each step's fused product.  Circuits are
+// independent and their steps contiguous, so host threads take whole
+// circuits from a shared counter (each writes only its own steps' slots).
 void fill_matrices(sv_batch *b)
 {
-    std::vector<std::vector<Block>> blocks(b->ninst);
-    for (int i = 0; i < b->ninst; ++i)
-        blocks[i] = circuit_blocks(b, i);
-    for (const StepPlan &sp : b->steps) {
-        std::vector<const Block *> mem;
-        for (int m : sp.members)
-            mem.push_back(&blocks[sp.inst][m]);
-        const Block f = fuse(mem, sp.qmask);
-        const size_t dd = size_t(sp.d) * sp.d;
-        if (b->dtype == SV_C64) {
-            float *dst = static_cast<float *>(b->h_mats) + 2 * size_t(sp.mat);
-            for (size_t e = 0; e < dd; ++e) {
-                dst[2 * e] = float(f.U[e].real());
-                dst[2 * e + 1] = float(f.U[e].imag());
-            }
-        } else {
-            double *dst = static_cast<double *>(b->h_mats) + 2 * size_t(sp.mat);
-            for (size_t e = 0; e < dd; ++e) {
-                dst[2 * e] = f.U[e].real();
-                dst[2 * e + 1] = f.U[e].imag();
+    std::vector<size_t> first(size_t(b->ninst) + 1, b->steps.size());
+    for (size_t k = b->steps.size(); k-- > 0;)
+        first[size_t(b->steps[k].inst)] = k;
+    for (int i = b->ninst - 1; i >= 0; --i)
+        first[size_t(i)] = std::min(first[size_t(i)], first[size_t(i) + 1]);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (int i; (i = next.fetch_add(1)) < b->ninst;) {
+            const std::vector<Block> blocks = circuit_blocks(b, i);
+            for (size_t k = first[size_t(i)]; k < first[size_t(i) + 1]; ++k) {
+                const StepPlan &sp = b->steps[k];
+                std::vector<const Block *> mem;
+                for (int m : sp.members)
+                    mem.push_back(&blocks[size_t(m)]);
+                const Block f = fuse(mem, sp.qmask);
+                const size_t dd = size_t(sp.d) * sp.d;
+                if (b->dtype == SV_C64) {
+                    float *dst = static_cast<float *>(b->h_mats) + 2 * size_t(sp.mat);
+                    for (size_t e = 0; e < dd; ++e) {
+                        dst[2 * e] = float(f.U[e].real());
+                        dst[2 * e + 1] = float(f.U[e].imag());
+                    }
+                } else {
+                    double *dst = static_cast<double *>(b->h_mats) + 2 * size_t(sp.mat);
+                    for (size_t e = 0; e < dd; ++e) {
+                        dst[2 * e] = f.U[e].real();
+                        dst[2 * e + 1] = f.U[e].imag();
+                    }
+                }
             }
         }
-    }
+    };
+    const int nt = std::max(1, std::min({16, int(std::thread::hardware_concurrency()), b->ninst}));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t)
+        pool.emplace_back(work);
+    work();
+    for (std::thread &t : pool)
+        t.join();
 }
 
 int build(sv_batch *b)
