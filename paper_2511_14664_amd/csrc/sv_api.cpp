@@ -1570,54 +1570,37 @@ static int check_shots(const double *uniforms, int shots, const int64_t *out)
     return SV_OK;
 }
 
-// Shots from the totals bs[0..nb) of consecutive 2^lbs-amplitude blocks (on
-// the host): the inclusive prefix of the totals in FP64, sequentially; each
-// shot's block (first prefix above u * norm) and its residual target; then
-// the in-block search on the device.  d_work holds 3 * shots doubles; the
-// pinned staging is reused, so bs must not live in the part of it that the
-// shots' blocks and targets overwrite before the prefix is taken (it is
-// taken first).
-static int sample_from_blocks(sv_state *h, const double *bs, uint64_t nb, int lbs, const double *uniforms, int shots,
-                              double *d_work, int64_t *out)
+// Shot work area in device scratch: blocks (int64) | targets | outputs
+// (int64) | uniforms, shots entries each.
+constexpr uint64_t kShotWork = 4;
+
+// Queue the shots from the totals d_bs[0..nb) of consecutive 2^lbs-amplitude
+// blocks, all on the device: the uniforms go up through the pinned staging
+// (its first shots * 8 bytes, so no copy into it may be pending), each shot's
+// block and residual target are chosen from the totals, then the in-block
+// search writes physical indices to the outputs.  Returns the outputs.
+static int queue_samples(sv_state *h, const double *d_bs, uint64_t nb, int lbs, const double *uniforms, int shots,
+                         double *d_work, int64_t **d_out)
 {
-    std::vector<double> pre(nb);
-    double run = 0.0;
-    uint64_t last_pos = 0;
-    for (uint64_t b = 0; b < nb; ++b) {
-        run += bs[b];
-        pre[b] = run;
-        if (bs[b] > 0.0)
-            last_pos = b;
-    }
-    const double norm = run;
-    const double last_total = bs[last_pos];
-    std::vector<int64_t> blk(shots);
-    std::vector<double> tgt(shots);
-    for (int s = 0; s < shots; ++s) {
-        const double t = uniforms[s] * norm;
-        const uint64_t b = uint64_t(std::upper_bound(pre.begin(), pre.end(), t) - pre.begin());
-        if (b >= nb) {
-            blk[s] = int64_t(last_pos);
-            tgt[s] = last_total;  // no in-block index exceeds it: last nonzero is returned
-        } else {
-            blk[s] = int64_t(b);
-            tgt[s] = t - (b > 0 ? pre[b - 1] : 0.0);
-        }
-    }
     int64_t *d_blk = reinterpret_cast<int64_t *>(d_work);
     double *d_tgt = d_work + shots;
-    int64_t *d_out = reinterpret_cast<int64_t *>(d_work + 2 * uint64_t(shots));
-    memcpy(h->h_pinned, blk.data(), shots * 8);
-    memcpy(static_cast<char *>(h->h_pinned) + shots * 8, tgt.data(), shots * 8);
-    HIP_TRY(hipMemcpyAsync(d_blk, h->h_pinned, 2 * uint64_t(shots) * 8, hipMemcpyHostToDevice, h->stream));
-    hipError_t e = launch_sample_search(h->d_state, h->n, h->dtype, d_blk, d_tgt, shots, d_out, lbs, h->stream);
+    *d_out = reinterpret_cast<int64_t *>(d_work + 2 * uint64_t(shots));
+    double *d_uni = d_work + 3 * uint64_t(shots);
+    memcpy(h->h_pinned, uniforms, uint64_t(shots) * 8);
+    HIP_TRY(hipMemcpyAsync(d_uni, h->h_pinned, uint64_t(shots) * 8, hipMemcpyHostToDevice, h->stream));
+    hipError_t e = launch_sample_prep(d_bs, nb, d_uni, shots, d_blk, d_tgt, h->stream);
+    if (e == hipSuccess)
+        e = launch_sample_search(h->d_state, h->n, h->dtype, d_blk, d_tgt, shots, *d_out, lbs, h->stream);
     if (e != hipSuccess) {
-        set_error("sample search launch failed: %s", hipGetErrorString(e));
+        set_error("sampling launch failed: %s", hipGetErrorString(e));
         return SV_EDEVICE;
     }
-    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_out, uint64_t(shots) * 8, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    const int64_t *phys = static_cast<const int64_t *>(h->h_pinned);
+    return SV_OK;
+}
+
+// Physical sample indices (copied back) to logical ones.
+static void map_samples(const sv_state *h, const int64_t *phys, int shots, int64_t *out)
+{
     const bool ident = identity_map(h);
     for (int s = 0; s < shots; ++s) {
         if (ident) {
@@ -1629,7 +1612,6 @@ static int sample_from_blocks(sv_state *h, const double *bs, uint64_t nb, int lb
             out[s] = l;
         }
     }
-    return SV_OK;
 }
 
 int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
@@ -1644,13 +1626,11 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
     DeviceGuard dg(h->device);
     const int lbs = sample_log_block(h->n);
     const uint64_t nb = uint64_t(1) << (h->n - lbs);
-    // scratch: block sums | blocks (int64) | targets | outputs (int64)
-    const uint64_t need = (nb + 3 * uint64_t(shots)) * 8;
-    rc = ensure_scratch(h, need);
+    // scratch: block sums | shot work; pinned: the uniforms, then the outputs
+    rc = ensure_scratch(h, (nb + kShotWork * uint64_t(shots)) * 8);
     if (rc != SV_OK)
         return rc;
-    // pinned: the block sums, then (after the prefix) the shots' staging
-    rc = ensure_pinned(h, std::max<uint64_t>(nb, 2 * uint64_t(shots)) * 8);
+    rc = ensure_pinned(h, uint64_t(shots) * 8);
     if (rc != SV_OK)
         return rc;
     double *d_bs = h->d_scratch;
@@ -1659,10 +1639,14 @@ int sv_sample(sv_handle h, const double *uniforms, int shots, int64_t *out)
         set_error("block-sum launch failed: %s", hipGetErrorString(e));
         return SV_EDEVICE;
     }
-    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_bs, nb * 8, hipMemcpyDeviceToHost, h->stream));
+    int64_t *d_out = nullptr;
+    rc = queue_samples(h, d_bs, nb, lbs, uniforms, shots, h->d_scratch + nb, &d_out);
+    if (rc != SV_OK)
+        return rc;
+    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_out, uint64_t(shots) * 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    return sample_from_blocks(h, static_cast<const double *>(h->h_pinned), nb, lbs, uniforms, shots, h->d_scratch + nb,
-                              out);
+    map_samples(h, static_cast<const int64_t *>(h->h_pinned), shots, out);
+    return SV_OK;
 }
 
 int sv_readout(sv_handle h, const int *qubits, int m, double *probs, const char *const *terms, int nterms,
@@ -1722,13 +1706,14 @@ int sv_readout(sv_handle h, const int *qubits, int m, double *probs, const char 
     const uint64_t nb = uint64_t(1) << (h->n - lbs);
     const uint64_t nbins = want_p ? uint64_t(1) << m : 0;
     const uint64_t red = readout_scratch_doubles(h->n, mm, phys, h->dtype);
-    // scratch: fold and Z partials | block totals | marginal | Z values | shots (3 per shot)
-    const uint64_t need = red + nb + nbins + uint64_t(nterms) + 3 * uint64_t(shots);
+    // scratch: fold and Z partials | block totals | marginal | Z values | shot work
+    const uint64_t need = red + nb + nbins + uint64_t(nterms) + kShotWork * uint64_t(shots);
     rc = ensure_scratch(h, need * 8);
     if (rc != SV_OK)
         return rc;
-    // pinned: block totals | marginal | Z values, then the shots' staging
-    rc = ensure_pinned(h, std::max<uint64_t>(nb + nbins + uint64_t(nterms), 2 * uint64_t(shots)) * 8);
+    // pinned: the uniforms going up; then marginal | Z values | shots coming back
+    const uint64_t nres = nbins + uint64_t(nterms);
+    rc = ensure_pinned(h, (nres + uint64_t(shots)) * 8);
     if (rc != SV_OK)
         return rc;
     double *d_tot = h->d_scratch + red;
@@ -1741,18 +1726,23 @@ int sv_readout(sv_handle h, const int *qubits, int m, double *probs, const char 
         set_error("read-out launch failed: %s", hipGetErrorString(e));
         return SV_EDEVICE;
     }
-    HIP_TRY(hipMemcpyAsync(h->h_pinned, d_tot, (nb + nbins + uint64_t(nterms)) * 8, hipMemcpyDeviceToHost,
-                           h->stream));
+    int64_t *d_out = nullptr;
+    if (shots > 0 && (rc = queue_samples(h, d_tot, nb, lbs, uniforms, shots, d_work, &d_out)) != SV_OK)
+        return rc;
+    // one copy back and one wait for all three results
+    char *hp = static_cast<char *>(h->h_pinned);
+    if (nres > 0)
+        HIP_TRY(hipMemcpyAsync(hp, d_marg, nres * 8, hipMemcpyDeviceToHost, h->stream));
+    if (shots > 0)
+        HIP_TRY(hipMemcpyAsync(hp + nres * 8, d_out, uint64_t(shots) * 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    const double *hp = static_cast<const double *>(h->h_pinned);
     if (want_p)
-        memcpy(probs, hp + nb, nbins * 8);
+        memcpy(probs, hp, nbins * 8);
     if (nterms > 0)
-        memcpy(expect, hp + nb + nbins, uint64_t(nterms) * 8);
-    if (shots == 0)
-        return SV_OK;
-    std::vector<double> tot(hp, hp + nb);
-    return sample_from_blocks(h, tot.data(), nb, lbs, uniforms, shots, d_work, samples);
+        memcpy(expect, hp + nbins * 8, uint64_t(nterms) * 8);
+    if (shots > 0)
+        map_samples(h, reinterpret_cast<const int64_t *>(hp + nres * 8), shots, samples);
+    return SV_OK;
 }
 
 // Uniform s of the shot stream of `seed`: the s-th output of SplitMix64

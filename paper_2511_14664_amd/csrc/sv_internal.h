@@ -253,6 +253,10 @@ hipError_t launch_expect_xy(const void *st, int n, int dtype, uint64_t xmask, ui
                             double *d_scratch, double *d_out2, hipStream_t s);
 int sample_log_block(int n);
 hipError_t launch_block_sums(const void *st, int n, int dtype, double *d_bsums, hipStream_t s);
+// Each shot's block and residual target from nb (a power of two) block totals
+// and the shots' uniforms, all on the device (one workgroup).
+hipError_t launch_sample_prep(const double *d_bsums, uint64_t nb, const double *d_uniforms, int shots,
+                              int64_t *d_blocks, double *d_targets, hipStream_t s);
 // Per-shot search inside 2^lbs-amplitude blocks (lbs <= 20).
 hipError_t launch_sample_search(const void *st, int n, int dtype, const int64_t *d_blocks,
                                 const double *d_targets, int shots, int64_t *d_out, int lbs, hipStream_t s);

@@ -370,6 +370,86 @@ __global__ __launch_bounds__(kThreads) void k_block_sums(const R *__restrict__ s
         bs[blockIdx.x] = acc;
 }
 
+// Stage 1b (one workgroup): each shot's block and residual target from the
+// block totals, on the device.  Thread c sums the totals of chunk c (nb / 1024
+// consecutive blocks, or one block when nb < 1024) in order; one thread
+// forms the chunks' running sums in order.  Shot s targets t = u_s * norm and
+// takes the first block whose running sum (chunk start + in-chunk partial
+// sum, added in the same order as the chunk total) exceeds t, with residual
+// t minus the running sum before that block.  Running sums are sums of
+// nonnegative terms in one fixed order, so they never decrease and the
+// chunk search and the in-chunk walk agree.  A target at or past the total
+// takes the last block of nonzero total with that total as residual.
+constexpr int kPrepThreads = 1024;
+
+__global__ __launch_bounds__(kPrepThreads) void k_sample_prep(const double *__restrict__ bs, uint64_t nb,
+                                                              const double *__restrict__ uni, int shots,
+                                                              int64_t *__restrict__ blk, double *__restrict__ tgt)
+{
+    __shared__ double csum[kPrepThreads];
+    __shared__ double cpre[kPrepThreads + 1];
+    __shared__ int64_t cnz[kPrepThreads];
+    __shared__ int64_t s_last;
+    const int tid = threadIdx.x;
+    const uint64_t nchunk = nb < uint64_t(kPrepThreads) ? nb : uint64_t(kPrepThreads);
+    const uint64_t cl = nb / nchunk;  // nb is a power of two
+    if (uint64_t(tid) < nchunk) {
+        double acc = 0.0;
+        int64_t nz = -1;
+        for (uint64_t b = uint64_t(tid) * cl; b < uint64_t(tid + 1) * cl; ++b) {
+            const double x = bs[b];
+            acc += x;
+            if (x > 0.0)
+                nz = int64_t(b);
+        }
+        csum[tid] = acc;
+        cnz[tid] = nz;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double run = 0.0;
+        int64_t last = 0;
+        for (uint64_t c = 0; c < nchunk; ++c) {
+            cpre[c] = run;
+            run += csum[c];
+            if (cnz[c] >= 0)
+                last = cnz[c];
+        }
+        cpre[nchunk] = run;
+        s_last = last;
+    }
+    __syncthreads();
+    const double norm = cpre[nchunk];
+    for (int sh = tid; sh < shots; sh += kPrepThreads) {
+        const double t = uni[sh] * norm;
+        uint64_t lo = 0, hi = nchunk;  // first chunk c with cpre[c + 1] > t
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (cpre[mid + 1] > t)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        int64_t b_out = s_last;
+        double t_out = bs[s_last];
+        if (lo < nchunk) {
+            const double start = cpre[lo];
+            double part = 0.0;
+            for (uint64_t b = lo * cl; b < (lo + 1) * cl; ++b) {
+                const double before = part;
+                part += bs[b];
+                if (start + part > t) {
+                    b_out = int64_t(b);
+                    t_out = t - (start + before);
+                    break;
+                }
+            }
+        }
+        blk[sh] = b_out;
+        tgt[sh] = t_out;
+    }
+}
+
 // Stage 2: one workgroup per shot walks its block in segments of 1024
 // amplitudes (4 consecutive per thread) and returns the first index whose
 // in-block running sum exceeds the residual target.  If rounding leaves none,
@@ -1124,6 +1204,18 @@ hipError_t launch_block_sums(const void *st, int n, int dtype, double *d_bsums, 
         hipLaunchKernelGGL(k_block_sums<float>, dim3(uint32_t(nb)), dim3(kThreads), 0, s, (const float *)st, d_bsums, lbs);
     else
         hipLaunchKernelGGL(k_block_sums<double>, dim3(uint32_t(nb)), dim3(kThreads), 0, s, (const double *)st, d_bsums, lbs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_prep(const double *d_bsums, uint64_t nb, const double *d_uniforms, int shots,
+                              int64_t *d_blocks, double *d_targets, hipStream_t s)
+{
+    if (shots <= 0)
+        return hipSuccess;
+    if (nb == 0 || (nb & (nb - 1)) != 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample_prep, dim3(1), dim3(kPrepThreads), 0, s, d_bsums, nb, d_uniforms, shots, d_blocks,
+                       d_targets);
     return hipGetLastError();
 }
 
