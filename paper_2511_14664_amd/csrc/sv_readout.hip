@@ -680,6 +680,18 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
     for (int t = 0; t < (NZ > 0 ? NZ : 1); ++t)
         zacc[t] = 0.0;
     double tsum = 0.0;
+    // complex64: the next segment's loads are issued before the current
+    // segment's arithmetic (a vector value: registers, not private memory)
+    typedef float f32xL __attribute__((ext_vector_type(F32 ? 4 * NLD : 4)));
+    f32xL qn;
+    if constexpr (F32) {
+        const float4 *v4 = reinterpret_cast<const float4 *>(st) + ((uint64_t(blockIdx.x) << (a.F + kSegLog)) >> 1);
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const float4 q = ldnt(&v4[tid + k * kThreads]);
+            qn[4 * k] = q.x, qn[4 * k + 1] = q.y, qn[4 * k + 2] = q.z, qn[4 * k + 3] = q.w;
+        }
+    }
     for (uint32_t j = 0; j < (1u << a.F); ++j) {
         const uint64_t base = ((uint64_t(blockIdx.x) << a.F) | j) << kSegLog;
         // the thread's 16 probabilities, by the index bits its loads differ in
@@ -688,11 +700,19 @@ __global__ __launch_bounds__(kThreads) void k_marg_fold(const R *__restrict__ st
         // (uniform) index indexes registers rather than private memory
         f64x16 w;
         if constexpr (F32) {
-            const float4 *v4 = reinterpret_cast<const float4 *>(st) + (base >> 1);
+            const f32xL qc = qn;
+            if (j + 1 < (1u << a.F)) {
+                const float4 *v4 = reinterpret_cast<const float4 *>(st) + ((base + SEG) >> 1);
+#pragma unroll
+                for (int k = 0; k < NLD; ++k) {
+                    const float4 q = ldnt(&v4[tid + k * kThreads]);
+                    qn[4 * k] = q.x, qn[4 * k + 1] = q.y, qn[4 * k + 2] = q.z, qn[4 * k + 3] = q.w;
+                }
+            }
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) {
-                const float4 q = ldnt(&v4[tid + k * kThreads]);
+                const float4 q = make_float4(qc[4 * k], qc[4 * k + 1], qc[4 * k + 2], qc[4 * k + 3]);
                 const double p0 = double(q.x) * q.x + double(q.y) * q.y;
                 const double p1 = double(q.z) * q.z + double(q.w) * q.w;
                 if constexpr (KSUM) {
