@@ -127,8 +127,7 @@ __device__ __forceinline__ uint64_t index_off(int k, const UnitMap &m)
 // itself; kScalar, one i0.  Controls on index bits inside one 128-byte line
 // stay out of the unit map: every amplitude of the line is read and written,
 // those whose in-line controls are not all set unchanged, so the stores cover
-// whole lines (sweeps that left parts of their lines unwritten ran 15-25 %
-// slower on a 28-qubit state).
+// whole lines instead of leaving the HBM partial-line writes.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Gate1Args {
