@@ -97,12 +97,9 @@ template <typename R>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
 {
     using C = typename CT<R>::C;
-    // tile amplitudes per thread in flight between global memory and LDS, and
-    // gate groups per thread per LDS sweep iteration (fewer for complex128,
-    // whose matrix and groups take twice the registers)
+    // tile amplitudes per thread in flight between global memory and LDS
     constexpr uint32_t kU = 8;
     typedef R VU __attribute__((ext_vector_type(2 * kU)));
-    constexpr int kG = std::is_same<R, float>::value ? 4 : 2;
     extern __shared__ __align__(16) unsigned char smem[];
     C *tile = reinterpret_cast<C *>(smem);
     unsigned char *tileb = smem;
@@ -251,9 +248,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
                 sp = a.steps[ps.step0 + si];
             const C *M = kLds ? mcache + (sp.mat - ps.mat0) : mats + sp.mat;
             const int ta = sp.a, tb = sp.b;
-            // Each sweep takes kG groups per thread per iteration, all LDS
-            // reads before the first write (the groups are disjoint), while
-            // at least kG * kBatchThreads groups remain; then one at a time.
+            // Each sweep takes one group per thread per iteration (two or four
+            // groups with all their LDS reads ahead were slower).
             if (sp.type <= 1) {
                 const C m00 = M[0], m01 = M[1], m10 = M[2], m11 = M[3];
                 const int lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
@@ -264,23 +260,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
                 auto first = [&](uint32_t j) __attribute__((always_inline)) {
                     return swz((ctl ? ins2(j, lo, hi) : ins1(j, ta)) | cbit) * uint32_t(sizeof(C));
                 };
-                uint32_t j = tid;
-                for (; j + (kG - 1) * kBatchThreads < cnt; j += kG * kBatchThreads) {
-                    uint32_t o[kG];
-                    C v0[kG], v1[kG];
-#pragma unroll
-                    for (int g = 0; g < kG; ++g) {
-                        o[g] = first(j + g * kBatchThreads);
-                        v0[g] = lds_at<C>(tileb, o[g]);
-                        v1[g] = lds_at<C>(tileb, o[g] ^ pt);
-                    }
-#pragma unroll
-                    for (int g = 0; g < kG; ++g) {
-                        lds_at<C>(tileb, o[g]) = cfma(m01, v1[g], cmul(m00, v0[g]));
-                        lds_at<C>(tileb, o[g] ^ pt) = cfma(m11, v1[g], cmul(m10, v0[g]));
-                    }
-                }
-                for (; j < cnt; j += kBatchThreads) {
+                for (uint32_t j = tid; j < cnt; j += kBatchThreads) {
                     const uint32_t o = first(j);
                     const C v0 = lds_at<C>(tileb, o), v1 = lds_at<C>(tileb, o ^ pt);
                     lds_at<C>(tileb, o) = cfma(m01, v1, cmul(m00, v0));
@@ -299,7 +279,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     px[e] = swz(((e & 1) ? 1u << ta : 0u) | ((e & 2) ? 1u << tb : 0u)) * uint32_t(sizeof(C));
-                auto group = [&](const C *v, uint32_t o) __attribute__((always_inline)) {
+                for (uint32_t j = tid; j < cnt; j += kBatchThreads) {
+                    const uint32_t o = swz(ins2(j, lo, hi)) * uint32_t(sizeof(C));
+                    C v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        v[e] = lds_at<C>(tileb, o ^ px[e]);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         C acc = cmul(m[r * 4], v[0]);
@@ -308,29 +293,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs a)
                             acc = cfma(m[r * 4 + c], v[c], acc);
                         lds_at<C>(tileb, o ^ px[r]) = acc;
                     }
-                };
-                uint32_t j = tid;
-                for (; j + (kG - 1) * kBatchThreads < cnt; j += kG * kBatchThreads) {
-                    uint32_t o[kG];
-                    C v[kG][4];
-#pragma unroll
-                    for (int g = 0; g < kG; ++g) {
-                        o[g] = swz(ins2(j + g * kBatchThreads, lo, hi)) * uint32_t(sizeof(C));
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            v[g][e] = lds_at<C>(tileb, o[g] ^ px[e]);
-                    }
-#pragma unroll
-                    for (int g = 0; g < kG; ++g)
-                        group(v[g], o[g]);
-                }
-                for (; j < cnt; j += kBatchThreads) {
-                    const uint32_t o = swz(ins2(j, lo, hi)) * uint32_t(sizeof(C));
-                    C v[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        v[e] = lds_at<C>(tileb, o ^ px[e]);
-                    group(v, o);
                 }
             }
             __syncthreads();
